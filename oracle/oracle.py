@@ -1,0 +1,287 @@
+"""Python binding of the CPU oracle (liboracle.so, built by oracle/build.sh).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is a plain, slow FP64 implementation of
+the method written from the paper; the only callers are tests/, the smoke
+check and the CPU-baseline leg of the benchmark.  It shares no code with the
+GPU library and imports nothing from it.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+SCENE_KIND = {"push": 1, "pickplace": 2, "movepush": 3}
+MAX_STATIC = 8
+
+_d = ctypes.c_double
+_i = ctypes.c_int32
+
+
+class RefScene(ctypes.Structure):
+    _fields_ = [
+        ("kind", _i), ("substeps", _i), ("horizon", _i),
+        ("dt", _d), ("gravity", _d), ("k_contact", _d), ("c_contact", _d), ("eps_v", _d),
+        ("mu_ground", _d), ("mu_tool", _d), ("mu_static", _d), ("mu_ramp", _d),
+        ("obj_half", _d * 3), ("obj_mass", _d), ("obj_pos0", _d * 3), ("obj_yaw0", _d),
+        ("n_static", _i),
+        ("st_center", (_d * 3) * MAX_STATIC), ("st_half", (_d * 3) * MAX_STATIC),
+        ("st_yaw", _d * MAX_STATIC), ("st_pitch", _d * MAX_STATIC), ("st_ramp", _i * MAX_STATIC),
+        ("pusher_radius", _d), ("pusher_standoff", _d), ("pusher_height", _d), ("pusher_vmax", _d),
+        ("pusher_steps", _i),
+        ("goal_rho_lo", _d), ("goal_rho_hi", _d), ("goal_phi_lo", _d), ("goal_phi_hi", _d),
+        ("goal_tol", _d), ("time_weight", _d),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("oracle not built: run oracle/build.sh")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        u64, u32 = ctypes.c_uint64, ctypes.c_uint32
+        L.ref_scene_size.restype = ctypes.c_int
+        L.ref_philox.argtypes = [u64, u32, u32, u32, u32, u32, vp]
+        L.ref_philox_raw.argtypes = [vp, vp, vp]
+        L.ref_u01.argtypes = [vp, ctypes.c_int, vp]
+        L.ref_logf_vec.argtypes = [vp, ctypes.c_int, vp]
+        L.ref_sincos2pi_vec.argtypes = [vp, ctypes.c_int, vp, vp]
+        L.ref_normals.argtypes = [u64, u32, u32, ctypes.c_int, ctypes.c_int, vp]
+        L.ref_sample.argtypes = [u64, u32, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.ref_draw_instance.argtypes = [P(RefScene), u64, u32, vp]
+        L.ref_rollout.argtypes = [P(RefScene), u64, u32, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int,
+                                  ctypes.c_int]
+        L.ref_count_ops.argtypes = [P(RefScene), u64, u32, vp, vp]
+        L.ref_select.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp]
+        L.ref_cholesky.argtypes = [ctypes.c_int, vp, vp]
+        L.ref_factor_cov.argtypes = [ctypes.c_int, vp, vp]
+        L.ref_refit.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int32, vp, vp, vp, vp]
+        L.ref_plan_solve.argtypes = [P(RefScene), u64, u32, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.ref_box_sim.argtypes = [vp, ctypes.c_int, vp]
+        L.ref_sphere_box.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
+        L.ref_box_box.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        if L.ref_scene_size() != ctypes.sizeof(RefScene):
+            raise RuntimeError("oracle RefScene layout mismatch")
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def param_dim(workload):
+    return {"push": 3, "pickplace": 16, "movepush": 12}[workload["scene"]["kind"]]
+
+
+def make_scene(workload):
+    """Fill the oracle's scene record from a workload dict."""
+    sc = workload["scene"]
+    s = RefScene()
+    s.kind = SCENE_KIND[sc["kind"]]
+    s.substeps, s.horizon = sc["substeps"], sc["horizon"]
+    s.dt, s.gravity = sc["dt"], sc["gravity"]
+    s.k_contact, s.c_contact, s.eps_v = sc["k_contact"], sc["c_contact"], sc["eps_v"]
+    s.mu_ground, s.mu_tool, s.mu_static, s.mu_ramp = sc["mu_ground"], sc["mu_tool"], sc["mu_static"], sc["mu_ramp"]
+    ob = sc["object"]
+    for i in range(3):
+        s.obj_half[i] = ob["half"][i]
+        s.obj_pos0[i] = ob["pos0"][i]
+    s.obj_mass, s.obj_yaw0 = ob["mass"], ob["yaw0"]
+    boxes = sc.get("static_boxes", [])
+    assert len(boxes) <= MAX_STATIC
+    s.n_static = len(boxes)
+    for j, b in enumerate(boxes):
+        for i in range(3):
+            s.st_center[j][i] = b["center"][i]
+            s.st_half[j][i] = b["half"][i]
+        s.st_yaw[j], s.st_pitch[j] = b.get("yaw", 0.0), b.get("pitch", 0.0)
+        s.st_ramp[j] = 1 if b.get("ramp", False) else 0
+    pu = sc.get("pusher")
+    if pu:
+        s.pusher_radius, s.pusher_standoff, s.pusher_height = pu["radius"], pu["standoff"], pu["height"]
+        s.pusher_vmax, s.pusher_steps = pu["vmax"], pu["steps"]
+    go = sc.get("goal")
+    if go:
+        s.goal_rho_lo, s.goal_rho_hi = go["rho"]
+        s.goal_phi_lo, s.goal_phi_hi = go["phi"]
+        s.goal_tol, s.time_weight = go["tol"], go["time_weight"]
+    return s
+
+
+def philox(seed, tag, block, sample, it, inst):
+    out = np.zeros(4, np.uint32)
+    lib().ref_philox(seed, tag, block, sample, it, inst, _ptr(out))
+    return out
+
+
+def philox_raw(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().ref_philox_raw(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def u01(x):
+    x = np.ascontiguousarray(x, np.uint32)
+    out = np.zeros(x.shape, np.float32)
+    lib().ref_u01(_ptr(x), x.size, _ptr(out))
+    return out
+
+
+def logf(u):
+    u = np.ascontiguousarray(u, np.float32)
+    out = np.zeros(u.shape, np.float32)
+    lib().ref_logf_vec(_ptr(u), u.size, _ptr(out))
+    return out
+
+
+def sincos2pi(u):
+    u = np.ascontiguousarray(u, np.float32)
+    s = np.zeros(u.shape, np.float32)
+    c = np.zeros(u.shape, np.float32)
+    lib().ref_sincos2pi_vec(_ptr(u), u.size, _ptr(s), _ptr(c))
+    return s, c
+
+
+def normals(seed, it, inst, pop, D):
+    out = np.zeros((pop, D), np.float32)
+    lib().ref_normals(seed, it, inst, pop, D, _ptr(out))
+    return out
+
+
+def sample(seed, it, inst, pop, mu, L):
+    mu = np.ascontiguousarray(mu, np.float64)
+    L = np.ascontiguousarray(L, np.float64)
+    D = mu.size
+    out = np.zeros((pop, D), np.float32)
+    lib().ref_sample(seed, it, inst, pop, D, _ptr(mu), _ptr(L), _ptr(out))
+    return out
+
+
+def draw_instance(workload, seed, inst=0):
+    s = make_scene(workload)
+    g = np.zeros(2, np.float64)
+    lib().ref_draw_instance(ctypes.byref(s), seed, inst, _ptr(g))
+    return g
+
+
+def rollout(workload, seed, Z, inst=0, trace_steps=0, threads=None):
+    """FP64 rollouts of the rows of Z: returns cost (f64), tier (u8), pose (pop x 7), trace or None."""
+    s = make_scene(workload)
+    Z = np.ascontiguousarray(Z, np.float32)
+    pop = Z.shape[0]
+    cost = np.zeros(pop, np.float64)
+    tier = np.zeros(pop, np.uint8)
+    pose = np.zeros((pop, 7), np.float64)
+    tw = 13
+    trace = np.zeros((pop, trace_steps, tw), np.float64) if trace_steps else None
+    threads = threads or os.cpu_count() or 1
+    rc = lib().ref_rollout(ctypes.byref(s), seed, inst, pop, _ptr(Z), _ptr(cost), _ptr(tier), _ptr(pose),
+                           _ptr(trace) if trace is not None else None, trace_steps, threads)
+    if rc != 0:
+        raise RuntimeError("oracle rollout failed (%d)" % rc)
+    return cost, tier, pose, trace
+
+
+def count_ops(workload, seed, z, inst=0):
+    """Operation tally of one rollout: dict(add, mul, fma, div, sqrt, trans, flops)."""
+    s = make_scene(workload)
+    z = np.ascontiguousarray(z, np.float32)
+    out = np.zeros(6, np.uint64)
+    lib().ref_count_ops(ctypes.byref(s), seed, inst, _ptr(z), _ptr(out))
+    d = dict(zip(["add", "mul", "fma", "div", "sqrt", "trans"], [int(v) for v in out]))
+    d["flops"] = d["add"] + d["mul"] + 2 * d["fma"] + d["div"] + d["sqrt"]
+    return d
+
+
+def select(cost, tier, n_elite):
+    cost = np.ascontiguousarray(cost, np.float32)
+    tier = np.ascontiguousarray(tier, np.uint8)
+    idx = np.zeros(max(n_elite, 1), np.int32)
+    mode = np.zeros(1, np.int32)
+    counts = np.zeros(4, np.int32)
+    ne = lib().ref_select(cost.size, _ptr(cost), _ptr(tier), n_elite, _ptr(idx), _ptr(mode), _ptr(counts))
+    return idx[:ne].copy(), int(mode[0]), counts
+
+
+def cholesky(A):
+    A = np.ascontiguousarray(A, np.float64)
+    L = np.zeros_like(A)
+    rc = lib().ref_cholesky(A.shape[0], _ptr(A), _ptr(L))
+    return L, rc
+
+
+def factor_cov(S):
+    S = np.ascontiguousarray(S, np.float64)
+    L = np.zeros_like(S)
+    rc = lib().ref_factor_cov(S.shape[0], _ptr(S), _ptr(L))
+    return L, rc
+
+
+def refit(Z, elite, mode, cov_mode, cov0, mu, S):
+    Z = np.ascontiguousarray(Z, np.float32)
+    D = Z.shape[1]
+    elite = np.ascontiguousarray(elite, np.int32)
+    cov0 = np.ascontiguousarray(cov0, np.float64)
+    mu = np.array(mu, np.float64)
+    S = np.array(S, np.float64)
+    L = np.zeros((D, D), np.float64)
+    rc = lib().ref_refit(D, cov_mode, _ptr(Z), _ptr(elite), elite.size, mode, _ptr(cov0), _ptr(mu), _ptr(S),
+                         _ptr(L))
+    return mu, S, L, rc
+
+
+def plan_solve(workload, seed, inst=0, threads=None, iters=None, pop=None):
+    cem = workload["cem"]
+    D = param_dim(workload)
+    pop = pop or cem["pop"]
+    iters = iters if iters is not None else cem["iters"]
+    cov_mode = 0 if cem["cov_mode"] == "diag" else 1
+    mu0 = np.asarray(cem["mu0"], np.float64)
+    cov0 = np.diag(np.asarray(cem["cov0_diag"], np.float64))
+    s = make_scene(workload)
+    best_z = np.zeros(D, np.float32)
+    best_cost = np.zeros(1, np.float64)
+    best_tier = np.zeros(1, np.int32)
+    mu = np.zeros(D, np.float64)
+    S = np.zeros((D, D), np.float64)
+    stats = np.zeros((iters, 8), np.float64)
+    threads = threads or os.cpu_count() or 1
+    lib().ref_plan_solve(ctypes.byref(s), seed, inst, pop, cem["n_elite"], iters, cov_mode, _ptr(mu0), _ptr(cov0),
+                         threads, _ptr(best_z), _ptr(best_cost), _ptr(best_tier), _ptr(mu), _ptr(S), _ptr(stats))
+    return dict(best_z=best_z, best_cost=float(best_cost[0]), best_tier=int(best_tier[0]), mu=mu, S=S, stats=stats)
+
+
+def box_sim(he, m, p0, q0, v0, w0, gvec, k, c, mu, eps_v, h, plane, nsteps):
+    """Single free box (optionally on the plane z = 0): nsteps x 13 trace of p q v w."""
+    prm = np.array(list(he) + [m] + list(p0) + list(q0) + list(v0) + list(w0) + list(gvec)
+                   + [k, c, mu, eps_v, h, 1.0 if plane else 0.0, 0.0], np.float64)
+    out = np.zeros((nsteps, 13), np.float64)
+    lib().ref_box_sim(_ptr(prm), nsteps, _ptr(out))
+    return out
+
+
+def sphere_box(c, r, p, q, he):
+    a = [np.ascontiguousarray(v, np.float64) for v in (c, p, q, he)]
+    out = np.zeros(7, np.float64)
+    n = lib().ref_sphere_box(_ptr(a[0]), ctypes.c_double(r), _ptr(a[1]), _ptr(a[2]), _ptr(a[3]), _ptr(out))
+    return out if n else None
+
+
+def box_box(pA, qA, heA, pB, qB, heB):
+    """Contacts of A's vertices inside B: rows x[3] n[3] d (n from B into A)."""
+    a = [np.ascontiguousarray(v, np.float64) for v in (pA, qA, heA, pB, qB, heB)]
+    out = np.zeros((8, 7), np.float64)
+    n = lib().ref_box_box(*[_ptr(v) for v in a], _ptr(out))
+    return out[:n].copy()

@@ -1,0 +1,271 @@
+// Oracle C entry points (ref_*), host pointers only.
+// TEST INFRASTRUCTURE ONLY: the only callers are tests/, the smoke check and
+// the CPU-baseline leg of the benchmark.  Nothing here is shared with, or
+// called by, the GPU library.
+//
+// Built with g++ -O2 -ffp-contract=off so that no multiply-add is fused behind
+// the code's back: every rounding step is the one written.
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <thread>
+#include <vector>
+
+#include "ref_cem.hpp"
+#include "ref_push.hpp"
+#include "ref_random.hpp"
+#include "ref_scene.hpp"
+
+namespace ref {
+thread_local Tally g_tally;
+}
+
+using namespace ref;
+
+namespace {
+
+RolloutOut rollout_one(const RefScene &s, const Instance &in, const float *z, double *trace, int trace_steps) {
+  return push_rollout<double>(s, in, z, trace, trace_steps);
+}
+
+int param_dim(const RefScene &s) {
+  if (s.kind == SCENE_PUSH) return 3;
+  if (s.kind == SCENE_PICKPLACE) return 16;
+  return 12;
+}
+
+void parallel_for(int n, int threads, const std::function<void(int)> &fn) {
+  if (threads <= 1 || n <= 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> ts;
+  for (int t = 0; t < threads; ++t)
+    ts.emplace_back([&]() {
+      for (;;) {
+        const int i = next.fetch_add(1);
+        if (i >= n) break;
+        fn(i);
+      }
+    });
+  for (auto &t : ts) t.join();
+}
+
+}  // namespace
+
+extern "C" {
+
+int ref_scene_size(void) { return (int)sizeof(RefScene); }
+
+void ref_philox(uint64_t seed, uint32_t tag, uint32_t block, uint32_t sample, uint32_t iter, uint32_t inst,
+                uint32_t out[4]) {
+  Word4 x = philox_draw(seed, tag, block, sample, iter, inst);
+  for (int i = 0; i < 4; ++i) out[i] = x.w[i];
+}
+
+void ref_philox_raw(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  Word4 c;
+  for (int i = 0; i < 4; ++i) c.w[i] = ctr[i];
+  Word4 x = philox4x32_10(c, key[0], key[1]);
+  for (int i = 0; i < 4; ++i) out[i] = x.w[i];
+}
+
+void ref_u01(const uint32_t *x, int n, float *out) {
+  for (int i = 0; i < n; ++i) out[i] = u01(x[i]);
+}
+void ref_logf_vec(const float *u, int n, float *out) {
+  for (int i = 0; i < n; ++i) out[i] = ref_logf(u[i]);
+}
+void ref_sincos2pi_vec(const float *u, int n, float *s, float *c) {
+  for (int i = 0; i < n; ++i) ref_sincos2pi(u[i], &s[i], &c[i]);
+}
+
+// eps[i][d] for samples 0..pop-1 of iteration iter, instance inst.
+void ref_normals(uint64_t seed, uint32_t iter, uint32_t inst, int pop, int D, float *eps) {
+  for (int i = 0; i < pop; ++i)
+    for (int d = 0; d < D; ++d) eps[(long)i * D + d] = cem_normal(seed, d, (uint32_t)i, iter, inst);
+}
+
+// Z (pop x D, FP32) = mu + L eps for iteration iter, instance inst.
+void ref_sample(uint64_t seed, uint32_t iter, uint32_t inst, int pop, int D, const double *mu, const double *L,
+                float *Z) {
+  for (int i = 0; i < pop; ++i) cem_sample_row(seed, (uint32_t)i, iter, inst, D, mu, L, Z + (long)i * D, nullptr);
+}
+
+void ref_draw_instance(const RefScene *s, uint64_t seed, uint32_t inst, double goal[2]) {
+  Instance in = draw_instance(*s, seed, inst);
+  goal[0] = in.goal[0];
+  goal[1] = in.goal[1];
+}
+
+// Roll out pop parameter rows; trace (optional) gets trace_steps states per env.
+int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const float *Z, double *cost,
+                uint8_t *tier, double *pose, double *trace, int trace_steps, int threads) {
+  const int D = param_dim(*s);
+  const Instance in = draw_instance(*s, seed, inst);
+  if (s->kind != SCENE_PUSH) return 1;
+  const int tw = TRACE_FREE;
+  parallel_for(pop, threads, [&](int i) {
+    RolloutOut o = rollout_one(*s, in, Z + (long)i * D, trace ? trace + (long)i * trace_steps * tw : nullptr,
+                               trace_steps);
+    cost[i] = o.cost;
+    tier[i] = (uint8_t)o.tier;
+    if (pose)
+      for (int c = 0; c < 7; ++c) pose[(long)i * 7 + c] = o.pose[c];
+  });
+  return 0;
+}
+
+// Operation tally of one rollout of parameter row z: add, mul, fma, div, sqrt, trans.
+void ref_count_ops(const RefScene *s, uint64_t seed, uint32_t inst, const float *z, uint64_t out[6]) {
+  const Instance in = draw_instance(*s, seed, inst);
+  g_tally = Tally();
+  push_rollout<Cnt>(*s, in, z, nullptr, 0);
+  out[0] = g_tally.add; out[1] = g_tally.mul; out[2] = g_tally.fma;
+  out[3] = g_tally.div; out[4] = g_tally.sqrt; out[5] = g_tally.trans;
+}
+
+// A single free box, optionally resting on the plane z = 0 (8 corner contacts),
+// under an arbitrary gravity vector: the closed-form pins of the integrator and
+// of the contact model run through this.  prm layout:
+// he[3] m p0[3] q0[4] v0[3] w0[3] gvec[3] k c mu eps_v h plane(0/1)  (27 doubles).
+// trace: nsteps x 13 (p q v w after each step).
+void ref_box_sim(const double *prm, int nsteps, double *trace) {
+  const V3<double> he(prm[0], prm[1], prm[2]);
+  const double m = prm[3];
+  Body<double> b;
+  b.p = V3<double>(prm[4], prm[5], prm[6]);
+  b.q.w = prm[7]; b.q.x = prm[8]; b.q.y = prm[9]; b.q.z = prm[10];
+  b.v = V3<double>(prm[11], prm[12], prm[13]);
+  b.w = V3<double>(prm[14], prm[15], prm[16]);
+  const V3<double> gv(prm[17], prm[18], prm[19]);
+  const double k = prm[20], c = prm[21], mu = prm[22], eps_v = prm[23], h = prm[24];
+  const bool plane = prm[25] != 0.0;
+  const V3<double> Ib(m * (he.y * he.y + he.z * he.z) / 3.0, m * (he.x * he.x + he.z * he.z) / 3.0,
+                      m * (he.x * he.x + he.y * he.y) / 3.0);
+  for (int n = 0; n < nsteps; ++n) {
+    Wrench<double> W;
+    if (plane) {
+      Contact<double> cs[8];
+      const int nc = box_plane(b.p, quat_to_mat(b.q), he, cs);
+      for (int i = 0; i < nc; ++i) {
+        const V3<double> vA = b.v + cross(b.w, cs[i].x - b.p);
+        add_force(W, b.p, cs[i].x, penalty_force(cs[i], vA, V3<double>(), k, c, mu, eps_v));
+      }
+    }
+    integrate_free(b, W, m, Ib, gv, h);
+    double *o = trace + (long)n * 13;
+    o[0] = b.p.x; o[1] = b.p.y; o[2] = b.p.z;
+    o[3] = b.q.w; o[4] = b.q.x; o[5] = b.q.y; o[6] = b.q.z;
+    o[7] = b.v.x; o[8] = b.v.y; o[9] = b.v.z;
+    o[10] = b.w.x; o[11] = b.w.y; o[12] = b.w.z;
+  }
+}
+
+// Narrowphase probes.  Poses are (p[3], q[4]).  Each contact row: x[3] n[3] d.
+int ref_sphere_box(const double c[3], double r, const double p[3], const double q[4], const double he[3],
+                   double out[7]) {
+  Q4<double> qq; qq.w = q[0]; qq.x = q[1]; qq.y = q[2]; qq.z = q[3];
+  Contact<double> ct;
+  const int n = sphere_box(V3<double>(c[0], c[1], c[2]), r, V3<double>(p[0], p[1], p[2]), quat_to_mat(qq),
+                           V3<double>(he[0], he[1], he[2]), &ct);
+  if (n) {
+    out[0] = ct.x.x; out[1] = ct.x.y; out[2] = ct.x.z;
+    out[3] = ct.n.x; out[4] = ct.n.y; out[5] = ct.n.z; out[6] = ct.d;
+  }
+  return n;
+}
+
+int ref_box_box(const double pA[3], const double qA[4], const double heA[3], const double pB[3], const double qB[4],
+                const double heB[3], double out[8 * 7]) {
+  Q4<double> a; a.w = qA[0]; a.x = qA[1]; a.y = qA[2]; a.z = qA[3];
+  Q4<double> b; b.w = qB[0]; b.x = qB[1]; b.y = qB[2]; b.z = qB[3];
+  Contact<double> cs[8];
+  const int n = box_verts_in_box(V3<double>(pA[0], pA[1], pA[2]), quat_to_mat(a), V3<double>(heA[0], heA[1], heA[2]),
+                                 V3<double>(pB[0], pB[1], pB[2]), quat_to_mat(b), V3<double>(heB[0], heB[1], heB[2]),
+                                 cs);
+  for (int i = 0; i < n; ++i) {
+    double *o = out + i * 7;
+    o[0] = cs[i].x.x; o[1] = cs[i].x.y; o[2] = cs[i].x.z;
+    o[3] = cs[i].n.x; o[4] = cs[i].n.y; o[5] = cs[i].n.z; o[6] = cs[i].d;
+  }
+  return n;
+}
+
+int ref_select(int pop, const float *cost, const uint8_t *tier, int n_elite, int32_t *elite_idx, int32_t *mode,
+               int32_t tier_counts[4]) {
+  return select_elites(pop, cost, tier, n_elite, elite_idx, mode, tier_counts);
+}
+
+int ref_cholesky(int D, const double *A, double *L) { return cholesky(D, A, L) ? 0 : 1; }
+int ref_factor_cov(int D, const double *S, double *L) { return factor_cov(D, S, L); }
+
+int ref_refit(int D, int cov_mode, const float *Z, const int32_t *elite, int ne, int32_t mode, const double *cov0,
+              double *mu, double *S, double *L) {
+  return refit(D, cov_mode, Z, elite, ne, mode, cov0, mu, S, L);
+}
+
+// Alg. 1 end to end: `iters` CE iterations of sample -> rollout -> select ->
+// refit on one instance.  Outputs: best-ever row and its cost/tier, final
+// theta (mu, S), and per-iteration stats rows of 8 doubles:
+// [best cost this iteration, n_tier0, n_tier1, n_tier2, n_tier3, n_elite, mode, best-ever cost].
+int ref_plan_solve(const RefScene *s, uint64_t seed, uint32_t inst, int pop, int n_elite, int iters, int cov_mode,
+                   const double *mu0, const double *cov0, int threads, float *best_z, double *best_cost,
+                   int32_t *best_tier, double *mu_out, double *S_out, double *stats) {
+  const int D = param_dim(*s);
+  std::vector<double> mu(mu0, mu0 + D), S(cov0, cov0 + D * D), L(D * D);
+  if (cov_mode == 0)
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b)
+        if (a != b) S[a * D + b] = 0.0;
+  factor_cov(D, S.data(), L.data());
+  std::vector<float> Z((long)pop * D), costf(pop);
+  std::vector<double> cost(pop);
+  std::vector<uint8_t> tier(pop);
+  std::vector<int32_t> elite(n_elite);
+  int32_t bt = 4;
+  double bc = INFINITY;
+  for (int j = 0; j < iters; ++j) {
+    ref_sample(seed, (uint32_t)j, inst, pop, D, mu.data(), L.data(), Z.data());
+    ref_rollout(s, seed, inst, pop, Z.data(), cost.data(), tier.data(), nullptr, nullptr, 0, threads);
+    for (int i = 0; i < pop; ++i) costf[i] = (float)cost[i];
+    int32_t mode, counts[4];
+    const int ne = select_elites(pop, costf.data(), tier.data(), n_elite, elite.data(), &mode, counts);
+    // best of this iteration = first key in sorted order
+    int bi = -1;
+    for (int i = 0; i < pop; ++i) {
+      const int ti = std::isnan(cost[i]) ? 3 : tier[i];
+      const double ci = std::isnan(cost[i]) ? INFINITY : cost[i];
+      if (bi < 0) { bi = i; continue; }
+      const int tb = std::isnan(cost[bi]) ? 3 : tier[bi];
+      const double cb = std::isnan(cost[bi]) ? INFINITY : cost[bi];
+      if (ti < tb || (ti == tb && ci < cb)) bi = i;
+    }
+    if (bi >= 0) {
+      const int ti = std::isnan(cost[bi]) ? 3 : tier[bi];
+      if (ti < bt || (ti == bt && cost[bi] < bc)) {
+        bt = ti;
+        bc = cost[bi];
+        for (int d = 0; d < D; ++d) best_z[d] = Z[(long)bi * D + d];
+      }
+    }
+    if (stats) {
+      double *st = stats + (long)j * 8;
+      st[0] = bi >= 0 ? cost[bi] : INFINITY;
+      for (int t = 0; t < 4; ++t) st[1 + t] = counts[t];
+      st[5] = ne;
+      st[6] = mode;
+      st[7] = bc;
+    }
+    refit(D, cov_mode, Z.data(), elite.data(), ne, mode, cov0, mu.data(), S.data(), L.data());
+  }
+  *best_cost = bc;
+  *best_tier = bt;
+  for (int d = 0; d < D; ++d) mu_out[d] = mu[d];
+  for (int i = 0; i < D * D; ++i) S_out[i] = S[i];
+  return 0;
+}
+
+}  // extern "C"

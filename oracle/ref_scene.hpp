@@ -1,0 +1,55 @@
+// Oracle: scene description and the seeded per-instance draws.
+// TEST INFRASTRUCTURE ONLY (see ref_scalar.hpp).
+#pragma once
+#include <cstdint>
+
+#include "ref_random.hpp"
+
+namespace ref {
+
+constexpr int SCENE_PUSH = 1;
+constexpr int SCENE_PICKPLACE = 2;
+constexpr int SCENE_MOVEPUSH = 3;
+constexpr int MAX_STATIC = 8;
+
+// Everything a rollout needs, in FP64.  Filled by the oracle's Python binding
+// from the same workload description the GPU library receives.
+struct RefScene {
+  int32_t kind;
+  int32_t substeps, horizon;
+  double dt, gravity, k_contact, c_contact, eps_v;
+  // friction coefficients: ground, pusher/finger, static boxes, ramp
+  double mu_ground, mu_tool, mu_static, mu_ramp;
+  // the one free object: a box
+  double obj_half[3], obj_mass, obj_pos0[3], obj_yaw0;
+  // static boxes: centre, half extents, yaw (about z) then pitch (about y), friction class
+  int32_t n_static;
+  double st_center[MAX_STATIC][3], st_half[MAX_STATIC][3], st_yaw[MAX_STATIC], st_pitch[MAX_STATIC];
+  int32_t st_ramp[MAX_STATIC];
+  // kinematic pusher sphere (push scene)
+  double pusher_radius, pusher_standoff, pusher_height, pusher_vmax;
+  int32_t pusher_steps;
+  // goal: drawn per instance on the scene stream; tolerance and time weight of the cost
+  double goal_rho_lo, goal_rho_hi, goal_phi_lo, goal_phi_hi, goal_tol, time_weight;
+};
+
+// Per-instance draws (scene stream 1, sample 0, iteration 0, instance b):
+// goal = object start + rho (cos phi, sin phi), rho ~ U[rho_lo, rho_hi],
+// phi ~ U[phi_lo, phi_hi].
+struct Instance {
+  double goal[2];
+};
+
+inline Instance draw_instance(const RefScene &s, uint64_t seed, uint32_t b) {
+  Word4 x = philox_draw(seed, STREAM_SCENE, 0, 0, 0, b);
+  const double u0 = (double)u01(x.w[0]);
+  const double u1 = (double)u01(x.w[1]);
+  const double rho = s.goal_rho_lo + (s.goal_rho_hi - s.goal_rho_lo) * u0;
+  const double phi = s.goal_phi_lo + (s.goal_phi_hi - s.goal_phi_lo) * u1;
+  Instance in;
+  in.goal[0] = s.obj_pos0[0] + rho * std::cos(phi);
+  in.goal[1] = s.obj_pos0[1] + rho * std::sin(phi);
+  return in;
+}
+
+}  // namespace ref
