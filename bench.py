@@ -1,0 +1,157 @@
+"""Throughput of the CE hot path on one MI355X.
+
+One step = one CE iteration of the whole hot path on one batch of synthetic
+input: Philox sampling of the population, the rollout of every sampled plan
+over the full horizon, elite selection and the FP64 refit.  Prints one JSON
+line with env-steps/s (one env-step = one control step dt of one environment,
+with all its physics substeps), CE iterations/s, the roofline of the rollout
+kernel and the CPU oracle's throughput on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks: FP32 vector (packed) 157.3 TFLOP/s, HBM3E 8 TB/s.
+PEAK_FP32_TFLOPS = 157.3
+DEFAULT_WORKLOAD = "push"
+
+# HBM traffic per rollout launch measured with rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+# scaled by the copy-kernel calibration), keyed by workload; valid only while
+# the rollout sources hash to the recorded value.
+MEASURED_TRAFFIC = {}
+
+ROLLOUT_SOURCES = {
+    "push": ["rollout_push.hip", "rigid.hpp", "devmath.hpp"],
+}
+
+
+def _src_hash(workload):
+    h = hashlib.sha256()
+    for f in ROLLOUT_SOURCES.get(workload, []):
+        with open(os.path.join(ROOT, "paper_2512_11571_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(w, seed, budget_s):
+    """The oracle (FP64, all host threads up to 16) on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle import oracle as O
+    cem = w["cem"]
+    threads = max(1, min(16, os.cpu_count() or 1))
+    H = w["scene"]["horizon"]
+    mu0 = np.asarray(cem["mu0"], np.float64)
+    L, _ = O.factor_cov(np.diag(np.asarray(cem["cov0_diag"], np.float64)))
+    n = min(cem["pop"], 4 * threads)
+    Z = O.sample(seed, 0, 0, n, mu0, L)
+    done, reps = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        O.rollout(w, seed, Z, threads=threads)
+        done += n * H
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "%d x %d rollouts of %d iteration-0 samples (full horizon %d steps), %.1f s"
+                      % (reps, n, n, H, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own "
+              "share of the population independently); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_11571_amd import workloads
+    from paper_2512_11571_amd.binding import Context
+
+    w = workloads.load(a.workload)
+    cem, sc = w["cem"], w["scene"]
+    pop, H, D = cem["pop"], sc["horizon"], {"push": 3, "pickplace": 16, "movepush": 12}[sc["kind"]]
+    K = a.steps if a.steps is not None else cem["iters"]
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    Z = torch.empty((pop, D), dtype=torch.float32, device=dev)
+    cost = torch.empty(pop, dtype=torch.float32, device=dev)
+    tier = torch.empty(pop, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    with Context(w, seed=a.seed) as c:
+        def step(j, evs=None):
+            c.cem_sample(j, Z, stream)
+            if evs is not None:
+                evs[0].record(stream)
+            c.rollout_batch(Z, cost, tier, None, stream)
+            if evs is not None:
+                evs[1].record(stream)
+            c.cem_refit(Z, cost, tier, None, None, stream)
+
+        for j in range(a.warmup):
+            step(j)
+        torch.cuda.synchronize()
+        c.reset()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(K):
+            step(j, evs[j])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        roll_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+        mu, S = c.get_theta()
+
+    env_steps = pop * H * K
+    value = env_steps / elapsed
+    roll_avg_s = sum(roll_ms) / len(roll_ms) / 1e3
+    meas = w.get("measurement", {})
+    fps = meas.get("flops_per_env_step")
+    achieved = (fps * pop * H / roll_avg_s / 1e12) if fps else None
+    tr = MEASURED_TRAFFIC.get(a.workload)
+    traffic = tr["bytes_per_launch"] if tr and tr.get("src_hash") == _src_hash(a.workload) else None
+    out = {
+        "metric": "env-steps/s (CE iterations/s alongside)",
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / K * 1e3,
+        "cem_iters_per_s": K / elapsed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FP64 refit and Cholesky)",
+        "data": "synthetic (seeded scene and Philox samples)",
+        "config": {"workload": a.workload, "pop": pop, "horizon": H, "substeps": sc["substeps"], "dim": D,
+                   "n_elite": cem["n_elite"], "dt": sc["dt"], "seed": a.seed},
+        "rollout_kernel_ms": roll_avg_s * 1e3,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": traffic,
+                     "flops_per_env_step": fps},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, a.seed, a.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/* cemtamp: cross-entropy optimisation of the controller parameters of a fixed
+ * task-and-motion plan, rolled out in parallel through contact-rich rigid-body
+ * dynamics on an AMD Instinct MI355X (gfx950).
+ *
+ * The method (Sec. III-B, Alg. 1 of "Cross-Entropy Optimization of Physically
+ * Grounded Task and Motion Plans"): given a symbolic plan pi = (a_1..a_k) whose
+ * actions carry continuous controller parameters Z_pi, repeat
+ *   sample n_env parameter vectors Z ~ phi(theta)          -> cem_sample
+ *   roll every plan out through the dynamics, scoring the
+ *   per-step action costs, final cost and feasibility        -> rollout_batch
+ *   refit theta to the top N_e feasible samples              -> cem_refit
+ * and return the best sample and the final theta             -> plan_solve.
+ * phi is a Gaussian N(mu, Sigma): independent normals (cov_mode 0, as in the
+ * paper's experiments, Sec. IV-A "Algorithm setting") or a full covariance
+ * (cov_mode 1).
+ *
+ * Conventions for every call:
+ *  - Return value: CEM_OK (0) or a CEM_E_* code; nothing aborts or throws.
+ *    cem_last_error(ctx) gives a text for the last failure on that context.
+ *  - "_dev" pointers are device (HBM) pointers owned by the caller; the library
+ *    never frees them.  "stream" is a hipStream_t passed as void* (NULL = the
+ *    null stream).  Calls taking a stream are asynchronous on it; faults of the
+ *    asynchronous work surface at the next synchronous call.
+ *  - The context owns theta, its Cholesky factor, the per-instance scene draws,
+ *    the elite scratch, the best-so-far record and the replay graph; all of it
+ *    is allocated by cem_init, so the per-iteration calls never allocate.
+ *  - One host thread at a time per context; separate contexts are independent.
+ */
+#ifndef CEMTAMP_H
+#define CEMTAMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CEM_OK = 0,
+  CEM_E_ARG = 1,      /* invalid argument (size, pointer, mode)            */
+  CEM_E_SCENE = 2,    /* invalid scene description                          */
+  CEM_E_ALLOC = 3,    /* device allocation failed                           */
+  CEM_E_HIP = 4,      /* a HIP runtime call failed                          */
+  CEM_E_NUMERIC = 5,  /* covariance not factorable: diagonal fallback used  */
+  CEM_E_STATE = 6     /* call not valid in the context's current state      */
+};
+
+enum { CEM_SCENE_PUSH = 1, CEM_SCENE_PICKPLACE = 2, CEM_SCENE_MOVEPUSH = 3 };
+
+#define CEM_MAX_STATIC 8
+#define CEM_MAX_D 16
+#define CEM_STATS_COLS 8
+#define CEM_TRACE_FREE 13
+
+/* The physical scene and the plan's controllers (Problem 1: state space
+ * X = Q x SE(3)^m, dynamics x_{t+1} = f(x_t, c_i, z_i), horizon T).
+ * Units SI, z up, gravity along -z.  Copied by cem_init. */
+typedef struct cem_scene {
+  int32_t kind;                 /* CEM_SCENE_*                                     */
+  int32_t substeps;             /* physics substeps per control step dt            */
+  int32_t horizon;              /* control steps T                                 */
+  float dt, gravity, k_contact, c_contact, eps_v;
+  float mu_ground, mu_tool, mu_static, mu_ramp;   /* friction per contact class  */
+  float obj_half[3], obj_mass, obj_pos0[3], obj_yaw0;  /* the free object (a box) */
+  int32_t n_static;             /* static boxes: centre, half extents, yaw, pitch */
+  float st_center[CEM_MAX_STATIC][3], st_half[CEM_MAX_STATIC][3];
+  float st_yaw[CEM_MAX_STATIC], st_pitch[CEM_MAX_STATIC];
+  int32_t st_ramp[CEM_MAX_STATIC];              /* 1: friction class mu_ramp      */
+  float pusher_radius, pusher_standoff, pusher_height, pusher_vmax;
+  int32_t pusher_steps;         /* control steps the pusher moves                  */
+  float goal_rho_lo, goal_rho_hi, goal_phi_lo, goal_phi_hi;  /* seeded goal draw  */
+  float goal_tol, time_weight;  /* success radius; weight of the time cost         */
+} cem_scene;
+
+/* One CE problem (Alg. 1 inputs).  mu0 has D entries, cov0 D x D row-major
+ * (cov_mode 0 reads its diagonal only).  D is fixed by the scene kind
+ * (push 3, pick-place 16, move-push 12).  Pointers are host pointers, copied. */
+typedef struct cem_problem {
+  const cem_scene *scene;
+  int32_t pop;                  /* n_env: samples per iteration, 1..65536          */
+  int32_t n_elite;              /* N_e, 1..min(pop, 256)                           */
+  int32_t cov_mode;             /* 0 diagonal, 1 full                              */
+  int32_t reserved;
+  const double *mu0, *cov0;
+  uint64_t seed;                /* Philox key                                      */
+  uint32_t instance;            /* Philox counter word 3 (task instance id)        */
+} cem_problem;
+
+/* Output of plan_solve (host memory, filled on return). */
+typedef struct cem_result {
+  float best_z[CEM_MAX_D];      /* best sample over all iterations                 */
+  float best_cost;
+  int32_t best_tier;            /* 0 feasible, 1 actions ok / goal missed, 2 other, 3 diverged */
+  int32_t iters_done;
+  int32_t dim;
+  double mu[CEM_MAX_D];         /* final theta                                     */
+  double cov[CEM_MAX_D * CEM_MAX_D];
+} cem_result;
+
+typedef struct cem_ctx cem_ctx;
+
+/* Validates the problem, allocates the context's device state on the current
+ * device, draws the per-instance scene quantities (the push goal) on the GPU
+ * and factors cov0.  Synchronous.  *out is NULL on failure. */
+int cem_init(const cem_problem *p, cem_ctx **out);
+void cem_free(cem_ctx *c);
+
+int cem_dim(const cem_ctx *c);
+/* sizeof of the ABI structs (0 cem_scene, 1 cem_problem, 2 cem_result; else 0),
+ * for bindings to check their layouts. */
+int cem_sizeof(int which);
+const char *cem_strerror(int code);
+const char *cem_last_error(const cem_ctx *c);
+
+/* Alg. 1, sampling step: Z_dev (pop x D row-major, FP32) = mu + L eps with
+ * eps ~ N(0, I) from Philox-4x32-10 counters (tag 0, sample i, iteration
+ * iter, instance) and Box-Muller; accumulated in FP64, rounded once. */
+int cem_sample(cem_ctx *c, int32_t iter, float *Z_dev, void *stream);
+
+/* Alg. 1, evaluation step: roll every row of Z_dev (pop x D) out for the
+ * horizon and write cost_dev[pop] (plan cost, Problem 2 objective),
+ * tier_dev[pop] (0 feasible, 1 all actions succeeded but goal missed,
+ * 2 other, 3 diverged) and, if pose_dev is non-NULL, the final object pose
+ * pose_dev[pop][7] = (p, q).  pop may differ from the problem's pop. */
+int rollout_batch(cem_ctx *c, const float *Z_dev, int32_t pop, float *cost_dev, uint8_t *tier_dev,
+                  float *pose_dev, void *stream);
+
+/* Same dynamics, recording the free object's state (p q v w, 13 floats)
+ * after each of the first n_steps control steps: trace_dev[pop][n_steps][13]. */
+int rollout_trace(cem_ctx *c, const float *Z_dev, int32_t pop, int32_t n_steps, float *trace_dev, void *stream);
+
+/* Alg. 1, update step: order the samples by (tier, cost, index), NaN cost as
+ * tier 3; take the top N_e feasible, or all feasible if fewer, or - with
+ * none feasible - the best whose actions all succeeded (Sec. III-B); refit
+ * mu and Sigma (maximum likelihood, FP64) and factor Sigma in FP64.  A
+ * single selected sample gives mu = that sample, Sigma = diag((0.1 sigma0)^2);
+ * nothing selectable leaves theta unchanged.  Optional outputs:
+ * elite_idx_dev[n_elite] (-1 padded), sel_info_dev[6] = (n_e, mode,
+ * n_tier0..3).  Also updates the best-so-far record. */
+int cem_refit(cem_ctx *c, const float *Z_dev, const float *cost_dev, const uint8_t *tier_dev, int32_t pop,
+              int32_t *elite_idx_dev, int32_t *sel_info_dev, void *stream);
+
+/* Alg. 1 end to end: iters iterations of sample -> rollout -> refit on the
+ * context's own buffers, replayed from one captured HIP graph per iteration.
+ * Continues from the context's current theta and iteration counter.
+ * Synchronous.  stats_host (nullable) gets iters rows of CEM_STATS_COLS floats:
+ * best cost of the iteration, n_tier0..3, n_e, mode, best cost so far. */
+int plan_solve(cem_ctx *c, int32_t iters, cem_result *res, float *stats_host, void *stream);
+
+/* theta access (host arrays mu[D], cov[D*D]); set refactors.  Synchronous. */
+int cem_get_theta(cem_ctx *c, double *mu, double *cov);
+int cem_set_theta(cem_ctx *c, const double *mu, const double *cov);
+/* Cholesky factor currently used by cem_sample (host L[D*D]). Synchronous. */
+int cem_get_factor(cem_ctx *c, double *L);
+/* Per-instance draws (push: goal xy). Synchronous. */
+int cem_get_instance(cem_ctx *c, double *goal_xy);
+/* Reset the best-so-far record and the iteration counter. Synchronous. */
+int cem_reset(cem_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,262 @@
+"""Thin ctypes binding of libcemtamp.so (include/cemtamp.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; this module turns
+workload dicts into the C structs, torch device tensors into pointers and the
+current torch stream into a hipStream_t.  There is no fallback: if the
+library is not built or no GPU is present, calls raise.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcemtamp.so")
+
+CEM_OK = 0
+ERRORS = {1: "CEM_E_ARG", 2: "CEM_E_SCENE", 3: "CEM_E_ALLOC", 4: "CEM_E_HIP", 5: "CEM_E_NUMERIC", 6: "CEM_E_STATE"}
+SCENE_KIND = {"push": 1, "pickplace": 2, "movepush": 3}
+DIM = {"push": 3, "pickplace": 16, "movepush": 12}
+MAX_STATIC = 8
+MAX_D = 16
+STATS_COLS = 8
+TRACE_FREE = 13
+
+_f = ctypes.c_float
+_i = ctypes.c_int32
+
+
+class CemScene(ctypes.Structure):
+    _fields_ = [
+        ("kind", _i), ("substeps", _i), ("horizon", _i),
+        ("dt", _f), ("gravity", _f), ("k_contact", _f), ("c_contact", _f), ("eps_v", _f),
+        ("mu_ground", _f), ("mu_tool", _f), ("mu_static", _f), ("mu_ramp", _f),
+        ("obj_half", _f * 3), ("obj_mass", _f), ("obj_pos0", _f * 3), ("obj_yaw0", _f),
+        ("n_static", _i),
+        ("st_center", (_f * 3) * MAX_STATIC), ("st_half", (_f * 3) * MAX_STATIC),
+        ("st_yaw", _f * MAX_STATIC), ("st_pitch", _f * MAX_STATIC), ("st_ramp", _i * MAX_STATIC),
+        ("pusher_radius", _f), ("pusher_standoff", _f), ("pusher_height", _f), ("pusher_vmax", _f),
+        ("pusher_steps", _i),
+        ("goal_rho_lo", _f), ("goal_rho_hi", _f), ("goal_phi_lo", _f), ("goal_phi_hi", _f),
+        ("goal_tol", _f), ("time_weight", _f),
+    ]
+
+
+class CemProblem(ctypes.Structure):
+    _fields_ = [
+        ("scene", ctypes.POINTER(CemScene)),
+        ("pop", _i), ("n_elite", _i), ("cov_mode", _i), ("reserved", _i),
+        ("mu0", ctypes.POINTER(ctypes.c_double)), ("cov0", ctypes.POINTER(ctypes.c_double)),
+        ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
+    ]
+
+
+class CemResult(ctypes.Structure):
+    _fields_ = [
+        ("best_z", _f * MAX_D), ("best_cost", _f), ("best_tier", _i), ("iters_done", _i), ("dim", _i),
+        ("mu", ctypes.c_double * MAX_D), ("cov", ctypes.c_double * (MAX_D * MAX_D)),
+    ]
+
+
+EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem_last_error", "cem_sample", "rollout_batch",
+           "rollout_trace", "cem_refit", "plan_solve", "cem_get_theta", "cem_set_theta", "cem_get_factor",
+           "cem_get_instance", "cem_reset"]
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcemtamp.so is not built: run `python -m paper_2512_11571_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, P = ctypes.c_void_p, ctypes.POINTER
+        L.cem_init.argtypes = [P(CemProblem), P(vp)]
+        L.cem_free.argtypes = [vp]
+        L.cem_free.restype = None
+        L.cem_dim.argtypes = [vp]
+        L.cem_strerror.argtypes = [ctypes.c_int]
+        L.cem_strerror.restype = ctypes.c_char_p
+        L.cem_last_error.argtypes = [vp]
+        L.cem_last_error.restype = ctypes.c_char_p
+        L.cem_sample.argtypes = [vp, _i, vp, vp]
+        L.rollout_batch.argtypes = [vp, vp, _i, vp, vp, vp, vp]
+        L.rollout_trace.argtypes = [vp, vp, _i, _i, vp, vp]
+        L.cem_refit.argtypes = [vp, vp, vp, vp, _i, vp, vp, vp]
+        L.plan_solve.argtypes = [vp, _i, P(CemResult), vp, vp]
+        L.cem_get_theta.argtypes = [vp, vp, vp]
+        L.cem_set_theta.argtypes = [vp, vp, vp]
+        L.cem_get_factor.argtypes = [vp, vp]
+        L.cem_get_instance.argtypes = [vp, vp]
+        L.cem_reset.argtypes = [vp]
+        L.cem_sizeof.argtypes = [ctypes.c_int]
+        for which, st in enumerate((CemScene, CemProblem, CemResult)):
+            if L.cem_sizeof(which) != ctypes.sizeof(st):
+                raise RuntimeError("ABI struct layout mismatch for %s" % st.__name__)
+        _lib = L
+    return _lib
+
+
+class CemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERRORS.get(code, code), msg))
+        self.code = code
+
+
+def make_scene(workload):
+    """cem_scene from a workload dict."""
+    sc = workload["scene"]
+    s = CemScene()
+    s.kind = SCENE_KIND[sc["kind"]]
+    s.substeps, s.horizon = sc["substeps"], sc["horizon"]
+    s.dt, s.gravity = sc["dt"], sc["gravity"]
+    s.k_contact, s.c_contact, s.eps_v = sc["k_contact"], sc["c_contact"], sc["eps_v"]
+    s.mu_ground, s.mu_tool, s.mu_static, s.mu_ramp = sc["mu_ground"], sc["mu_tool"], sc["mu_static"], sc["mu_ramp"]
+    ob = sc["object"]
+    for i in range(3):
+        s.obj_half[i] = ob["half"][i]
+        s.obj_pos0[i] = ob["pos0"][i]
+    s.obj_mass, s.obj_yaw0 = ob["mass"], ob["yaw0"]
+    boxes = sc.get("static_boxes", [])
+    if len(boxes) > MAX_STATIC:
+        raise ValueError("at most %d static boxes" % MAX_STATIC)
+    s.n_static = len(boxes)
+    for j, b in enumerate(boxes):
+        for i in range(3):
+            s.st_center[j][i] = b["center"][i]
+            s.st_half[j][i] = b["half"][i]
+        s.st_yaw[j], s.st_pitch[j] = b.get("yaw", 0.0), b.get("pitch", 0.0)
+        s.st_ramp[j] = 1 if b.get("ramp", False) else 0
+    pu = sc.get("pusher")
+    if pu:
+        s.pusher_radius, s.pusher_standoff, s.pusher_height = pu["radius"], pu["standoff"], pu["height"]
+        s.pusher_vmax, s.pusher_steps = pu["vmax"], pu["steps"]
+    go = sc.get("goal")
+    if go:
+        s.goal_rho_lo, s.goal_rho_hi = go["rho"]
+        s.goal_phi_lo, s.goal_phi_hi = go["phi"]
+        s.goal_tol, s.time_weight = go["tol"], go["time_weight"]
+    return s
+
+
+def _dptr(t):
+    """Device pointer of a CUDA/HIP torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """One CE problem on the current device (wraps cem_ctx*)."""
+
+    def __init__(self, workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None, cov0=None):
+        cem = workload["cem"]
+        self.workload = workload
+        self.kind = workload["scene"]["kind"]
+        self.D = DIM[self.kind]
+        self.pop = int(pop if pop is not None else cem["pop"])
+        self.n_elite = int(n_elite if n_elite is not None else cem["n_elite"])
+        self.cov_mode = 0 if cem["cov_mode"] == "diag" else 1
+        self._scene = make_scene(workload)
+        self._mu0 = np.ascontiguousarray(mu0 if mu0 is not None else cem["mu0"], np.float64)
+        if cov0 is None:
+            cov0 = np.diag(np.asarray(cem["cov0_diag"], np.float64))
+        self._cov0 = np.ascontiguousarray(cov0, np.float64)
+        p = CemProblem()
+        p.scene = ctypes.pointer(self._scene)
+        p.pop, p.n_elite, p.cov_mode = self.pop, self.n_elite, self.cov_mode
+        p.mu0 = self._mu0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.cov0 = self._cov0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.seed, p.instance = int(seed), int(instance)
+        h = ctypes.c_void_p()
+        rc = lib().cem_init(ctypes.byref(p), ctypes.byref(h))
+        if rc != CEM_OK:
+            raise CemError(rc, lib().cem_strerror(rc).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != CEM_OK:
+            raise CemError(rc, lib().cem_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cem_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # --- the C ABI calls -------------------------------------------------
+    def cem_sample(self, it, Z, stream=None):
+        self._check(lib().cem_sample(self.h, int(it), _dptr(Z), _stream(stream)))
+
+    def rollout_batch(self, Z, cost, tier, pose=None, stream=None):
+        self._check(lib().rollout_batch(self.h, _dptr(Z), Z.shape[0], _dptr(cost), _dptr(tier), _dptr(pose),
+                                        _stream(stream)))
+
+    def rollout_trace(self, Z, n_steps, trace, stream=None):
+        self._check(lib().rollout_trace(self.h, _dptr(Z), Z.shape[0], int(n_steps), _dptr(trace), _stream(stream)))
+
+    def cem_refit(self, Z, cost, tier, elite_idx=None, sel_info=None, stream=None):
+        self._check(lib().cem_refit(self.h, _dptr(Z), _dptr(cost), _dptr(tier), Z.shape[0], _dptr(elite_idx),
+                                    _dptr(sel_info), _stream(stream)))
+
+    def plan_solve(self, iters, stream=None):
+        res = CemResult()
+        stats = np.zeros((max(iters, 1), STATS_COLS), np.float32)
+        s = _stream(stream) if stream is not None else None
+        self._check(lib().plan_solve(self.h, int(iters), ctypes.byref(res), _np_ptr(stats), s))
+        D = self.D
+        return dict(best_z=np.array(res.best_z[:D], np.float32), best_cost=float(res.best_cost),
+                    best_tier=int(res.best_tier), iters_done=int(res.iters_done),
+                    mu=np.array(res.mu[:D]), cov=np.array(res.cov[:D * D]).reshape(D, D), stats=stats[:iters])
+
+    def get_theta(self):
+        mu = np.zeros(self.D)
+        cov = np.zeros((self.D, self.D))
+        self._check(lib().cem_get_theta(self.h, _np_ptr(mu), _np_ptr(cov)))
+        return mu, cov
+
+    def set_theta(self, mu, cov):
+        mu = np.ascontiguousarray(mu, np.float64)
+        cov = np.ascontiguousarray(cov, np.float64)
+        self._check(lib().cem_set_theta(self.h, _np_ptr(mu), _np_ptr(cov)))
+
+    def get_factor(self):
+        L = np.zeros((self.D, self.D))
+        self._check(lib().cem_get_factor(self.h, _np_ptr(L)))
+        return L
+
+    def get_instance(self):
+        g = np.zeros(2)
+        self._check(lib().cem_get_instance(self.h, _np_ptr(g)))
+        return g
+
+    def reset(self):
+        self._check(lib().cem_reset(self.h))

@@ -1,0 +1,370 @@
+// The C ABI (include/cemtamp.h): context management, argument validation,
+// launches and the replayed CE iteration.  Host code only; every step of the
+// method runs in the kernels of the other translation units.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+using namespace cem;
+
+struct cem_ctx {
+  cem_scene scene;
+  int D = 0, pop = 0, n_elite = 0, cov_mode = 0;
+  uint64_t seed = 0;
+  uint32_t inst = 0;
+  int device = 0;
+  DevState *st = nullptr;
+  float *Z = nullptr, *cost = nullptr, *pose = nullptr, *stats = nullptr;
+  uint8_t *tier = nullptr;
+  hipStream_t own = nullptr;
+  hipGraphExec_t iter_graph = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int fail(cem_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(cem_ctx *c, hipError_t e, const char *what) {
+  return fail(c, CEM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr)                           \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+int dim_of(int kind) {
+  switch (kind) {
+    case CEM_SCENE_PUSH: return 3;
+    case CEM_SCENE_PICKPLACE: return 16;
+    case CEM_SCENE_MOVEPUSH: return 12;
+    default: return 0;
+  }
+}
+
+bool pos(float x) { return std::isfinite(x) && x > 0.0f; }
+bool nonneg(float x) { return std::isfinite(x) && x >= 0.0f; }
+
+const char *check_scene(const cem_scene &s) {
+  if (dim_of(s.kind) == 0) return "unknown scene kind";
+  if (s.kind != CEM_SCENE_PUSH) return "scene kind not supported by this build";
+  if (s.substeps < 1 || s.substeps > 1000) return "substeps out of range [1, 1000]";
+  if (s.horizon < 1 || s.horizon > 100000) return "horizon out of range [1, 100000]";
+  if (!pos(s.dt) || !nonneg(s.gravity) || !nonneg(s.k_contact) || !nonneg(s.c_contact) || !pos(s.eps_v))
+    return "invalid physical constants";
+  if (!nonneg(s.mu_ground) || !nonneg(s.mu_tool) || !nonneg(s.mu_static) || !nonneg(s.mu_ramp))
+    return "invalid friction coefficient";
+  if (!pos(s.obj_half[0]) || !pos(s.obj_half[1]) || !pos(s.obj_half[2]) || !pos(s.obj_mass))
+    return "invalid object";
+  if (s.n_static < 0 || s.n_static > CEM_MAX_STATIC) return "n_static out of range";
+  if (s.kind == CEM_SCENE_PUSH) {
+    if (!pos(s.pusher_radius) || !nonneg(s.pusher_vmax) || s.pusher_steps < 0) return "invalid pusher";
+    if (!nonneg(s.goal_tol) || !nonneg(s.time_weight)) return "invalid goal tolerance or time weight";
+    if (!(s.goal_rho_lo <= s.goal_rho_hi) || !(s.goal_phi_lo <= s.goal_phi_hi)) return "invalid goal ranges";
+  }
+  return nullptr;
+}
+
+int launch_rollout(cem_ctx *c, const float *Z, int pop, float *cost, uint8_t *tier, float *pose, float *trace,
+                   int trace_steps, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  switch (c->scene.kind) {
+    case CEM_SCENE_PUSH:
+      e = launch_rollout_push(c->scene, c->st, Z, pop, cost, tier, pose, trace, trace_steps, s);
+      break;
+    default:
+      return fail(c, CEM_E_SCENE, "scene kind not supported by this build");
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "rollout launch");
+  return CEM_OK;
+}
+
+int factor_and_check(cem_ctx *c, hipStream_t s) {
+  HIPCHK(c, launch_factor(c->st, s));
+  int32_t status = 0;
+  HIPCHK(c, hipMemcpyAsync(&status, &c->st->factor_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (status != 0) return fail(c, CEM_E_NUMERIC, "covariance is not positive definite: diagonal fallback in use");
+  return CEM_OK;
+}
+
+int reset_best(cem_ctx *c, hipStream_t s) {
+  const int32_t iter = 0, tier = 4;
+  const float inf = INFINITY;
+  HIPCHK(c, hipMemcpyAsync(&c->st->iter, &iter, sizeof iter, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(&c->st->best_tier, &tier, sizeof tier, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(&c->st->best_cost, &inf, sizeof inf, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return CEM_OK;
+}
+
+// theta upload: mu (D), covariance (D x D; off-diagonals dropped in diag mode).
+int upload_theta(cem_ctx *c, const double *mu, const double *cov, bool also_cov0, hipStream_t s) {
+  const int D = c->D;
+  double hm[MAX_D], hs[MAX_D * MAX_D];
+  for (int d = 0; d < D; ++d) {
+    if (!std::isfinite(mu[d])) return fail(c, CEM_E_ARG, "mu has a non-finite entry");
+    hm[d] = mu[d];
+  }
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) {
+      const double v = cov[a * D + b];
+      if (!std::isfinite(v)) return fail(c, CEM_E_ARG, "covariance has a non-finite entry");
+      if (v != cov[b * D + a]) return fail(c, CEM_E_ARG, "covariance is not symmetric");
+      hs[a * D + b] = (c->cov_mode == 0 && a != b) ? 0.0 : v;
+    }
+  HIPCHK(c, hipMemcpyAsync(c->st->mu, hm, sizeof(double) * D, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->st->S, hs, sizeof(double) * D * D, hipMemcpyHostToDevice, s));
+  if (also_cov0) HIPCHK(c, hipMemcpyAsync(c->st->cov0, hs, sizeof(double) * D * D, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return CEM_OK;
+}
+
+void release(cem_ctx *c) {
+  if (!c) return;
+  if (c->iter_graph) (void)hipGraphExecDestroy(c->iter_graph);
+  if (c->own) (void)hipStreamDestroy(c->own);
+  (void)hipFree(c->st);
+  (void)hipFree(c->Z);
+  (void)hipFree(c->cost);
+  (void)hipFree(c->pose);
+  (void)hipFree(c->tier);
+  (void)hipFree(c->stats);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cem_strerror(int code) {
+  switch (code) {
+    case CEM_OK: return "ok";
+    case CEM_E_ARG: return "invalid argument";
+    case CEM_E_SCENE: return "invalid scene";
+    case CEM_E_ALLOC: return "device allocation failed";
+    case CEM_E_HIP: return "HIP runtime error";
+    case CEM_E_NUMERIC: return "covariance not factorable (diagonal fallback used)";
+    case CEM_E_STATE: return "invalid context state";
+    default: return "unknown error";
+  }
+}
+
+const char *cem_last_error(const cem_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int cem_dim(const cem_ctx *c) { return c ? c->D : 0; }
+
+int cem_sizeof(int which) {
+  switch (which) {
+    case 0: return (int)sizeof(cem_scene);
+    case 1: return (int)sizeof(cem_problem);
+    case 2: return (int)sizeof(cem_result);
+    default: return 0;
+  }
+}
+
+int cem_init(const cem_problem *p, cem_ctx **out) {
+  if (!out) return CEM_E_ARG;
+  *out = nullptr;
+  if (!p || !p->scene || !p->mu0 || !p->cov0) return CEM_E_ARG;
+  const char *why = check_scene(*p->scene);
+  if (why) return CEM_E_SCENE;
+  const int D = dim_of(p->scene->kind);
+  if (p->pop < 1 || p->pop > MAX_POP) return CEM_E_ARG;
+  if (p->n_elite < 1 || p->n_elite > p->pop || p->n_elite > MAX_ELITE) return CEM_E_ARG;
+  if (p->cov_mode != 0 && p->cov_mode != 1) return CEM_E_ARG;
+
+  cem_ctx *c = new (std::nothrow) cem_ctx();
+  if (!c) return CEM_E_ALLOC;
+  c->scene = *p->scene;
+  c->D = D;
+  c->pop = p->pop;
+  c->n_elite = p->n_elite;
+  c->cov_mode = p->cov_mode;
+  c->seed = p->seed;
+  c->inst = p->instance;
+  int rc = CEM_OK;
+  do {
+    if (hipGetDevice(&c->device) != hipSuccess) { rc = fail(c, CEM_E_HIP, "hipGetDevice"); break; }
+    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
+      rc = fail(c, CEM_E_HIP, "stream create");
+      break;
+    }
+    const size_t P = (size_t)p->pop;
+    if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess || hipMalloc(&c->Z, sizeof(float) * P * D) != hipSuccess ||
+        hipMalloc(&c->cost, sizeof(float) * P) != hipSuccess || hipMalloc(&c->pose, sizeof(float) * P * 7) != hipSuccess ||
+        hipMalloc(&c->tier, P) != hipSuccess ||
+        hipMalloc(&c->stats, sizeof(float) * MAX_STATS_ITERS * CEM_STATS_COLS) != hipSuccess) {
+      rc = fail(c, CEM_E_ALLOC, "device allocation");
+      break;
+    }
+    DevState h;
+    std::memset(&h, 0, sizeof h);
+    h.D = D;
+    h.cov_mode = p->cov_mode;
+    h.n_elite = p->n_elite;
+    h.best_cost = INFINITY;
+    h.best_tier = 4;
+    if (hipMemcpyAsync(c->st, &h, sizeof h, hipMemcpyHostToDevice, c->own) != hipSuccess) {
+      rc = fail(c, CEM_E_HIP, "state upload");
+      break;
+    }
+    if ((rc = upload_theta(c, p->mu0, p->cov0, true, c->own)) != CEM_OK) break;
+    if (launch_instance_draw(c->scene, c->seed, c->inst, c->st, c->own) != hipSuccess) {
+      rc = fail(c, CEM_E_HIP, "instance draw launch");
+      break;
+    }
+    rc = factor_and_check(c, c->own);
+    if (rc == CEM_E_NUMERIC) rc = fail(c, CEM_E_ARG, "cov0 is not positive definite");
+  } while (0);
+  if (rc != CEM_OK) {
+    release(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return CEM_OK;
+}
+
+void cem_free(cem_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->own);
+  release(c);
+  delete c;
+}
+
+int cem_sample(cem_ctx *c, int32_t iter, float *Z_dev, void *stream) {
+  if (!c) return CEM_E_ARG;
+  if (!Z_dev || iter < 0) return fail(c, CEM_E_ARG, "Z_dev is null or iter < 0");
+  HIPCHK(c, launch_sample(c->seed, c->inst, iter, c->st, c->pop, c->D, Z_dev, (hipStream_t)stream));
+  return CEM_OK;
+}
+
+int rollout_batch(cem_ctx *c, const float *Z_dev, int32_t pop, float *cost_dev, uint8_t *tier_dev, float *pose_dev,
+                  void *stream) {
+  if (!c) return CEM_E_ARG;
+  if (!Z_dev || !cost_dev || !tier_dev) return fail(c, CEM_E_ARG, "null buffer");
+  if (pop < 0 || pop > MAX_POP) return fail(c, CEM_E_ARG, "pop out of range [0, 65536]");
+  if (pop == 0) return CEM_OK;
+  return launch_rollout(c, Z_dev, pop, cost_dev, tier_dev, pose_dev, nullptr, 0, (hipStream_t)stream);
+}
+
+int rollout_trace(cem_ctx *c, const float *Z_dev, int32_t pop, int32_t n_steps, float *trace_dev, void *stream) {
+  if (!c) return CEM_E_ARG;
+  if (!Z_dev || !trace_dev) return fail(c, CEM_E_ARG, "null buffer");
+  if (pop < 0 || pop > MAX_POP) return fail(c, CEM_E_ARG, "pop out of range [0, 65536]");
+  if (n_steps < 1 || n_steps > c->scene.horizon) return fail(c, CEM_E_ARG, "n_steps out of range [1, horizon]");
+  if (pop == 0) return CEM_OK;
+  return launch_rollout(c, Z_dev, pop, nullptr, nullptr, nullptr, trace_dev, n_steps, (hipStream_t)stream);
+}
+
+int cem_refit(cem_ctx *c, const float *Z_dev, const float *cost_dev, const uint8_t *tier_dev, int32_t pop,
+              int32_t *elite_idx_dev, int32_t *sel_info_dev, void *stream) {
+  if (!c) return CEM_E_ARG;
+  if (!Z_dev || !cost_dev || !tier_dev) return fail(c, CEM_E_ARG, "null buffer");
+  if (pop < 1 || pop > MAX_POP) return fail(c, CEM_E_ARG, "pop out of range [1, 65536]");
+  HIPCHK(c, launch_select_refit(c->st, Z_dev, cost_dev, tier_dev, pop, elite_idx_dev, sel_info_dev, c->stats,
+                                MAX_STATS_ITERS, 1, (hipStream_t)stream));
+  return CEM_OK;
+}
+
+int plan_solve(cem_ctx *c, int32_t iters, cem_result *res, float *stats_host, void *stream) {
+  if (!c) return CEM_E_ARG;
+  if (!res || iters < 0) return fail(c, CEM_E_ARG, "null result or iters < 0");
+  hipStream_t s = stream ? (hipStream_t)stream : c->own;
+  int32_t it0 = 0;
+  HIPCHK(c, hipMemcpyAsync(&it0, &c->st->iter, sizeof it0, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (it0 + iters > MAX_STATS_ITERS) return fail(c, CEM_E_ARG, "iteration counter would exceed 4096");
+  if (!c->iter_graph) {
+    // one CE iteration: sample (iteration read from the device counter) ->
+    // rollout -> select/refit (advances the counter), captured once
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = launch_sample(c->seed, c->inst, -1, c->st, c->pop, c->D, c->Z, c->own);
+    int r2 = launch_rollout(c, c->Z, c->pop, c->cost, c->tier, c->pose, nullptr, 0, c->own);
+    hipError_t e3 = launch_select_refit(c->st, c->Z, c->cost, c->tier, c->pop, nullptr, nullptr, c->stats,
+                                        MAX_STATS_ITERS, 1, c->own);
+    hipError_t e4 = hipStreamEndCapture(c->own, &g);
+    if (e1 != hipSuccess || r2 != CEM_OK || e3 != hipSuccess || e4 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(c, CEM_E_HIP, "graph capture of the CE iteration failed");
+    }
+    hipError_t e5 = hipGraphInstantiate(&c->iter_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e5 != hipSuccess) {
+      c->iter_graph = nullptr;
+      return hip_fail(c, e5, "hipGraphInstantiate");
+    }
+  }
+  for (int j = 0; j < iters; ++j) HIPCHK(c, hipGraphLaunch(c->iter_graph, s));
+  DevState h;
+  HIPCHK(c, hipMemcpyAsync(&h, c->st, sizeof h, hipMemcpyDeviceToHost, s));
+  if (stats_host && iters > 0)
+    HIPCHK(c, hipMemcpyAsync(stats_host, c->stats + (size_t)it0 * CEM_STATS_COLS,
+                             sizeof(float) * iters * CEM_STATS_COLS, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  std::memset(res, 0, sizeof *res);
+  res->dim = c->D;
+  for (int d = 0; d < c->D; ++d) {
+    res->best_z[d] = h.best_z[d];
+    res->mu[d] = h.mu[d];
+  }
+  for (int t = 0; t < c->D * c->D; ++t) res->cov[t] = h.S[t];
+  res->best_cost = h.best_cost;
+  res->best_tier = h.best_tier;
+  res->iters_done = h.iter;
+  return h.factor_status ? fail(c, CEM_E_NUMERIC, "diagonal fallback used in the last refit") : CEM_OK;
+}
+
+int cem_get_theta(cem_ctx *c, double *mu, double *cov) {
+  if (!c) return CEM_E_ARG;
+  if (!mu || !cov) return fail(c, CEM_E_ARG, "null output");
+  HIPCHK(c, hipMemcpyAsync(mu, c->st->mu, sizeof(double) * c->D, hipMemcpyDeviceToHost, c->own));
+  HIPCHK(c, hipMemcpyAsync(cov, c->st->S, sizeof(double) * c->D * c->D, hipMemcpyDeviceToHost, c->own));
+  HIPCHK(c, hipStreamSynchronize(c->own));
+  return CEM_OK;
+}
+
+int cem_set_theta(cem_ctx *c, const double *mu, const double *cov) {
+  if (!c) return CEM_E_ARG;
+  if (!mu || !cov) return fail(c, CEM_E_ARG, "null input");
+  HIPCHK(c, hipDeviceSynchronize());
+  int rc = upload_theta(c, mu, cov, false, c->own);
+  if (rc != CEM_OK) return rc;
+  return factor_and_check(c, c->own);
+}
+
+int cem_get_factor(cem_ctx *c, double *L) {
+  if (!c) return CEM_E_ARG;
+  if (!L) return fail(c, CEM_E_ARG, "null output");
+  HIPCHK(c, hipMemcpyAsync(L, c->st->L, sizeof(double) * c->D * c->D, hipMemcpyDeviceToHost, c->own));
+  HIPCHK(c, hipStreamSynchronize(c->own));
+  return CEM_OK;
+}
+
+int cem_get_instance(cem_ctx *c, double *goal_xy) {
+  if (!c) return CEM_E_ARG;
+  if (!goal_xy) return fail(c, CEM_E_ARG, "null output");
+  HIPCHK(c, hipMemcpyAsync(goal_xy, c->st->goal, sizeof(double) * 2, hipMemcpyDeviceToHost, c->own));
+  HIPCHK(c, hipStreamSynchronize(c->own));
+  return CEM_OK;
+}
+
+int cem_reset(cem_ctx *c) {
+  if (!c) return CEM_E_ARG;
+  HIPCHK(c, hipDeviceSynchronize());
+  return reset_best(c, c->own);
+}
+
+}  // extern "C"

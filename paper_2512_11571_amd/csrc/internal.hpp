@@ -1,0 +1,42 @@
+// Internal declarations shared by the library's translation units (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cemtamp.h"
+
+namespace cem {
+
+constexpr int MAX_D = CEM_MAX_D;
+constexpr int MAX_ELITE = 256;
+constexpr int MAX_POP = 65536;
+constexpr int MAX_STATS_ITERS = 4096;
+
+// Device-resident CE state of one context (one task instance).
+struct DevState {
+  double mu[MAX_D];
+  double S[MAX_D * MAX_D];     // covariance
+  double L[MAX_D * MAX_D];     // its Cholesky factor (lower, row-major)
+  double cov0[MAX_D * MAX_D];  // initial covariance (its diagonal feeds the single-elite noise)
+  double goal[2];              // per-instance draw (push goal)
+  int32_t iter;                // CE iteration counter for the replayed iteration
+  int32_t D, cov_mode, n_elite;
+  float best_z[MAX_D];
+  float best_cost;
+  int32_t best_tier;
+  int32_t factor_status;       // 0 ok, 1 diagonal fallback used
+  int32_t sel_info[6];         // n_e, mode, n_tier0..3 of the last refit
+};
+
+// Launchers (each file owns its kernels).
+hipError_t launch_instance_draw(const cem_scene &sc, uint64_t seed, uint32_t inst, DevState *st, hipStream_t s);
+hipError_t launch_sample(uint64_t seed, uint32_t inst, int32_t iter, const DevState *st, int pop, int D, float *Z,
+                         hipStream_t s);
+hipError_t launch_factor(DevState *st, hipStream_t s);
+hipError_t launch_select_refit(DevState *st, const float *Z, const float *cost, const uint8_t *tier, int pop,
+                               int32_t *elite_idx, int32_t *sel_info, float *stats, int stats_cap,
+                               int advance_iter, hipStream_t s);
+hipError_t launch_rollout_push(const cem_scene &sc, const DevState *st, const float *Z, int pop, float *cost,
+                               uint8_t *tier, float *pose, float *trace, int trace_steps, hipStream_t s);
+
+}  // namespace cem

@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every entry point include/cemtamp.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cemtamp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char|size_t)\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_method_calls():
+    names = _declared()
+    for n in ("cem_init", "cem_sample", "rollout_batch", "cem_refit", "plan_solve", "cem_free", "cem_strerror"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2512_11571_amd import binding
+    L = binding.lib()
+    for n in _declared():
+        assert hasattr(L, n), n
+    assert set(binding.EXPORTS) == set(_declared())
+
+
+def test_struct_layouts_match():
+    from paper_2512_11571_amd import binding
+    L = binding.lib()
+    assert L.cem_sizeof(0) == ctypes.sizeof(binding.CemScene)
+    assert L.cem_sizeof(1) == ctypes.sizeof(binding.CemProblem)
+    assert L.cem_sizeof(2) == ctypes.sizeof(binding.CemResult)
+    assert L.cem_sizeof(7) == 0
+
+
+def test_strerror_without_gpu():
+    from paper_2512_11571_amd import binding
+    L = binding.lib()
+    assert L.cem_strerror(0) == b"ok"
+    assert L.cem_strerror(5).startswith(b"covariance")
+    assert L.cem_last_error(None) == b"null context"
+
+
+def test_init_rejects_bad_arguments_before_touching_the_device():
+    from paper_2512_11571_amd import binding, workloads
+    w = workloads.load("push")
+    with pytest.raises(binding.CemError) as e:
+        binding.Context(w, pop=0)
+    assert e.value.code == 1
+    with pytest.raises(binding.CemError) as e:
+        binding.Context(w, n_elite=65)
+    assert e.value.code == 1
+    bad = dict(w, scene=dict(w["scene"], substeps=0))
+    with pytest.raises(binding.CemError) as e:
+        binding.Context(bad)
+    assert e.value.code == 2
