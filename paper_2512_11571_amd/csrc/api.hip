@@ -253,9 +253,9 @@ int cem_sample(cem_ctx *c, int32_t iter, float *Z_dev, void *stream) {
 int rollout_batch(cem_ctx *c, const float *Z_dev, int32_t pop, float *cost_dev, uint8_t *tier_dev, float *pose_dev,
                   void *stream) {
   if (!c) return CEM_E_ARG;
-  if (!Z_dev || !cost_dev || !tier_dev) return fail(c, CEM_E_ARG, "null buffer");
   if (pop < 0 || pop > MAX_POP) return fail(c, CEM_E_ARG, "pop out of range [0, 65536]");
   if (pop == 0) return CEM_OK;
+  if (!Z_dev || !cost_dev || !tier_dev) return fail(c, CEM_E_ARG, "null buffer");
   return launch_rollout(c, Z_dev, pop, cost_dev, tier_dev, pose_dev, nullptr, 0, (hipStream_t)stream);
 }
 

@@ -49,7 +49,8 @@ def test_factor_and_instance_draw(oracle, push, Context):
             assert rc == 0 and np.array_equal(c.get_factor(), Lr)
             g = c.get_instance()
             gr = oracle.draw_instance(push, seed, inst=2)
-            assert np.max(np.abs(g - gr)) < 1e-12
+            # same uniforms; the ABI carries the draw ranges in FP32, the oracle in FP64
+            assert np.max(np.abs(g - gr)) < 1e-6
 
 
 @pytest.mark.parametrize("pop", [1, 64, 1000, 65536])
@@ -70,7 +71,7 @@ def test_full_covariance_factor_and_sample_bit_exact(oracle, push, Context):
     w = dict(push, cem=dict(push["cem"], cov_mode="full"))
     A = np.array([[0.5, 0.1, -0.05], [0.1, 0.3, 0.02], [-0.05, 0.02, 0.2]])
     mu = np.array([0.1, -0.2, 0.7])
-    with Context(w, seed=9) as c:
+    with Context(w, seed=9, pop=4096) as c:
         c.set_theta(mu, A)
         Lr, _ = oracle.factor_cov(A)
         L = c.get_factor()
