@@ -33,7 +33,37 @@ class RefScene(ctypes.Structure):
         ("pusher_steps", _i),
         ("goal_rho_lo", _d), ("goal_rho_hi", _d), ("goal_phi_lo", _d), ("goal_phi_hi", _d),
         ("goal_tol", _d), ("time_weight", _d),
+        ("n_joints", _i), ("j_type", _i * 12), ("j_axis", _i * 12), ("j_parent", _i * 12), ("b_collide", _i * 12),
+        ("j_origin", (_d * 3) * 12), ("b_mass", _d * 12), ("b_com", (_d * 3) * 12), ("b_half", (_d * 3) * 12),
+        ("j_inom", _d * 12), ("q0", _d * 12),
+        ("ee_body", _i), ("ee_offset", _d * 3),
+        ("ik_iters", _i), ("omega_c", _d), ("zeta", _d), ("ik_lambda", _d),
+        ("base_vmin", _d), ("base_vmax", _d), ("base_wmax", _d), ("base_tol", _d), ("yaw_tol", _d), ("ee_tol", _d),
+        ("t_approach", _d), ("t_descend", _d), ("t_close", _d), ("t_lift", _d), ("t_transfer", _d),
+        ("t_release", _d), ("timeout_move", _d), ("timeout_pick", _d), ("timeout_place", _d),
+        ("pregrasp", _d), ("finger_open", _d), ("finger_closed", _d), ("rest_speed", _d),
+        ("goal_static", _i), ("joint_speed_max", _d), ("accel_max", _d),
     ]
+
+
+class Tree(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("type", ctypes.c_int * 12), ("axis", ctypes.c_int * 12),
+                ("parent", ctypes.c_int * 12), ("origin", (_d * 3) * 12), ("mass", _d * 12),
+                ("com", (_d * 3) * 12), ("half", (_d * 3) * 12)]
+
+
+def make_tree(joints):
+    """Kinematic tree from a list of joint dicts (type 0 revolute / 1 prismatic, axis 0..5 = +x..-z)."""
+    t = Tree()
+    t.n = len(joints)
+    for j, jd in enumerate(joints):
+        t.type[j], t.axis[j], t.parent[j] = jd["type"], jd["axis"], jd["parent"]
+        t.mass[j] = jd["mass"]
+        for k in range(3):
+            t.origin[j][k] = jd["origin"][k]
+            t.com[j][k] = jd["com"][k]
+            t.half[j][k] = jd["half"][k]
+    return t
 
 
 _lib = None
@@ -66,6 +96,15 @@ def lib():
         L.ref_refit.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int32, vp, vp, vp, vp]
         L.ref_plan_solve.argtypes = [P(RefScene), u64, u32, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.ref_tree_aba.argtypes = [P(Tree), vp, vp, vp, vp, ctypes.c_double, vp]
+        L.ref_tree_rnea.argtypes = [P(Tree), vp, vp, vp, vp, ctypes.c_double, vp]
+        L.ref_tree_crba.argtypes = [P(Tree), vp, vp]
+        L.ref_tree_fk.argtypes = [P(Tree), vp, vp, vp]
+        L.ref_ik.argtypes = [P(RefScene), vp, vp, vp, vp, vp, vp]
+        L.ref_tree_sim.argtypes = [P(Tree), vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp]
+        L.ref_object_sim.argtypes = [P(RefScene), vp, vp, vp, ctypes.c_int, vp]
+        if L.ref_tree_size() != ctypes.sizeof(Tree):
+            raise RuntimeError("oracle Tree layout mismatch")
         L.ref_box_sim.argtypes = [vp, ctypes.c_int, vp]
         L.ref_sphere_box.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
         L.ref_box_box.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -112,9 +151,32 @@ def make_scene(workload):
         s.pusher_vmax, s.pusher_steps = pu["vmax"], pu["steps"]
     go = sc.get("goal")
     if go:
-        s.goal_rho_lo, s.goal_rho_hi = go["rho"]
-        s.goal_phi_lo, s.goal_phi_hi = go["phi"]
+        s.goal_rho_lo, s.goal_rho_hi = go.get("rho", (0.0, 0.0))
+        s.goal_phi_lo, s.goal_phi_hi = go.get("phi", (0.0, 0.0))
         s.goal_tol, s.time_weight = go["tol"], go["time_weight"]
+    rb = sc.get("robot")
+    if rb:
+        J = rb["joints"]
+        s.n_joints = len(J)
+        for j, jd in enumerate(J):
+            s.j_type[j], s.j_axis[j], s.j_parent[j], s.b_collide[j] = jd["type"], jd["axis"], jd["parent"], jd["collide"]
+            s.b_mass[j], s.j_inom[j], s.q0[j] = jd["mass"], jd["inom"], rb["q0"][j]
+            for k in range(3):
+                s.j_origin[j][k] = jd["origin"][k]
+                s.b_com[j][k] = jd["com"][k]
+                s.b_half[j][k] = jd["half"][k]
+        s.ee_body = rb["ee_body"]
+        for k in range(3):
+            s.ee_offset[k] = rb["ee_offset"][k]
+        ct = sc["controller"]
+        s.ik_iters = ct["ik_iters"]
+        for f in ("omega_c", "zeta", "ik_lambda", "base_vmin", "base_vmax", "base_wmax", "base_tol", "yaw_tol",
+                  "ee_tol", "t_approach", "t_descend", "t_close", "t_lift", "t_transfer", "t_release",
+                  "timeout_move", "timeout_pick", "timeout_place", "pregrasp", "finger_open", "finger_closed",
+                  "joint_speed_max", "accel_max"):
+            setattr(s, f, ct[f])
+        s.rest_speed = sc["rest_speed"]
+        s.goal_static = sc["goal_static"]
     return s
 
 
@@ -184,7 +246,7 @@ def rollout(workload, seed, Z, inst=0, trace_steps=0, threads=None):
     cost = np.zeros(pop, np.float64)
     tier = np.zeros(pop, np.uint8)
     pose = np.zeros((pop, 7), np.float64)
-    tw = 13
+    tw = 13 if workload["scene"]["kind"] == "push" else 35
     trace = np.zeros((pop, trace_steps, tw), np.float64) if trace_steps else None
     threads = threads or os.cpu_count() or 1
     rc = lib().ref_rollout(ctypes.byref(s), seed, inst, pop, _ptr(Z), _ptr(cost), _ptr(tier), _ptr(pose),
@@ -285,3 +347,59 @@ def box_box(pA, qA, heA, pB, qB, heB):
     out = np.zeros((8, 7), np.float64)
     n = lib().ref_box_box(*[_ptr(v) for v in a], _ptr(out))
     return out[:n].copy()
+
+
+def _f64(a, n=None):
+    return np.ascontiguousarray(a if a is not None else np.zeros(n), np.float64)
+
+
+def tree_aba(tree, q, qd, tau, fext=None, g=9.81):
+    n = tree.n
+    fx = _f64(fext, (n, 6)) if fext is not None else np.zeros((n, 6))
+    out = np.zeros(n)
+    lib().ref_tree_aba(ctypes.byref(tree), _ptr(_f64(q)), _ptr(_f64(qd)), _ptr(_f64(tau)), _ptr(fx), g, _ptr(out))
+    return out
+
+
+def tree_rnea(tree, q, qd, qdd, fext=None, g=9.81):
+    n = tree.n
+    fx = _f64(fext, (n, 6)) if fext is not None else np.zeros((n, 6))
+    out = np.zeros(n)
+    lib().ref_tree_rnea(ctypes.byref(tree), _ptr(_f64(q)), _ptr(_f64(qd)), _ptr(_f64(qdd)), _ptr(fx), g, _ptr(out))
+    return out
+
+
+def tree_crba(tree, q):
+    M = np.zeros((tree.n, tree.n))
+    lib().ref_tree_crba(ctypes.byref(tree), _ptr(_f64(q)), _ptr(M))
+    return M
+
+
+def tree_fk(tree, q):
+    R = np.zeros((tree.n, 3, 3))
+    p = np.zeros((tree.n, 3))
+    lib().ref_tree_fk(ctypes.byref(tree), _ptr(_f64(q)), _ptr(R), _ptr(p))
+    return R, p
+
+
+def tree_sim(tree, q0, qd0, g, h, n):
+    out = np.zeros((n, 2 * tree.n))
+    lib().ref_tree_sim(ctypes.byref(tree), _ptr(_f64(q0)), _ptr(_f64(qd0)), g, h, n, _ptr(out))
+    return out[:, :tree.n], out[:, tree.n:]
+
+
+def object_sim(workload, p0, q0, v0, n):
+    s = make_scene(workload)
+    out = np.zeros((n, 13))
+    lib().ref_object_sim(ctypes.byref(s), _ptr(_f64(p0)), _ptr(_f64(q0)), _ptr(_f64(v0)), n, _ptr(out))
+    return out
+
+
+def ik(workload, q, pt, Rt):
+    s = make_scene(workload)
+    qo = np.zeros(len(q))
+    pe = np.zeros(3)
+    Re = np.zeros(9)
+    lib().ref_ik(ctypes.byref(s), _ptr(_f64(q)), _ptr(_f64(pt)), _ptr(_f64(np.asarray(Rt).ravel())), _ptr(qo),
+                 _ptr(pe), _ptr(Re))
+    return qo, pe, Re.reshape(3, 3)

@@ -15,6 +15,8 @@
 #include "ref_cem.hpp"
 #include "ref_push.hpp"
 #include "ref_random.hpp"
+#include "ref_robot.hpp"
+#include "ref_spatial.hpp"
 #include "ref_scene.hpp"
 
 namespace ref {
@@ -26,7 +28,8 @@ using namespace ref;
 namespace {
 
 RolloutOut rollout_one(const RefScene &s, const Instance &in, const float *z, double *trace, int trace_steps) {
-  return push_rollout<double>(s, in, z, trace, trace_steps);
+  if (s.kind == SCENE_PUSH) return push_rollout<double>(s, in, z, trace, trace_steps);
+  return robot_rollout<double>(s, in, z, trace, trace_steps);
 }
 
 int param_dim(const RefScene &s) {
@@ -105,8 +108,8 @@ int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const 
                 uint8_t *tier, double *pose, double *trace, int trace_steps, int threads) {
   const int D = param_dim(*s);
   const Instance in = draw_instance(*s, seed, inst);
-  if (s->kind != SCENE_PUSH) return 1;
-  const int tw = TRACE_FREE;
+  if (s->kind != SCENE_PUSH && s->kind != SCENE_PICKPLACE) return 1;
+  const int tw = s->kind == SCENE_PUSH ? TRACE_FREE : TRACE_ROBOT;
   parallel_for(pop, threads, [&](int i) {
     RolloutOut o = rollout_one(*s, in, Z + (long)i * D, trace ? trace + (long)i * trace_steps * tw : nullptr,
                                trace_steps);
@@ -122,7 +125,8 @@ int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const 
 void ref_count_ops(const RefScene *s, uint64_t seed, uint32_t inst, const float *z, uint64_t out[6]) {
   const Instance in = draw_instance(*s, seed, inst);
   g_tally = Tally();
-  push_rollout<Cnt>(*s, in, z, nullptr, 0);
+  if (s->kind == SCENE_PUSH) push_rollout<Cnt>(*s, in, z, nullptr, 0);
+  else robot_rollout<Cnt>(*s, in, z, nullptr, 0);
   out[0] = g_tally.add; out[1] = g_tally.mul; out[2] = g_tally.fma;
   out[3] = g_tally.div; out[4] = g_tally.sqrt; out[5] = g_tally.trans;
 }
@@ -192,6 +196,101 @@ int ref_box_box(const double pA[3], const double qA[4], const double heA[3], con
     o[3] = cs[i].n.x; o[4] = cs[i].n.y; o[5] = cs[i].n.z; o[6] = cs[i].d;
   }
   return n;
+}
+
+// Kinematic-tree probes for the dynamics pins (Tree layout of ref_spatial.hpp).
+int ref_tree_size(void) { return (int)sizeof(Tree); }
+void ref_tree_aba(const Tree *t, const double *q, const double *qd, const double *tau, const double *fext, double g,
+                  double *qdd) {
+  aba(*t, q, qd, tau, (const double(*)[6])fext, g, qdd);
+}
+void ref_tree_rnea(const Tree *t, const double *q, const double *qd, const double *qdd, const double *fext, double g,
+                   double *tau) {
+  rnea(*t, q, qd, qdd, (const double(*)[6])fext, g, tau);
+}
+void ref_tree_crba(const Tree *t, const double *q, double *M) { crba(*t, q, M); }
+// Passive tree (zero joint torque, gravity g): n semi-implicit Euler steps of
+// length h; trace n x 2*n_joints (q, qd after each step).
+void ref_tree_sim(const Tree *t, const double *q0, const double *qd0, double g, double h, int n, double *trace) {
+  double q[MAXJ], qd[MAXJ], tau[MAXJ], qdd[MAXJ];
+  for (int j = 0; j < t->n; ++j) { q[j] = q0[j]; qd[j] = qd0[j]; tau[j] = 0.0; }
+  for (int s = 0; s < n; ++s) {
+    aba(*t, q, qd, tau, (const double(*)[6]) nullptr, g, qdd);
+    for (int j = 0; j < t->n; ++j) {
+      qd[j] = qd[j] + h * qdd[j];
+      q[j] = q[j] + h * qd[j];
+      trace[(long)s * 2 * t->n + j] = q[j];
+      trace[(long)s * 2 * t->n + t->n + j] = qd[j];
+    }
+  }
+}
+// The scene's free object alone (ground and static boxes, no robot) from pose
+// p0 (3) q0 (4) and velocity v0 (3): n substeps of the scene's h; trace n x 13.
+void ref_object_sim(const RefScene *s, const double *p0, const double *q0, const double *v0, int n, double *trace) {
+  const double h = s->dt / (double)s->substeps;
+  const V3<double> he(s->obj_half[0], s->obj_half[1], s->obj_half[2]);
+  const double m = s->obj_mass;
+  const V3<double> Ib(m * (he.y * he.y + he.z * he.z) / 3.0, m * (he.x * he.x + he.z * he.z) / 3.0,
+                      m * (he.x * he.x + he.y * he.y) / 3.0);
+  Body<double> b;
+  b.p = V3<double>(p0[0], p0[1], p0[2]);
+  b.q.w = q0[0]; b.q.x = q0[1]; b.q.y = q0[2]; b.q.z = q0[3];
+  b.v = V3<double>(v0[0], v0[1], v0[2]);
+  for (int st = 0; st < n; ++st) {
+    const M3<double> R = quat_to_mat(b.q);
+    Wrench<double> W;
+    Contact<double> cs[8];
+    auto vel = [&](const V3<double> &x) { return b.v + cross(b.w, x - b.p); };
+    int nc = box_plane(b.p, R, he, cs);
+    for (int i = 0; i < nc; ++i)
+      add_force(W, b.p, cs[i].x, penalty_force(cs[i], vel(cs[i].x), V3<double>(), s->k_contact, s->c_contact, s->mu_ground, s->eps_v));
+    for (int k = 0; k < s->n_static; ++k) {
+      const M3<double> SR = static_rot<double>(*s, k);
+      const V3<double> SP(s->st_center[k][0], s->st_center[k][1], s->st_center[k][2]);
+      const V3<double> SH(s->st_half[k][0], s->st_half[k][1], s->st_half[k][2]);
+      const double mu = s->st_ramp[k] ? s->mu_ramp : s->mu_static;
+      nc = box_verts_in_box(b.p, R, he, SP, SR, SH, cs);
+      for (int i = 0; i < nc; ++i)
+        add_force(W, b.p, cs[i].x, penalty_force(cs[i], vel(cs[i].x), V3<double>(), s->k_contact, s->c_contact, mu, s->eps_v));
+      nc = box_verts_in_box(SP, SR, SH, b.p, R, he, cs);
+      for (int i = 0; i < nc; ++i)
+        add_force(W, b.p, cs[i].x, -penalty_force(cs[i], V3<double>(), vel(cs[i].x), s->k_contact, s->c_contact, mu, s->eps_v));
+    }
+    integrate_free(b, W, m, Ib, V3<double>(0.0, 0.0, -s->gravity), h);
+    double *o = trace + (long)st * 13;
+    o[0] = b.p.x; o[1] = b.p.y; o[2] = b.p.z;
+    o[3] = b.q.w; o[4] = b.q.x; o[5] = b.q.y; o[6] = b.q.z;
+    o[7] = b.v.x; o[8] = b.v.y; o[9] = b.v.z;
+    o[10] = b.w.x; o[11] = b.w.y; o[12] = b.w.z;
+  }
+}
+void ref_tree_fk(const Tree *t, const double *q, double *R, double *p) {
+  M3<double> Rw[MAXJ];
+  V3<double> pw[MAXJ];
+  forward_kinematics(*t, q, Rw, pw);
+  for (int j = 0; j < t->n; ++j) {
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) R[j * 9 + a * 3 + b] = Rw[j].m[a][b];
+    p[j * 3 + 0] = pw[j].x; p[j * 3 + 1] = pw[j].y; p[j * 3 + 2] = pw[j].z;
+  }
+}
+// EE pose after damped-least-squares IK from q (robot scenes): q_out, EE p, R.
+void ref_ik(const RefScene *s, const double *q, const double pt[3], const double Rt[9], double *q_out, double pe[3],
+            double Re[9]) {
+  const Tree tr = tree_of(*s);
+  double qq[MAXJ];
+  for (int j = 0; j < tr.n; ++j) qq[j] = q[j];
+  M3<double> R;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) R.m[a][b] = Rt[a * 3 + b];
+  ik_dls(*s, tr, qq, V3<double>(pt[0], pt[1], pt[2]), R);
+  M3<double> E;
+  V3<double> p;
+  ee_pose(*s, tr, qq, &E, &p);
+  for (int j = 0; j < tr.n; ++j) q_out[j] = qq[j];
+  pe[0] = p.x; pe[1] = p.y; pe[2] = p.z;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Re[a * 3 + b] = E.m[a][b];
 }
 
 int ref_select(int pop, const float *cost, const uint8_t *tier, int n_elite, int32_t *elite_idx, int32_t *mode,

@@ -46,8 +46,8 @@ RolloutOut push_rollout(const RefScene &s, const Instance &inst, const float *z,
   const long push_sub = (long)s.pusher_steps * (long)s.substeps;
 
   Body<T> b;
-  // resting on its four bottom corners: penetration m g / (4 k)
-  b.p = V3<T>(T(s.obj_pos0[0]), T(s.obj_pos0[1]), he.z - m * g / (T(4.0) * k));
+  // resting height minus the penetration m g / (4 k) of four bottom corners
+  b.p = V3<T>(T(s.obj_pos0[0]), T(s.obj_pos0[1]), T(s.obj_pos0[2]) - m * g / (T(4.0) * k));
   const T cy = r_cos(T(0.5 * s.obj_yaw0)), sy = r_sin(T(0.5 * s.obj_yaw0));
   b.q.w = cy; b.q.x = T(0.0); b.q.y = T(0.0); b.q.z = sy;
 

@@ -31,6 +31,22 @@ struct RefScene {
   int32_t pusher_steps;
   // goal: drawn per instance on the scene stream; tolerance and time weight of the cost
   double goal_rho_lo, goal_rho_hi, goal_phi_lo, goal_phi_hi, goal_tol, time_weight;
+  // articulated robot (pick-place, move-push): joints 0-2 base x, y, yaw;
+  // 3-8 arm; 9, 10 fingers.  Tree layout as in ref_spatial.hpp.
+  int32_t n_joints;
+  int32_t j_type[12], j_axis[12], j_parent[12], b_collide[12];
+  double j_origin[12][3], b_mass[12], b_com[12][3], b_half[12][3], j_inom[12], q0[12];
+  int32_t ee_body;
+  double ee_offset[3];
+  // controller constants
+  int32_t ik_iters;
+  double omega_c, zeta, ik_lambda;
+  double base_vmin, base_vmax, base_wmax, base_tol, yaw_tol, ee_tol;
+  double t_approach, t_descend, t_close, t_lift, t_transfer, t_release;
+  double timeout_move, timeout_pick, timeout_place;
+  double pregrasp, finger_open, finger_closed, rest_speed;
+  int32_t goal_static;   // static box whose top face is the goal region
+  double joint_speed_max, accel_max;  // arm reference speed limit; torque limit I_nom * accel_max
 };
 
 // Per-instance draws (scene stream 1, sample 0, iteration 0, instance b):

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(64) rollout_push_kernel(cem_scene sc, const De
   const int push_sub = sc.pusher_steps * sc.substeps;
 
   FreeBody b;
-  b.p = v3(sc.obj_pos0[0], sc.obj_pos0[1], he.z - m * sc.gravity / (4.0f * k));
+  b.p = v3(sc.obj_pos0[0], sc.obj_pos0[1], sc.obj_pos0[2] - m * sc.gravity / (4.0f * k));
   float sy, cy;
   sincosf(0.5f * sc.obj_yaw0, &sy, &cy);
   b.q = Q4f{cy, 0.0f, 0.0f, sy};
