@@ -51,6 +51,8 @@ enum { CEM_SCENE_PUSH = 1, CEM_SCENE_PICKPLACE = 2, CEM_SCENE_MOVEPUSH = 3 };
 #define CEM_MAX_D 16
 #define CEM_STATS_COLS 8
 #define CEM_TRACE_FREE 13
+#define CEM_MAX_JOINTS 12
+#define CEM_TRACE_ROBOT 35   /* object p q v w (13), robot q (11), robot qd (11) */
 
 /* The physical scene and the plan's controllers (Problem 1: state space
  * X = Q x SE(3)^m, dynamics x_{t+1} = f(x_t, c_i, z_i), horizon T).
@@ -70,6 +72,36 @@ typedef struct cem_scene {
   int32_t pusher_steps;         /* control steps the pusher moves                  */
   float goal_rho_lo, goal_rho_hi, goal_phi_lo, goal_phi_hi;  /* seeded goal draw  */
   float goal_tol, time_weight;  /* success radius; weight of the time cost         */
+  /* Articulated mobile manipulator (pick-place, move-push).  Fixed topology:
+   * joints 0, 1, 2 move the base along world x, y and about z (bodies 0, 1
+   * massless); 3..8 a serial arm; 9, 10 the two fingers, children of body 8.
+   * Joint j moves body j relative to body j_parent[j]: its frame sits at
+   * j_origin (parent body frame, no fixed rotation), rotating (type 0) about
+   * or sliding (type 1) along axis 0..5 = +x,+y,+z,-x,-y,-z.  Body j: mass,
+   * COM (body frame), half extents of a solid box about the COM (inertia, and
+   * the collision box of the base and the fingers).  j_inom: nominal inertia
+   * scaling the joint PD gains; q0: initial configuration. */
+  int32_t n_joints;
+  int32_t j_type[CEM_MAX_JOINTS], j_axis[CEM_MAX_JOINTS], j_parent[CEM_MAX_JOINTS];
+  float j_origin[CEM_MAX_JOINTS][3], b_mass[CEM_MAX_JOINTS], b_com[CEM_MAX_JOINTS][3];
+  float b_half[CEM_MAX_JOINTS][3], j_inom[CEM_MAX_JOINTS], q0[CEM_MAX_JOINTS];
+  int32_t ee_body;              /* end-effector body and offset of the EE point   */
+  float ee_offset[3];
+  /* controllers: joint PD tau = inom (omega_c^2 e - 2 zeta omega_c qd),
+   * |tau| <= inom * accel_max; DLS IK (ik_iters steps, damping ik_lambda);
+   * base speed clamp [base_vmin, base_vmax], yaw rate base_wmax; success
+   * tolerances; phase durations (s) stretched so no arm reference moves
+   * faster than joint_speed_max; action timeouts (s); pre-grasp distance;
+   * finger open / closed targets; goal table (static box index) and the
+   * object speed below which it is at rest. */
+  int32_t ik_iters;
+  float omega_c, zeta, ik_lambda;
+  float base_vmin, base_vmax, base_wmax, base_tol, yaw_tol, ee_tol;
+  float t_approach, t_descend, t_close, t_lift, t_transfer, t_release;
+  float timeout_move, timeout_pick, timeout_place;
+  float pregrasp, finger_open, finger_closed, rest_speed;
+  int32_t goal_static;
+  float joint_speed_max, accel_max;
 } cem_scene;
 
 /* One CE problem (Alg. 1 inputs).  mu0 has D entries, cov0 D x D row-major

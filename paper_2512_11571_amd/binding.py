@@ -20,8 +20,14 @@ SCENE_KIND = {"push": 1, "pickplace": 2, "movepush": 3}
 DIM = {"push": 3, "pickplace": 16, "movepush": 12}
 MAX_STATIC = 8
 MAX_D = 16
+MAX_JOINTS = 12
 STATS_COLS = 8
 TRACE_FREE = 13
+TRACE_ROBOT = 35
+CONTROLLER_FIELDS = ("omega_c", "zeta", "ik_lambda", "base_vmin", "base_vmax", "base_wmax", "base_tol", "yaw_tol",
+                     "ee_tol", "t_approach", "t_descend", "t_close", "t_lift", "t_transfer", "t_release",
+                     "timeout_move", "timeout_pick", "timeout_place", "pregrasp", "finger_open", "finger_closed",
+                     "joint_speed_max", "accel_max")
 
 _f = ctypes.c_float
 _i = ctypes.c_int32
@@ -40,6 +46,16 @@ class CemScene(ctypes.Structure):
         ("pusher_steps", _i),
         ("goal_rho_lo", _f), ("goal_rho_hi", _f), ("goal_phi_lo", _f), ("goal_phi_hi", _f),
         ("goal_tol", _f), ("time_weight", _f),
+        ("n_joints", _i), ("j_type", _i * MAX_JOINTS), ("j_axis", _i * MAX_JOINTS), ("j_parent", _i * MAX_JOINTS),
+        ("j_origin", (_f * 3) * MAX_JOINTS), ("b_mass", _f * MAX_JOINTS), ("b_com", (_f * 3) * MAX_JOINTS),
+        ("b_half", (_f * 3) * MAX_JOINTS), ("j_inom", _f * MAX_JOINTS), ("q0", _f * MAX_JOINTS),
+        ("ee_body", _i), ("ee_offset", _f * 3),
+        ("ik_iters", _i), ("omega_c", _f), ("zeta", _f), ("ik_lambda", _f),
+        ("base_vmin", _f), ("base_vmax", _f), ("base_wmax", _f), ("base_tol", _f), ("yaw_tol", _f), ("ee_tol", _f),
+        ("t_approach", _f), ("t_descend", _f), ("t_close", _f), ("t_lift", _f), ("t_transfer", _f),
+        ("t_release", _f), ("timeout_move", _f), ("timeout_pick", _f), ("timeout_place", _f),
+        ("pregrasp", _f), ("finger_open", _f), ("finger_closed", _f), ("rest_speed", _f),
+        ("goal_static", _i), ("joint_speed_max", _f), ("accel_max", _f),
     ]
 
 
@@ -136,9 +152,31 @@ def make_scene(workload):
         s.pusher_vmax, s.pusher_steps = pu["vmax"], pu["steps"]
     go = sc.get("goal")
     if go:
-        s.goal_rho_lo, s.goal_rho_hi = go["rho"]
-        s.goal_phi_lo, s.goal_phi_hi = go["phi"]
+        s.goal_rho_lo, s.goal_rho_hi = go.get("rho", (0.0, 0.0))
+        s.goal_phi_lo, s.goal_phi_hi = go.get("phi", (0.0, 0.0))
         s.goal_tol, s.time_weight = go["tol"], go["time_weight"]
+    rb = sc.get("robot")
+    if rb:
+        J = rb["joints"]
+        if len(J) > MAX_JOINTS:
+            raise ValueError("at most %d joints" % MAX_JOINTS)
+        s.n_joints = len(J)
+        for j, jd in enumerate(J):
+            s.j_type[j], s.j_axis[j], s.j_parent[j] = jd["type"], jd["axis"], jd["parent"]
+            s.b_mass[j], s.j_inom[j], s.q0[j] = jd["mass"], jd["inom"], rb["q0"][j]
+            for k in range(3):
+                s.j_origin[j][k] = jd["origin"][k]
+                s.b_com[j][k] = jd["com"][k]
+                s.b_half[j][k] = jd["half"][k]
+        s.ee_body = rb["ee_body"]
+        for k in range(3):
+            s.ee_offset[k] = rb["ee_offset"][k]
+        ct = sc["controller"]
+        s.ik_iters = ct["ik_iters"]
+        for f in CONTROLLER_FIELDS:
+            setattr(s, f, ct[f])
+        s.rest_speed = sc["rest_speed"]
+        s.goal_static = sc["goal_static"]
     return s
 
 

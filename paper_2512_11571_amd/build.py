@@ -23,6 +23,7 @@ SOURCES = {
     "sampler.hip": ["-ffp-contract=off"],
     "select_refit.hip": ["-ffp-contract=off"],
     "rollout_push.hip": [],
+    "rollout_robot.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

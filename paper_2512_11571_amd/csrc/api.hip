@@ -58,7 +58,7 @@ bool nonneg(float x) { return std::isfinite(x) && x >= 0.0f; }
 
 const char *check_scene(const cem_scene &s) {
   if (dim_of(s.kind) == 0) return "unknown scene kind";
-  if (s.kind != CEM_SCENE_PUSH) return "scene kind not supported by this build";
+  if (s.kind == CEM_SCENE_MOVEPUSH) return "scene kind not supported by this build";
   if (s.substeps < 1 || s.substeps > 1000) return "substeps out of range [1, 1000]";
   if (s.horizon < 1 || s.horizon > 100000) return "horizon out of range [1, 100000]";
   if (!pos(s.dt) || !nonneg(s.gravity) || !nonneg(s.k_contact) || !nonneg(s.c_contact) || !pos(s.eps_v))
@@ -73,6 +73,29 @@ const char *check_scene(const cem_scene &s) {
     if (!nonneg(s.goal_tol) || !nonneg(s.time_weight)) return "invalid goal tolerance or time weight";
     if (!(s.goal_rho_lo <= s.goal_rho_hi) || !(s.goal_phi_lo <= s.goal_phi_hi)) return "invalid goal ranges";
   }
+  if (s.kind == CEM_SCENE_PICKPLACE) {
+    // the kernels unroll the fixed tree: base x, y, yaw; a serial arm 3..8; fingers 9, 10 on body 8
+    if (s.n_joints != 11) return "robot must have 11 joints";
+    for (int j = 0; j < 11; ++j) {
+      const int want = j == 0 ? -1 : (j <= 8 ? j - 1 : 8);
+      if (s.j_parent[j] != want) return "robot topology differs from base(3) + arm(6) + fingers(2)";
+      if (s.j_type[j] != 0 && s.j_type[j] != 1) return "joint type must be 0 or 1";
+      if (s.j_axis[j] < 0 || s.j_axis[j] > 5) return "joint axis must be 0..5";
+      if (!nonneg(s.b_mass[j]) || !nonneg(s.j_inom[j]) || !std::isfinite(s.q0[j])) return "invalid body";
+    }
+    if (s.j_type[0] != 1 || s.j_type[1] != 1 || s.j_type[9] != 1 || s.j_type[10] != 1)
+      return "base x, y and the fingers must be prismatic";
+    if (s.ee_body != 8) return "end effector must be body 8";
+    if (s.ik_iters < 0 || s.ik_iters > 1000 || !pos(s.ik_lambda) || !pos(s.omega_c) || !nonneg(s.zeta))
+      return "invalid controller gains";
+    if (!pos(s.base_vmin) || !(s.base_vmax >= s.base_vmin) || !pos(s.base_wmax) || !pos(s.joint_speed_max) ||
+        !pos(s.accel_max))
+      return "invalid speed limits";
+    if (!pos(s.t_approach) || !pos(s.t_descend) || !nonneg(s.t_close) || !pos(s.t_lift) || !pos(s.t_transfer) ||
+        !nonneg(s.t_release))
+      return "invalid phase durations";
+    if (s.goal_static < 0 || s.goal_static >= s.n_static) return "goal_static must index a static box";
+  }
   return nullptr;
 }
 
@@ -82,6 +105,9 @@ int launch_rollout(cem_ctx *c, const float *Z, int pop, float *cost, uint8_t *ti
   switch (c->scene.kind) {
     case CEM_SCENE_PUSH:
       e = launch_rollout_push(c->scene, c->st, Z, pop, cost, tier, pose, trace, trace_steps, s);
+      break;
+    case CEM_SCENE_PICKPLACE:
+      e = launch_rollout_pickplace(c->scene, Z, pop, cost, tier, pose, trace, trace_steps, s);
       break;
     default:
       return fail(c, CEM_E_SCENE, "scene kind not supported by this build");

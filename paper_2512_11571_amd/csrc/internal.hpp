@@ -36,6 +36,8 @@ hipError_t launch_factor(DevState *st, hipStream_t s);
 hipError_t launch_select_refit(DevState *st, const float *Z, const float *cost, const uint8_t *tier, int pop,
                                int32_t *elite_idx, int32_t *sel_info, float *stats, int stats_cap,
                                int advance_iter, hipStream_t s);
+hipError_t launch_rollout_pickplace(const cem_scene &sc, const float *Z, int pop, float *cost, uint8_t *tier,
+                                    float *pose, float *trace, int trace_steps, hipStream_t s);
 hipError_t launch_rollout_push(const cem_scene &sc, const DevState *st, const float *Z, int pop, float *cost,
                                uint8_t *tier, float *pose, float *trace, int trace_steps, hipStream_t s);
 
