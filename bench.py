@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks: FP32 vector (packed) 157.3 TFLOP/s, HBM3E 8 TB/s.
 PEAK_FP32_TFLOPS = 157.3
-DEFAULT_WORKLOAD = "push"
+DEFAULT_WORKLOAD = "pickplace"
 
 # HBM traffic per rollout launch measured with rocprofv3 (FETCH_SIZE + WRITE_SIZE,
 # scaled by the copy-kernel calibration), keyed by workload; valid only while
@@ -30,6 +30,7 @@ MEASURED_TRAFFIC = {}
 
 ROLLOUT_SOURCES = {
     "push": ["rollout_push.hip", "rigid.hpp", "devmath.hpp"],
+    "pickplace": ["rollout_robot.hip", "rigid.hpp", "devmath.hpp"],
 }
 
 

@@ -227,6 +227,14 @@ inline int sphere_box(const V3<T> &c, T r, const V3<T> &p, const M3<T> &R, const
   return 1;
 }
 
+// Broadphase: boxes A and B (half extents ha, hb) can only touch when their
+// bounding spheres (radius = half diagonal) overlap.
+template <class T> inline bool spheres_overlap(const V3<T> &pa, const V3<T> &ha, const V3<T> &pb, const V3<T> &hb) {
+  const V3<T> d = pa - pb;
+  const T r = r_sqrt(dot(ha, ha)) + r_sqrt(dot(hb, hb));
+  return dot(d, d) <= r * r;
+}
+
 // Vertex-face test of box A's vertices against box B (both dynamic or B static):
 // every vertex of A strictly inside B is a contact with depth = distance to
 // B's nearest face and n = that face's outward normal (from B into A).

@@ -367,6 +367,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       // object against static boxes, both ways
       for (int b = 0; b < s.n_static; ++b) {
         const T mu = T(s.st_ramp[b] ? s.mu_ramp : s.mu_static);
+        if (!spheres_overlap(ob.p, ohe, SP[b], SH[b])) continue;
         nc = box_verts_in_box(ob.p, oR, ohe, SP[b], SR[b], SH[b], cs);
         for (int i = 0; i < nc; ++i)
           add_force(W, ob.p, cs[i].x, penalty_force(cs[i], obj_vel(cs[i].x), V3<T>(), k, damp, mu, eps_v));
@@ -381,14 +382,15 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
         const V3<T> fc = pw[j] + mul(Rw[j], V3<T>(T(s.b_com[j][0]), T(s.b_com[j][1]), T(s.b_com[j][2])));
         const V3<T> fh(T(s.b_half[j][0]), T(s.b_half[j][1]), T(s.b_half[j][2]));
         bool any = false;
-        nc = box_verts_in_box(fc, Rw[j], fh, ob.p, oR, ohe, cs);
+        const bool nearf = spheres_overlap(fc, fh, ob.p, ohe);
+        nc = nearf ? box_verts_in_box(fc, Rw[j], fh, ob.p, oR, ohe, cs) : 0;
         for (int i = 0; i < nc; ++i) {
           const V3<T> F = penalty_force(cs[i], link_vel(j, cs[i].x), obj_vel(cs[i].x), k, damp, T(s.mu_tool), eps_v);
           link_force(j, cs[i].x, F);
           add_force(W, ob.p, cs[i].x, -F);
           any = true;
         }
-        nc = box_verts_in_box(ob.p, oR, ohe, fc, Rw[j], fh, cs);
+        nc = nearf ? box_verts_in_box(ob.p, oR, ohe, fc, Rw[j], fh, cs) : 0;
         for (int i = 0; i < nc; ++i) {
           const V3<T> F = penalty_force(cs[i], obj_vel(cs[i].x), link_vel(j, cs[i].x), k, damp, T(s.mu_tool), eps_v);
           add_force(W, ob.p, cs[i].x, F);
@@ -403,6 +405,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
         const V3<T> bc = pw[j] + mul(Rw[j], V3<T>(T(s.b_com[j][0]), T(s.b_com[j][1]), T(s.b_com[j][2])));
         const V3<T> bh(T(s.b_half[j][0]), T(s.b_half[j][1]), T(s.b_half[j][2]));
         for (int b = 0; b < s.n_static; ++b) {
+          if (!spheres_overlap(bc, bh, SP[b], SH[b])) continue;
           nc = box_verts_in_box(bc, Rw[j], bh, SP[b], SR[b], SH[b], cs);
           for (int i = 0; i < nc; ++i)
             link_force(j, cs[i].x, penalty_force(cs[i], link_vel(j, cs[i].x), V3<T>(), k, damp, T(s.mu_static), eps_v));

@@ -107,7 +107,7 @@ int launch_rollout(cem_ctx *c, const float *Z, int pop, float *cost, uint8_t *ti
       e = launch_rollout_push(c->scene, c->st, Z, pop, cost, tier, pose, trace, trace_steps, s);
       break;
     case CEM_SCENE_PICKPLACE:
-      e = launch_rollout_pickplace(c->scene, Z, pop, cost, tier, pose, trace, trace_steps, s);
+      e = launch_rollout_pickplace(&c->st->scene, Z, pop, cost, tier, pose, trace, trace_steps, s);
       break;
     default:
       return fail(c, CEM_E_SCENE, "scene kind not supported by this build");
@@ -241,6 +241,7 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
     h.n_elite = p->n_elite;
     h.best_cost = INFINITY;
     h.best_tier = 4;
+    h.scene = c->scene;
     if (hipMemcpyAsync(c->st, &h, sizeof h, hipMemcpyHostToDevice, c->own) != hipSuccess) {
       rc = fail(c, CEM_E_HIP, "state upload");
       break;

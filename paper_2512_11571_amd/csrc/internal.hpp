@@ -26,6 +26,7 @@ struct DevState {
   int32_t best_tier;
   int32_t factor_status;       // 0 ok, 1 diagonal fallback used
   int32_t sel_info[6];         // n_e, mode, n_tier0..3 of the last refit
+  cem_scene scene;             // device copy of the scene (read by the rollout kernels)
 };
 
 // Launchers (each file owns its kernels).
@@ -36,7 +37,7 @@ hipError_t launch_factor(DevState *st, hipStream_t s);
 hipError_t launch_select_refit(DevState *st, const float *Z, const float *cost, const uint8_t *tier, int pop,
                                int32_t *elite_idx, int32_t *sel_info, float *stats, int stats_cap,
                                int advance_iter, hipStream_t s);
-hipError_t launch_rollout_pickplace(const cem_scene &sc, const float *Z, int pop, float *cost, uint8_t *tier,
+hipError_t launch_rollout_pickplace(const cem_scene *sc_dev, const float *Z, int pop, float *cost, uint8_t *tier,
                                     float *pose, float *trace, int trace_steps, hipStream_t s);
 hipError_t launch_rollout_push(const cem_scene &sc, const DevState *st, const float *Z, int pop, float *cost,
                                uint8_t *tier, float *pose, float *trace, int trace_steps, hipStream_t s);

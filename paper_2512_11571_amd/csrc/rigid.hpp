@@ -67,14 +67,20 @@ __device__ __forceinline__ void sphere_on_box(const FreeBody &b, const M3f &R, V
     xb = cp;
   } else {
     // nearest face, order +x -x +y -y +z -z, first on ties
-    float ds[6] = {he.x - cb.x, he.x + cb.x, he.y - cb.y, he.y + cb.y, he.z - cb.z, he.z + cb.z};
+    const float ds[6] = {he.x - cb.x, he.x + cb.x, he.y - cb.y, he.y + cb.y, he.z - cb.z, he.z + cb.z};
     int f = 0;
-    for (int j = 1; j < 6; ++j) f = ds[j] < ds[f] ? j : f;
+    float dmin = ds[0];
+#pragma unroll
+    for (int j = 1; j < 6; ++j) {
+      const bool lt = ds[j] < dmin;
+      f = lt ? j : f;
+      dmin = lt ? ds[j] : dmin;
+    }
     const float sgn = (f & 1) ? -1.0f : 1.0f;
     const int ax = f >> 1;
     nb = v3(ax == 0 ? -sgn : 0.0f, ax == 1 ? -sgn : 0.0f, ax == 2 ? -sgn : 0.0f);
     xb = v3(ax == 0 ? sgn * he.x : cb.x, ax == 1 ? sgn * he.y : cb.y, ax == 2 ? sgn * he.z : cb.z);
-    depth = rad + ds[f];
+    depth = rad + dmin;
   }
   const V3f r = mul(R, xb);
   const V3f n = mul(R, nb);
