@@ -64,7 +64,62 @@ def cpu_baseline(w, seed, budget_s):
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
             "sample": "%d x %d rollouts of %d iteration-0 samples (full horizon %d steps), %.1f s"
-                      % (reps, n, n, H, dt)}
+                      % (reps, n, n, H, dt), "env_steps": done, "seconds": dt}
+
+
+def bench_batch(a):
+    """The batched workload: all instances, one CE iteration per step (graph replay)."""
+    import numpy as np
+    import torch
+    from paper_2512_11571_amd import workloads
+    from paper_2512_11571_amd.binding import Batch
+
+    insts = workloads.batch_instances()
+    K = a.steps if a.steps is not None else 3
+    cap = min(i["iters"] for i in insts)
+    if K > cap:
+        raise SystemExit("--steps must be <= %d so that every instance runs in every timed step" % cap)
+    torch.cuda.set_device(0)
+    with Batch(insts) as B:          # warm-up on a batch of its own
+        for _ in range(a.warmup):
+            B.step()
+        torch.cuda.synchronize()
+    with Batch(insts) as B:
+        tune = B.autotune()           # untimed; also the rollout pass duration (HIP events on its stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.solve(K)
+        elapsed = time.perf_counter() - t0
+    env_steps_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"] for i in insts)
+    fps = {k: workloads.load(k).get("measurement", {}).get("flops_per_env_step") for k in ("push", "pickplace")}
+    flops_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"]
+                     * (fps[i["workload"]["scene"]["kind"]] or 0.0) for i in insts)
+    roll_s = tune["rollout_us"] / 1e6
+    achieved = flops_iter / roll_s / 1e12 if roll_s > 0 else None
+    out = {
+        "metric": "env-steps/s (CE iterations/s alongside)",
+        "value": env_steps_iter * K / elapsed,
+        "unit": "env-steps/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
+        "ms_per_step": elapsed / K * 1e3, "cem_iters_per_s": K / elapsed,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (FP64 refit and Cholesky)", "data": "synthetic (seeded instances, scenes and Philox samples)",
+        "config": {"workload": "batch", "instances": len(insts), "env_steps_per_iter": env_steps_iter,
+                   "autotune": tune},
+        "rollout_kernel_ms": roll_s * 1e3,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": None,
+                     "flops_per_env_step": fps},
+    }
+    if not a.no_cpu_baseline:
+        per_kind = []
+        for k in ("push", "pickplace"):
+            w = next(i["workload"] for i in insts if i["workload"]["scene"]["kind"] == k)
+            per_kind.append(cpu_baseline(w, a.seed, a.cpu_seconds / 2))
+        tot_t = sum(p["seconds"] for p in per_kind)
+        steps = sum(p["env_steps"] for p in per_kind)
+        out["cpu_baseline"] = {"value": steps / tot_t, "unit": "env-steps/s", "cores": per_kind[0]["cores"],
+                               "kind": "oracle", "sample": "; ".join(p["sample"] for p in per_kind)}
+    print(json.dumps(out))
 
 
 def main():
@@ -81,6 +136,10 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own "
               "share of the population independently); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if a.workload == "batch":
+        bench_batch(a)
+        return
 
     import torch
     from paper_2512_11571_amd import workloads

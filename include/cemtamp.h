@@ -189,6 +189,32 @@ int cem_get_instance(cem_ctx *c, double *goal_xy);
 /* Reset the best-so-far record and the iteration counter. Synchronous. */
 int cem_reset(cem_ctx *c);
 
+/* ---- Many task instances in one launch ------------------------------------
+ * n independent CE problems (each its own scene kind, population, horizon,
+ * seed and instance id) iterated together: every CE iteration is one captured
+ * graph of a batched sampling launch, ONE persistent rollout launch whose
+ * workgroups pull (instance, 64-environment chunk) items, most expensive
+ * first, from an atomic queue, and one refit workgroup per instance.
+ * Instances stop at their own iteration cap iters[b].  Results per instance
+ * are the same bits as running that instance alone with plan_solve. */
+typedef struct cem_batch cem_batch;
+/* problems[n], iters[n] (host, copied).  Synchronous.  *out NULL on failure. */
+int cem_batch_init(const cem_problem *problems, const int32_t *iters, int32_t n, cem_batch **out);
+void cem_batch_free(cem_batch *b);
+int cem_batch_size(const cem_batch *b);
+const char *cem_batch_last_error(const cem_batch *b);
+/* The context of instance i (owned by the batch: theta, factor, instance draws). */
+cem_ctx *cem_batch_instance(cem_batch *b, int32_t i);
+/* Times one rollout pass for each persistent grid (1, 2, 4 workgroups per CU)
+ * and work-item size (64 or 32 environments) and keeps the fastest.
+ * config_out (nullable, 3 ints): grid, environments per item, microseconds of
+ * that pass.  Leaves the CE state untouched.  Synchronous. */
+int cem_batch_autotune(cem_batch *b, int32_t *config_out);
+/* One CE iteration of every instance under its cap, asynchronous on stream. */
+int cem_batch_step(cem_batch *b, void *stream);
+/* iters iterations, then results[n] (host) for every instance.  Synchronous. */
+int cem_batch_solve(cem_batch *b, int32_t iters, cem_result *results, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

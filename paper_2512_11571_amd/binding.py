@@ -77,7 +77,8 @@ class CemResult(ctypes.Structure):
 
 EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem_last_error", "cem_sample", "rollout_batch",
            "rollout_trace", "cem_refit", "plan_solve", "cem_get_theta", "cem_set_theta", "cem_get_factor",
-           "cem_get_instance", "cem_reset"]
+           "cem_get_instance", "cem_reset", "cem_batch_init", "cem_batch_free", "cem_batch_size",
+           "cem_batch_last_error", "cem_batch_instance", "cem_batch_autotune", "cem_batch_step", "cem_batch_solve"]
 
 _lib = None
 
@@ -109,6 +110,17 @@ def lib():
         L.cem_get_instance.argtypes = [vp, vp]
         L.cem_reset.argtypes = [vp]
         L.cem_sizeof.argtypes = [ctypes.c_int]
+        L.cem_batch_init.argtypes = [vp, vp, _i, P(vp)]
+        L.cem_batch_free.argtypes = [vp]
+        L.cem_batch_free.restype = None
+        L.cem_batch_size.argtypes = [vp]
+        L.cem_batch_last_error.argtypes = [vp]
+        L.cem_batch_last_error.restype = ctypes.c_char_p
+        L.cem_batch_instance.argtypes = [vp, _i]
+        L.cem_batch_instance.restype = vp
+        L.cem_batch_autotune.argtypes = [vp, vp]
+        L.cem_batch_step.argtypes = [vp, vp]
+        L.cem_batch_solve.argtypes = [vp, _i, vp, vp]
         for which, st in enumerate((CemScene, CemProblem, CemResult)):
             if L.cem_sizeof(which) != ctypes.sizeof(st):
                 raise RuntimeError("ABI struct layout mismatch for %s" % st.__name__)
@@ -201,33 +213,48 @@ def _np_ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def make_problem(workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None, cov0=None):
+    """(cem_problem, keep-alive list) for a workload dict."""
+    cem = workload["cem"]
+    scene = make_scene(workload)
+    mu0 = np.ascontiguousarray(mu0 if mu0 is not None else cem["mu0"], np.float64)
+    if cov0 is None:
+        cov0 = np.diag(np.asarray(cem["cov0_diag"], np.float64))
+    cov0 = np.ascontiguousarray(cov0, np.float64)
+    p = CemProblem()
+    p.scene = ctypes.pointer(scene)
+    p.pop = int(pop if pop is not None else cem["pop"])
+    p.n_elite = int(n_elite if n_elite is not None else cem["n_elite"])
+    p.cov_mode = 0 if cem["cov_mode"] == "diag" else 1
+    p.mu0 = mu0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.cov0 = cov0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.seed, p.instance = int(seed), int(instance)
+    return p, [scene, mu0, cov0]
+
+
+def _result_dict(res, D):
+    return dict(best_z=np.array(res.best_z[:D], np.float32), best_cost=float(res.best_cost),
+                best_tier=int(res.best_tier), iters_done=int(res.iters_done),
+                mu=np.array(res.mu[:D]), cov=np.array(res.cov[:D * D]).reshape(D, D))
+
+
 class Context:
     """One CE problem on the current device (wraps cem_ctx*)."""
 
-    def __init__(self, workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None, cov0=None):
-        cem = workload["cem"]
+    def __init__(self, workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None, cov0=None, handle=None):
         self.workload = workload
         self.kind = workload["scene"]["kind"]
         self.D = DIM[self.kind]
-        self.pop = int(pop if pop is not None else cem["pop"])
-        self.n_elite = int(n_elite if n_elite is not None else cem["n_elite"])
-        self.cov_mode = 0 if cem["cov_mode"] == "diag" else 1
-        self._scene = make_scene(workload)
-        self._mu0 = np.ascontiguousarray(mu0 if mu0 is not None else cem["mu0"], np.float64)
-        if cov0 is None:
-            cov0 = np.diag(np.asarray(cem["cov0_diag"], np.float64))
-        self._cov0 = np.ascontiguousarray(cov0, np.float64)
-        p = CemProblem()
-        p.scene = ctypes.pointer(self._scene)
-        p.pop, p.n_elite, p.cov_mode = self.pop, self.n_elite, self.cov_mode
-        p.mu0 = self._mu0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        p.cov0 = self._cov0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        p.seed, p.instance = int(seed), int(instance)
+        if handle is not None:          # borrowed from a batch, which owns it
+            self.h, self._owned = handle, False
+            return
+        p, self._keep = make_problem(workload, seed, instance, pop, n_elite, mu0, cov0)
+        self.pop, self.n_elite = p.pop, p.n_elite
         h = ctypes.c_void_p()
         rc = lib().cem_init(ctypes.byref(p), ctypes.byref(h))
         if rc != CEM_OK:
             raise CemError(rc, lib().cem_strerror(rc).decode())
-        self.h = h
+        self.h, self._owned = h, True
 
     def _check(self, rc):
         if rc != CEM_OK:
@@ -235,7 +262,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().cem_free(self.h)
+            if getattr(self, "_owned", False):
+                lib().cem_free(self.h)
             self.h = None
 
     def __del__(self):
@@ -270,10 +298,9 @@ class Context:
         stats = np.zeros((max(iters, 1), STATS_COLS), np.float32)
         s = _stream(stream) if stream is not None else None
         self._check(lib().plan_solve(self.h, int(iters), ctypes.byref(res), _np_ptr(stats), s))
-        D = self.D
-        return dict(best_z=np.array(res.best_z[:D], np.float32), best_cost=float(res.best_cost),
-                    best_tier=int(res.best_tier), iters_done=int(res.iters_done),
-                    mu=np.array(res.mu[:D]), cov=np.array(res.cov[:D * D]).reshape(D, D), stats=stats[:iters])
+        out = _result_dict(res, self.D)
+        out["stats"] = stats[:iters]
+        return out
 
     def get_theta(self):
         mu = np.zeros(self.D)
@@ -298,3 +325,65 @@ class Context:
 
     def reset(self):
         self._check(lib().cem_reset(self.h))
+
+
+class Batch:
+    """Many independent CE problems iterated together (wraps cem_batch*).
+
+    instances: list of dicts {"workload", "seed", "instance", "iters"}."""
+
+    def __init__(self, instances):
+        self.instances = instances
+        n = len(instances)
+        probs = (CemProblem * n)()
+        self._keep = []
+        for i, inst in enumerate(instances):
+            p, keep = make_problem(inst["workload"], inst["seed"], inst["instance"])
+            probs[i] = p
+            self._keep.append(keep)
+        self._probs = probs
+        iters = np.ascontiguousarray([inst["iters"] for inst in instances], np.int32)
+        h = ctypes.c_void_p()
+        rc = lib().cem_batch_init(probs, _np_ptr(iters), n, ctypes.byref(h))
+        if rc != CEM_OK:
+            raise CemError(rc, lib().cem_strerror(rc).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != CEM_OK:
+            raise CemError(rc, lib().cem_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cem_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def instance(self, i):
+        """Borrowed Context view of instance i (theta, factor, instance draws)."""
+        return Context(self.instances[i]["workload"], handle=lib().cem_batch_instance(self.h, i))
+
+    def autotune(self):
+        cfg = np.zeros(3, np.int32)
+        self._check(lib().cem_batch_autotune(self.h, _np_ptr(cfg)))
+        return dict(grid=int(cfg[0]), envs_per_item=int(cfg[1]), rollout_us=int(cfg[2]))
+
+    def step(self, stream=None):
+        self._check(lib().cem_batch_step(self.h, _stream(stream) if stream is not None else None))
+
+    def solve(self, iters, stream=None):
+        n = len(self.instances)
+        res = (CemResult * n)()
+        self._check(lib().cem_batch_solve(self.h, int(iters), res, _stream(stream) if stream is not None else None))
+        return [_result_dict(res[i], DIM[self.instances[i]["workload"]["scene"]["kind"]]) for i in range(n)]

@@ -22,8 +22,7 @@ SOURCES = {
     "api.hip": [],
     "sampler.hip": ["-ffp-contract=off"],
     "select_refit.hip": ["-ffp-contract=off"],
-    "rollout_push.hip": [],
-    "rollout_robot.hip": [],
+    "rollout.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

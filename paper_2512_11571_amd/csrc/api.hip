@@ -3,11 +3,13 @@
 // method runs in the kernels of the other translation units.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -99,19 +101,24 @@ const char *check_scene(const cem_scene &s) {
   return nullptr;
 }
 
+InstDesc desc_of(cem_ctx *c, const float *Z, int pop, float *cost, uint8_t *tier, float *pose) {
+  InstDesc d{};
+  d.st = c->st;
+  d.Z = Z;
+  d.cost = cost;
+  d.tier = tier;
+  d.pose = pose;
+  d.stats = c->stats;
+  d.kind = c->scene.kind;
+  d.pop = pop;
+  d.D = c->D;
+  d.iters = 1 << 30;
+  return d;
+}
+
 int launch_rollout(cem_ctx *c, const float *Z, int pop, float *cost, uint8_t *tier, float *pose, float *trace,
                    int trace_steps, hipStream_t s) {
-  hipError_t e = hipSuccess;
-  switch (c->scene.kind) {
-    case CEM_SCENE_PUSH:
-      e = launch_rollout_push(c->scene, c->st, Z, pop, cost, tier, pose, trace, trace_steps, s);
-      break;
-    case CEM_SCENE_PICKPLACE:
-      e = launch_rollout_pickplace(&c->st->scene, Z, pop, cost, tier, pose, trace, trace_steps, s);
-      break;
-    default:
-      return fail(c, CEM_E_SCENE, "scene kind not supported by this build");
-  }
+  const hipError_t e = launch_rollout_single(desc_of(c, Z, pop, cost, tier, pose), trace, trace_steps, s);
   if (e != hipSuccess) return hip_fail(c, e, "rollout launch");
   return CEM_OK;
 }
@@ -241,6 +248,9 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
     h.n_elite = p->n_elite;
     h.best_cost = INFINITY;
     h.best_tier = 4;
+    h.seed = c->seed;
+    h.inst_id = c->inst;
+    h.pop = c->pop;
     h.scene = c->scene;
     if (hipMemcpyAsync(c->st, &h, sizeof h, hipMemcpyHostToDevice, c->own) != hipSuccess) {
       rc = fail(c, CEM_E_HIP, "state upload");
@@ -392,6 +402,246 @@ int cem_reset(cem_ctx *c) {
   if (!c) return CEM_E_ARG;
   HIPCHK(c, hipDeviceSynchronize());
   return reset_best(c, c->own);
+}
+
+}  // extern "C"
+
+// ---- batched instances -------------------------------------------------------
+
+struct cem_batch {
+  std::vector<cem_ctx *> ctx;
+  std::vector<int32_t> iters;
+  InstDesc *insts = nullptr;
+  WorkItem *items = nullptr;
+  int n_items = 0, max_pop = 0, item_envs = 64, grid = 0, n_cu = 0;
+  int *queue = nullptr;
+  hipStream_t own = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int bfail(cem_batch *b, int code, const std::string &msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+#define BHIPCHK(b, expr)                                                                        \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) return bfail(b, CEM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Work list: every instance cut into items of `envs` environments, the most
+// expensive first (horizon x substeps x a per-substep weight of the scene kind),
+// so the long items start early and the short ones fill in behind them.
+int build_items(cem_batch *b, int envs) {
+  struct Key {
+    double cost;
+    WorkItem w;
+  };
+  std::vector<Key> keys;
+  for (int i = 0; i < (int)b->ctx.size(); ++i) {
+    const cem_ctx *c = b->ctx[i];
+    const double weight = c->scene.kind == CEM_SCENE_PUSH ? 1.0 : 28.0;
+    const double per_env = (double)c->scene.horizon * c->scene.substeps * weight;
+    for (int e0 = 0; e0 < c->pop; e0 += envs) {
+      Key k;
+      k.w.inst = i;
+      k.w.env0 = e0;
+      k.w.n = std::min(envs, c->pop - e0);
+      k.w.pad = 0;
+      k.cost = per_env;
+      keys.push_back(k);
+    }
+  }
+  std::stable_sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) { return a.cost > b.cost; });
+  std::vector<WorkItem> h(keys.size());
+  for (size_t i = 0; i < keys.size(); ++i) h[i] = keys[i].w;
+  if (b->items) (void)hipFree(b->items);
+  b->items = nullptr;
+  BHIPCHK(b, hipMalloc(&b->items, sizeof(WorkItem) * std::max<size_t>(1, h.size())));
+  BHIPCHK(b, hipMemcpy(b->items, h.data(), sizeof(WorkItem) * h.size(), hipMemcpyHostToDevice));
+  b->n_items = (int)h.size();
+  b->item_envs = envs;
+  return CEM_OK;
+}
+
+// One CE iteration of every instance still under its cap: batched sampling,
+// one persistent rollout launch over the work list, one refit workgroup per instance.
+int build_graph(cem_batch *b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  hipGraph_t g = nullptr;
+  BHIPCHK(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
+  const int n = (int)b->ctx.size();
+  hipError_t e1 = launch_sample_batch(b->insts, n, b->max_pop, b->own);
+  hipError_t e2 = launch_rollout_batch(b->insts, b->items, b->n_items, b->queue, b->grid, b->own);
+  hipError_t e3 = launch_select_refit_batch(b->insts, n, MAX_STATS_ITERS, b->own);
+  hipError_t e4 = hipStreamEndCapture(b->own, &g);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return bfail(b, CEM_E_HIP, "graph capture of the batched CE iteration failed");
+  }
+  hipError_t e5 = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e5 != hipSuccess) {
+    b->graph = nullptr;
+    return bfail(b, CEM_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e5));
+  }
+  return CEM_OK;
+}
+
+void batch_release(cem_batch *b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->own) (void)hipStreamDestroy(b->own);
+  (void)hipFree(b->insts);
+  (void)hipFree(b->items);
+  (void)hipFree(b->queue);
+  for (cem_ctx *c : b->ctx) cem_free(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cem_batch_init(const cem_problem *problems, const int32_t *iters, int32_t n, cem_batch **out) {
+  if (!out) return CEM_E_ARG;
+  *out = nullptr;
+  if (!problems || !iters || n < 1 || n > 4096) return CEM_E_ARG;
+  for (int i = 0; i < n; ++i)
+    if (iters[i] < 0 || iters[i] > MAX_STATS_ITERS) return CEM_E_ARG;
+  cem_batch *b = new (std::nothrow) cem_batch();
+  if (!b) return CEM_E_ALLOC;
+  int rc = CEM_OK;
+  for (int i = 0; i < n && rc == CEM_OK; ++i) {
+    cem_ctx *c = nullptr;
+    rc = cem_init(&problems[i], &c);
+    if (rc == CEM_OK) b->ctx.push_back(c);
+    else b->err = "cem_init failed for instance " + std::to_string(i);
+  }
+  if (rc == CEM_OK) {
+    b->iters.assign(iters, iters + n);
+    std::vector<InstDesc> h(n);
+    for (int i = 0; i < n; ++i) {
+      cem_ctx *c = b->ctx[i];
+      h[i] = desc_of(c, c->Z, c->pop, c->cost, c->tier, nullptr);
+      h[i].iters = iters[i];
+      b->max_pop = std::max(b->max_pop, c->pop);
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(&b->insts, sizeof(InstDesc) * n) != hipSuccess || hipMalloc(&b->queue, sizeof(int)) != hipSuccess ||
+        hipMemcpy(b->insts, h.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice) != hipSuccess) {
+      rc = CEM_E_HIP;
+      b->err = "batch set-up";
+    }
+  }
+  if (rc == CEM_OK) {
+    b->grid = 2 * b->n_cu;
+    rc = build_items(b, 64);
+  }
+  if (rc == CEM_OK) rc = build_graph(b);
+  if (rc != CEM_OK) {
+    batch_release(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return CEM_OK;
+}
+
+void cem_batch_free(cem_batch *b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->own);
+  batch_release(b);
+  delete b;
+}
+
+const char *cem_batch_last_error(const cem_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+int cem_batch_size(const cem_batch *b) { return b ? (int)b->ctx.size() : 0; }
+
+cem_ctx *cem_batch_instance(cem_batch *b, int32_t i) {
+  if (!b || i < 0 || i >= (int)b->ctx.size()) return nullptr;
+  return b->ctx[i];
+}
+
+int cem_batch_autotune(cem_batch *b, int32_t *config_out) {
+  if (!b) return CEM_E_ARG;
+  const int mults[3] = {1, 2, 4};
+  const int envs_opts[2] = {64, 32};
+  float best = INFINITY;
+  int best_grid = b->grid, best_envs = b->item_envs;
+  hipEvent_t e0, e1;
+  BHIPCHK(b, hipEventCreate(&e0));
+  BHIPCHK(b, hipEventCreate(&e1));
+  for (int ei = 0; ei < 2; ++ei) {
+    int rc = build_items(b, envs_opts[ei]);
+    if (rc != CEM_OK) return rc;
+    for (int mi = 0; mi < 3; ++mi) {
+      const int grid = mults[mi] * b->n_cu;
+      BHIPCHK(b, hipEventRecord(e0, b->own));
+      BHIPCHK(b, launch_rollout_batch(b->insts, b->items, b->n_items, b->queue, grid, b->own));
+      BHIPCHK(b, hipEventRecord(e1, b->own));
+      BHIPCHK(b, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      BHIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_grid = grid;
+        best_envs = envs_opts[ei];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->grid = best_grid;
+  int rc = build_items(b, best_envs);
+  if (rc == CEM_OK) rc = build_graph(b);
+  if (config_out) {
+    config_out[0] = b->grid;
+    config_out[1] = b->item_envs;
+    config_out[2] = (int32_t)(best * 1000.0f);  // microseconds of the fastest rollout pass
+  }
+  return rc;
+}
+
+int cem_batch_step(cem_batch *b, void *stream) {
+  if (!b) return CEM_E_ARG;
+  BHIPCHK(b, hipGraphLaunch(b->graph, stream ? (hipStream_t)stream : b->own));
+  return CEM_OK;
+}
+
+int cem_batch_solve(cem_batch *b, int32_t iters, cem_result *results, void *stream) {
+  if (!b) return CEM_E_ARG;
+  if (iters < 0) return bfail(b, CEM_E_ARG, "iters < 0");
+  hipStream_t s = stream ? (hipStream_t)stream : b->own;
+  for (int j = 0; j < iters; ++j) BHIPCHK(b, hipGraphLaunch(b->graph, s));
+  BHIPCHK(b, hipStreamSynchronize(s));
+  if (!results) return CEM_OK;
+  int rc = CEM_OK;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    cem_ctx *c = b->ctx[i];
+    DevState h;
+    BHIPCHK(b, hipMemcpy(&h, c->st, sizeof h, hipMemcpyDeviceToHost));
+    cem_result &r = results[i];
+    std::memset(&r, 0, sizeof r);
+    r.dim = c->D;
+    for (int d = 0; d < c->D; ++d) {
+      r.best_z[d] = h.best_z[d];
+      r.mu[d] = h.mu[d];
+    }
+    for (int t = 0; t < c->D * c->D; ++t) r.cov[t] = h.S[t];
+    r.best_cost = h.best_cost;
+    r.best_tier = h.best_tier;
+    r.iters_done = h.iter;
+    if (h.factor_status) rc = CEM_E_NUMERIC;
+  }
+  return rc;
 }
 
 }  // extern "C"

@@ -26,20 +26,39 @@ struct DevState {
   int32_t best_tier;
   int32_t factor_status;       // 0 ok, 1 diagonal fallback used
   int32_t sel_info[6];         // n_e, mode, n_tier0..3 of the last refit
+  uint64_t seed;               // Philox key
+  uint32_t inst_id;            // Philox counter word 3
+  int32_t pop;
   cem_scene scene;             // device copy of the scene (read by the rollout kernels)
+};
+
+// One task instance as the launches see it: its device state and buffers.
+struct InstDesc {
+  DevState *st;
+  const float *Z;   // pop x D parameter rows
+  float *cost;
+  uint8_t *tier;
+  float *pose;      // pop x 7, nullable
+  float *stats;     // iteration stats rows (batched refit), nullable
+  int32_t kind, pop, D, iters;  // iters: iteration cap in batched runs
+};
+// Up to 64 environments [env0, env0 + n) of instance `inst`.
+struct WorkItem {
+  int32_t inst, env0, n, pad;
 };
 
 // Launchers (each file owns its kernels).
 hipError_t launch_instance_draw(const cem_scene &sc, uint64_t seed, uint32_t inst, DevState *st, hipStream_t s);
 hipError_t launch_sample(uint64_t seed, uint32_t inst, int32_t iter, const DevState *st, int pop, int D, float *Z,
                          hipStream_t s);
+hipError_t launch_sample_batch(const InstDesc *insts, int n_inst, int max_pop, hipStream_t s);
 hipError_t launch_factor(DevState *st, hipStream_t s);
 hipError_t launch_select_refit(DevState *st, const float *Z, const float *cost, const uint8_t *tier, int pop,
                                int32_t *elite_idx, int32_t *sel_info, float *stats, int stats_cap,
                                int advance_iter, hipStream_t s);
-hipError_t launch_rollout_pickplace(const cem_scene *sc_dev, const float *Z, int pop, float *cost, uint8_t *tier,
-                                    float *pose, float *trace, int trace_steps, hipStream_t s);
-hipError_t launch_rollout_push(const cem_scene &sc, const DevState *st, const float *Z, int pop, float *cost,
-                               uint8_t *tier, float *pose, float *trace, int trace_steps, hipStream_t s);
+hipError_t launch_select_refit_batch(const InstDesc *insts, int n_inst, int stats_cap, hipStream_t s);
+hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s);
+hipError_t launch_rollout_batch(const InstDesc *insts, const WorkItem *items, int n_items, int *queue, int grid,
+                                hipStream_t s);
 
 }  // namespace cem

@@ -1,4 +1,5 @@
-// Evaluation step of CE optimisation (Alg. 1) for the mobile-manipulator
+// One environment of the mobile-manipulator pick-and-place plan (device function).
+//
 // pick-and-place plan (Sec. IV-A, pi_p&p without the final move to Exit):
 //   move_to(x, y, psi, v) -> grasp(q) -> move_to(x, y, psi, v) -> place(x, y, z, psi)
 // Problem 2 cost: dt per control step while the active action is not yet
@@ -27,12 +28,13 @@
 // over bodies without unrolling and without scratch; the rest of the state
 // stays in VGPRs.  HBM is touched only for z in and (cost, tier, pose) out;
 // the scene is read through wave-uniform scalar loads.
+#pragma once
 #include "robot_dyn.hpp"
 
 namespace cem {
 namespace {
 
-constexpr int BS = 64;
+constexpr int PP_LANES = 64;  // lanes sharing one LDS block of rows
 // LDS rows (each BS floats): q, qd, qref, bias acceleration c (6 per body),
 // bias force pA then U (6 per body), 1/D, u
 constexpr int R_Q = 0, R_QD = R_Q + NJ, R_QREF = R_QD + NJ, R_C = R_QREF + NJ, R_P = R_C + 6 * NJ,
@@ -41,7 +43,7 @@ constexpr int R_Q = 0, R_QD = R_Q + NJ, R_QREF = R_QD + NJ, R_C = R_QREF + NJ, R
 struct Lds {
   float *m;
   int lane;
-  __device__ __forceinline__ float &at(int row) const { return m[row * BS + lane]; }
+  __device__ __forceinline__ float &at(int row) const { return m[row * PP_LANES + lane]; }
   __device__ __forceinline__ SV sv_at(int row) const {
     return sv(v3(at(row), at(row + 1), at(row + 2)), v3(at(row + 3), at(row + 4), at(row + 5)));
   }
@@ -61,18 +63,15 @@ __device__ __forceinline__ Xf joint_X(const cem_scene &sc, int j, float q) {
   return X;
 }
 
+// Rolls out row `env` of Z (16 parameters) and writes its cost, tier, pose and
+// (TRACE) per-step trace.  `lds_mem` is the block's R_ROWS x PP_LANES float
+// array and `lane` this lane's column in it.
 template <bool TRACE>
-__global__ void __launch_bounds__(BS) rollout_pickplace_kernel(const cem_scene *__restrict__ scp,
-                                                               const float *__restrict__ Z, int pop,
-                                                               float *__restrict__ cost_out,
-                                                               uint8_t *__restrict__ tier_out,
-                                                               float *__restrict__ pose_out,
-                                                               float *__restrict__ trace, int trace_steps) {
-  __shared__ float lds_mem[R_ROWS * BS];
-  const int env = blockIdx.x * blockDim.x + threadIdx.x;
-  if (env >= pop) return;
-  const Lds L{lds_mem, (int)threadIdx.x};
-  const cem_scene &sc = *scp;  // device copy: uniform fields come in through scalar loads
+__device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *__restrict__ Z, long env,
+                                              float *lds_mem, int lane, float *__restrict__ cost_out,
+                                              uint8_t *__restrict__ tier_out, float *__restrict__ pose_out,
+                                              float *__restrict__ trace, int trace_steps) {
+  const Lds L{lds_mem, lane};
   const float h = sc.dt / (float)sc.substeps;
   const float dt = sc.dt;
   const float g = sc.gravity;
@@ -486,17 +485,4 @@ __global__ void __launch_bounds__(BS) rollout_pickplace_kernel(const cem_scene *
 }
 
 }  // namespace
-
-hipError_t launch_rollout_pickplace(const cem_scene *sc, const float *Z, int pop, float *cost, uint8_t *tier,
-                                    float *pose, float *trace, int trace_steps, hipStream_t s) {
-  const dim3 grid((pop + BS - 1) / BS);
-  if (trace)
-    hipLaunchKernelGGL(rollout_pickplace_kernel<true>, grid, dim3(BS), 0, s, sc, Z, pop, cost, tier, pose, trace,
-                       trace_steps);
-  else
-    hipLaunchKernelGGL(rollout_pickplace_kernel<false>, grid, dim3(BS), 0, s, sc, Z, pop, cost, tier, pose, nullptr,
-                       0);
-  return hipGetLastError();
-}
-
 }  // namespace cem

@@ -1,3 +1,5 @@
+// One environment of the single-action push plan (device function).
+//
 // Evaluation step of CE optimisation (Alg. 1) for the single-action push plan:
 // a kinematic, velocity-controlled sphere pushes one box over the ground plane.
 //
@@ -10,21 +12,19 @@
 //
 // One environment per lane; the whole state (13 floats) stays in VGPRs for the
 // H x n_sub substeps; HBM is touched only for z in and (cost, tier, pose) out.
+#pragma once
 #include "internal.hpp"
 #include "rigid.hpp"
 
 namespace cem {
 namespace {
 
+// Rolls out row i of Z (theta, o, s) and writes its cost, tier, pose and (TRACE) trace.
 template <bool TRACE>
-__global__ void __launch_bounds__(64) rollout_push_kernel(cem_scene sc, const DevState *__restrict__ st,
-                                                          const float *__restrict__ Z, int pop,
-                                                          float *__restrict__ cost_out,
-                                                          uint8_t *__restrict__ tier_out,
-                                                          float *__restrict__ pose_out, float *__restrict__ trace,
-                                                          int trace_steps) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= pop) return;
+__device__ __forceinline__ void push_env(const cem_scene &sc, const DevState *__restrict__ st,
+                                         const float *__restrict__ Z, long i, float *__restrict__ cost_out,
+                                         uint8_t *__restrict__ tier_out, float *__restrict__ pose_out,
+                                         float *__restrict__ trace, int trace_steps) {
   const float h = sc.dt / (float)sc.substeps;
   const V3f gv = v3(0.0f, 0.0f, -sc.gravity);
   const float k = sc.k_contact, damp = sc.c_contact, eps2 = sc.eps_v * sc.eps_v;
@@ -90,18 +90,4 @@ __global__ void __launch_bounds__(64) rollout_push_kernel(cem_scene sc, const De
 }
 
 }  // namespace
-
-hipError_t launch_rollout_push(const cem_scene &sc, const DevState *st, const float *Z, int pop, float *cost,
-                               uint8_t *tier, float *pose, float *trace, int trace_steps, hipStream_t s) {
-  const int bs = 64;
-  const dim3 grid((pop + bs - 1) / bs);
-  if (trace)
-    hipLaunchKernelGGL(rollout_push_kernel<true>, grid, dim3(bs), 0, s, sc, st, Z, pop, cost, tier, pose, trace,
-                       trace_steps);
-  else
-    hipLaunchKernelGGL(rollout_push_kernel<false>, grid, dim3(bs), 0, s, sc, st, Z, pop, cost, tier, pose,
-                       nullptr, 0);
-  return hipGetLastError();
-}
-
 }  // namespace cem

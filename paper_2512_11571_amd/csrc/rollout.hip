@@ -1,0 +1,86 @@
+// The rollout launch (evaluation step of Alg. 1) for one or many task instances.
+//
+// Work is cut into items of up to 64 environments of one instance (one wave,
+// one environment per lane).  A single instance runs one workgroup per item.
+// A batch of instances (independent CE problems with their own scene kind,
+// population and horizon) runs as one persistent launch: each workgroup pulls
+// the next item from an atomic queue until the list is exhausted, so the items
+// of long-horizon instances, put first in the list, overlap with the many short
+// ones and no workgroup idles while work remains.  Both modes execute the same
+// per-environment code in the same kernel, so an instance's results do not
+// depend on whether it ran alone or in a batch.
+#include "internal.hpp"
+#include "pickplace_env.hpp"
+#include "push_env.hpp"
+
+namespace cem {
+namespace {
+
+template <bool TRACE>
+__global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, const InstDesc *__restrict__ insts,
+                                                           const WorkItem *__restrict__ items, int n_items,
+                                                           int *__restrict__ queue, int check_iter,
+                                                           float *__restrict__ trace, int trace_steps) {
+  __shared__ float lds[R_ROWS * PP_LANES];
+  const int lane = threadIdx.x;
+  int it = blockIdx.x;
+  for (;;) {
+    if (queue) {
+      int v = 0;
+      if (lane == 0) v = atomicAdd(queue, 1);
+      it = __shfl(v, 0, 64);
+    }
+    if (it >= n_items) break;  // every wave of the grid reaches this once the queue is drained
+    InstDesc d;
+    int env0, n;
+    if (insts) {
+      const WorkItem w = items[it];
+      d = insts[w.inst];
+      env0 = w.env0;
+      n = w.n;
+    } else {
+      d = single;
+      env0 = it * 64;
+      n = min(64, d.pop - env0);
+    }
+    const bool active = !(check_iter && d.st->iter >= d.iters);
+    if (active && lane < n) {
+      const long env = env0 + lane;
+      const cem_scene &sc = d.st->scene;
+      if (d.kind == CEM_SCENE_PUSH)
+        push_env<TRACE>(sc, d.st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
+      else
+        pickplace_env<TRACE>(sc, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
+    }
+    if (!queue) break;
+  }
+}
+
+__global__ void reset_counter_kernel(int *q) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
+}
+
+}  // namespace
+
+hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s) {
+  const int n_items = (d.pop + 63) / 64;
+  if (n_items == 0) return hipSuccess;
+  if (trace)
+    hipLaunchKernelGGL(rollout_items_kernel<true>, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items,
+                       nullptr, 0, trace, trace_steps);
+  else
+    hipLaunchKernelGGL(rollout_items_kernel<false>, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items,
+                       nullptr, 0, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_rollout_batch(const InstDesc *insts, const WorkItem *items, int n_items, int *queue, int grid,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, queue);
+  InstDesc none{};
+  hipLaunchKernelGGL(rollout_items_kernel<false>, dim3(grid), dim3(64), 0, s, none, insts, items, n_items, queue,
+                     1, nullptr, 0);
+  return hipGetLastError();
+}
+
+}  // namespace cem

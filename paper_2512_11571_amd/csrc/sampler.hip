@@ -92,14 +92,10 @@ __device__ __forceinline__ void sincos_2pi(float u, float &s, float &c) {
   c = q == 0 ? cx : (q == 1 ? -sx : (q == 2 ? -cx : sx));
 }
 
-// One thread per sample row: D normals from ceil(D/4) Philox blocks, then
+// One sample row: D normals from ceil(D/4) Philox blocks, then
 // z_d = fl32(mu_d + sum_{e<=d} L_de eps_e) in FP64, ascending e.
-__global__ void __launch_bounds__(256) sample_kernel(uint64_t seed, uint32_t inst, int32_t iter_arg,
-                                                     const DevState *__restrict__ st, int pop, int D,
-                                                     float *__restrict__ Z) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= pop) return;
-  const uint32_t iter = iter_arg >= 0 ? (uint32_t)iter_arg : (uint32_t)st->iter;
+__device__ __forceinline__ void sample_row(uint64_t seed, uint32_t inst, uint32_t iter,
+                                           const DevState *__restrict__ st, int D, int i, float *__restrict__ Z) {
   float eps[MAX_D];
 #pragma unroll
   for (int blk = 0; blk < MAX_D / 4; ++blk) {
@@ -124,6 +120,25 @@ __global__ void __launch_bounds__(256) sample_kernel(uint64_t seed, uint32_t ins
   }
 }
 
+// One thread per row of one instance; the iteration is the argument or, when
+// negative, the instance's device counter (the replayed iteration).
+__global__ void __launch_bounds__(256) sample_kernel(uint64_t seed, uint32_t inst, int32_t iter_arg,
+                                                     const DevState *__restrict__ st, int pop, int D,
+                                                     float *__restrict__ Z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pop) return;
+  const uint32_t iter = iter_arg >= 0 ? (uint32_t)iter_arg : (uint32_t)st->iter;
+  sample_row(seed, inst, iter, st, D, i, Z);
+}
+
+// Batched: grid.y = instance; instances past their iteration cap are skipped.
+__global__ void __launch_bounds__(256) sample_batch_kernel(const InstDesc *__restrict__ insts) {
+  const InstDesc d = insts[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.pop || d.st->iter >= d.iters) return;
+  sample_row(d.st->seed, d.st->inst_id, (uint32_t)d.st->iter, d.st, d.D, i, const_cast<float *>(d.Z));
+}
+
 // Per-instance draws on the scene stream (tag 1): the push goal
 // g = start + rho (cos phi, sin phi), rho and phi uniform in their ranges.
 __global__ void instance_draw_kernel(cem_scene sc, uint64_t seed, uint32_t inst, DevState *st) {
@@ -142,6 +157,12 @@ hipError_t launch_sample(uint64_t seed, uint32_t inst, int32_t iter, const DevSt
                          hipStream_t s) {
   const int bs = 256;
   hipLaunchKernelGGL(sample_kernel, dim3((pop + bs - 1) / bs), dim3(bs), 0, s, seed, inst, iter, st, pop, D, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_batch(const InstDesc *insts, int n_inst, int max_pop, hipStream_t s) {
+  const int bs = 256;
+  hipLaunchKernelGGL(sample_batch_kernel, dim3((max_pop + bs - 1) / bs, n_inst), dim3(bs), 0, s, insts);
   return hipGetLastError();
 }
 

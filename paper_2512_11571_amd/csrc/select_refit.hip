@@ -109,12 +109,11 @@ __device__ void factor_into(DevState *st, double *A, double *L, int *bad) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(BS) select_refit_kernel(DevState *__restrict__ st, const float *__restrict__ Z,
-                                                          const float *__restrict__ cost,
-                                                          const uint8_t *__restrict__ tier, int pop,
-                                                          int32_t *__restrict__ elite_out,
-                                                          int32_t *__restrict__ sel_out, float *__restrict__ stats,
-                                                          int stats_cap, int advance_iter) {
+__device__ __forceinline__ void select_refit_block(DevState *__restrict__ st, const float *__restrict__ Z,
+                                                   const float *__restrict__ cost, const uint8_t *__restrict__ tier,
+                                                   int pop, int32_t *__restrict__ elite_out,
+                                                   int32_t *__restrict__ sel_out, float *__restrict__ stats,
+                                                   int stats_cap, int advance_iter) {
   __shared__ int cnt[4];
   __shared__ unsigned hist[256];
   __shared__ uint64_t sel[MAX_ELITE];
@@ -296,6 +295,22 @@ __global__ void __launch_bounds__(BS) select_refit_kernel(DevState *__restrict__
   }
 }
 
+__global__ void __launch_bounds__(BS) select_refit_kernel(DevState *__restrict__ st, const float *__restrict__ Z,
+                                                          const float *__restrict__ cost,
+                                                          const uint8_t *__restrict__ tier, int pop,
+                                                          int32_t *__restrict__ elite_out,
+                                                          int32_t *__restrict__ sel_out, float *__restrict__ stats,
+                                                          int stats_cap, int advance_iter) {
+  select_refit_block(st, Z, cost, tier, pop, elite_out, sel_out, stats, stats_cap, advance_iter);
+}
+
+// Batched: one workgroup per instance; instances past their iteration cap are skipped.
+__global__ void __launch_bounds__(BS) select_refit_batch_kernel(const InstDesc *__restrict__ insts, int stats_cap) {
+  const InstDesc d = insts[blockIdx.x];
+  if (d.st->iter >= d.iters) return;  // uniform over the workgroup
+  select_refit_block(d.st, d.Z, d.cost, d.tier, d.pop, nullptr, nullptr, d.stats, stats_cap, 1);
+}
+
 __global__ void __launch_bounds__(BS) factor_kernel(DevState *st) {
   __shared__ double A[MAX_D * MAX_D], Lw[MAX_D * MAX_D];
   __shared__ int bad;
@@ -309,6 +324,11 @@ hipError_t launch_select_refit(DevState *st, const float *Z, const float *cost, 
                                int advance_iter, hipStream_t s) {
   hipLaunchKernelGGL(select_refit_kernel, dim3(1), dim3(BS), 0, s, st, Z, cost, tier, pop, elite_idx, sel_info,
                      stats, stats_cap, advance_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_refit_batch(const InstDesc *insts, int n_inst, int stats_cap, hipStream_t s) {
+  hipLaunchKernelGGL(select_refit_batch_kernel, dim3(n_inst), dim3(BS), 0, s, insts, stats_cap);
   return hipGetLastError();
 }
 

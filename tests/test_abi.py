@@ -11,7 +11,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "cemtamp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char|size_t)\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char|size_t|cem_ctx)\s*\*?\s*([a-z_0-9]+)\s*\(", src,
+                       flags=re.M)
     return sorted(set(names))
 
 
@@ -59,3 +60,21 @@ def test_init_rejects_bad_arguments_before_touching_the_device():
     with pytest.raises(binding.CemError) as e:
         binding.Context(bad)
     assert e.value.code == 2
+
+
+def test_batch_workload_recipe():
+    from paper_2512_11571_amd import workloads
+    spec = workloads.load("batch")["batch"]
+    a = workloads.batch_instances()
+    b = workloads.batch_instances()
+    assert len(a) == spec["n_instances"] == 64
+    for i, (x, y) in enumerate(zip(a, b)):
+        w = x["workload"]
+        assert w == y["workload"]
+        assert w["scene"]["kind"] == spec["kinds"][i % 2]
+        assert spec["horizon"][0] <= w["scene"]["horizon"] <= spec["horizon"][1]
+        assert w["cem"]["pop"] % 64 == 0 and spec["pop"][0] <= w["cem"]["pop"] <= spec["pop"][1] + 63
+        assert w["cem"]["n_elite"] == w["cem"]["pop"] // 16
+        assert x["iters"] == spec["iters"][w["scene"]["kind"]]
+    pops = [x["workload"]["cem"]["pop"] * x["workload"]["scene"]["horizon"] for x in a]
+    assert 1e8 < sum(pops) < 6e8
