@@ -102,6 +102,13 @@ def lib():
         L.ref_tree_fk.argtypes = [P(Tree), vp, vp, vp]
         L.ref_ik.argtypes = [P(RefScene), vp, vp, vp, vp, vp, vp]
         L.ref_tree_sim.argtypes = [P(Tree), vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp]
+        L.ref_mlp_n_params.restype = ctypes.c_long
+        L.ref_mlp_init.argtypes = [u64, vp]
+        L.ref_mlp_forward.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int]
+        L.ref_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+        L.ref_mlp_loss_grad.restype = ctypes.c_double
+        L.ref_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_long, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.ref_object_sim.argtypes = [P(RefScene), vp, vp, vp, ctypes.c_int, vp]
         if L.ref_tree_size() != ctypes.sizeof(Tree):
             raise RuntimeError("oracle Tree layout mismatch")
@@ -380,6 +387,49 @@ def tree_fk(tree, q):
     p = np.zeros((tree.n, 3))
     lib().ref_tree_fk(ctypes.byref(tree), _ptr(_f64(q)), _ptr(R), _ptr(p))
     return R, p
+
+
+MLP_DIMS = (16, 256, 256, 256, 8)
+
+
+def mlp_n_params():
+    return int(lib().ref_mlp_n_params())
+
+
+def mlp_init(seed):
+    P = np.zeros(mlp_n_params())
+    lib().ref_mlp_init(seed, _ptr(P))
+    return P
+
+
+def mlp_forward(P, x, bf16=False):
+    x = _f64(x)
+    n = x.shape[0]
+    y = np.zeros((n, MLP_DIMS[-1]))
+    lib().ref_mlp_forward(_ptr(_f64(P)), _ptr(x), n, _ptr(y), 1 if bf16 else 0)
+    return y
+
+
+def mlp_loss_grad(P, x, t, want_grad=True):
+    x, t = _f64(x), _f64(t)
+    g = np.zeros(mlp_n_params()) if want_grad else None
+    loss = lib().ref_mlp_loss_grad(_ptr(_f64(P)), _ptr(x), _ptr(t), x.shape[0], _ptr(g) if want_grad else None)
+    return loss, g
+
+
+def adam_step(P, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays P, m, v (t = step number from 1)."""
+    lib().ref_adam_step(_ptr(P), _ptr(_f64(g)), _ptr(m), _ptr(v), P.size, lr, b1, b2, eps, t)
+
+
+def mlp_slices():
+    """(W, b) slices of the flat parameter vector per layer; W as (out, in)."""
+    out, o = [], 0
+    for l in range(4):
+        ni, no = MLP_DIMS[l], MLP_DIMS[l + 1]
+        out.append((slice(o, o + ni * no), (no, ni), slice(o + ni * no, o + ni * no + no)))
+        o += ni * no + no
+    return out
 
 
 def tree_sim(tree, q0, qd0, g, h, n):

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "ref_cem.hpp"
+#include "ref_mlp.hpp"
 #include "ref_push.hpp"
 #include "ref_random.hpp"
 #include "ref_robot.hpp"
@@ -291,6 +292,40 @@ void ref_ik(const RefScene *s, const double *q, const double pt[3], const double
   pe[0] = p.x; pe[1] = p.y; pe[2] = p.z;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) Re[a * 3 + b] = E.m[a][b];
+}
+
+// ---- surrogate network ----
+long ref_mlp_n_params(void) { return mlp_n_params(); }
+
+// He-normal initialisation: W entry p of layer l ~ N(0, 2 / fan_in) from the
+// normals of Philox stream 2 (block p / 4, sample 0, iteration 0, instance 0),
+// rounded to FP32; biases 0.
+void ref_mlp_init(uint64_t seed, double *P) {
+  for (long i = 0; i < mlp_n_params(); ++i) P[i] = 0.0;
+  for (int l = 0; l < MLP_L; ++l) {
+    const long w0 = mlp_w_off(l), nw = (long)MLP_DIMS[l] * MLP_DIMS[l + 1];
+    const double s = std::sqrt(2.0 / (double)MLP_DIMS[l]);
+    for (long k = 0; k < nw; ++k) {
+      const long p = w0 + k;
+      Word4 x = philox_draw(seed, STREAM_MLP_INIT, (uint32_t)(p / 4), 0, 0, 0);
+      float nrm[4];
+      normals4(x, nrm);
+      P[p] = (double)(float)((double)nrm[p % 4] * s);
+    }
+  }
+}
+
+void ref_mlp_forward(const double *P, const double *x, int n, double *y, int bf16) {
+  mlp_forward(P, x, n, y, bf16 != 0, nullptr);
+}
+
+double ref_mlp_loss_grad(const double *P, const double *x, const double *t, int n, double *dP) {
+  return mlp_loss_grad(P, x, t, n, dP);
+}
+
+void ref_adam_step(double *P, const double *g, double *m, double *v, long n, double lr, double b1, double b2,
+                   double eps, int t) {
+  adam_step(P, g, m, v, n, lr, b1, b2, eps, t);
 }
 
 int ref_select(int pop, const float *cost, const uint8_t *tier, int n_elite, int32_t *elite_idx, int32_t *mode,
