@@ -214,6 +214,65 @@ int cem_batch_autotune(cem_batch *b, int32_t *config_out);
 int cem_batch_step(cem_batch *b, void *stream);
 /* iters iterations, then results[n] (host) for every instance.  Synchronous. */
 int cem_batch_solve(cem_batch *b, int32_t iters, cem_result *results, void *stream);
+/* Runs iters iterations and after each appends every instance that ran its
+ * (parameter row, outcome) pairs to X_dev (rows x D, one D for all instances)
+ * and Y_dev (rows x 8: cost, final object position, orientation w >= 0; a
+ * diverged rollout gets the horizon cost and the start pose).  *n_out = rows
+ * written (at most capacity, else CEM_E_ARG).  Synchronous. */
+int cem_batch_record(cem_batch *b, int32_t iters, float *X_dev, float *Y_dev, int64_t capacity, int64_t *n_out,
+                     void *stream);
+
+/* ---- Learned surrogate for screening ----------------------------------------
+ * Not in the paper (whose limitation is the cost of full rollouts): a
+ * 16 -> 256 -> 256 -> 256 -> 8 perceptron with GELU (tanh form) predicting
+ * (cost, final object pose) from the 16 pick-and-place parameters, trained on
+ * simulated rollouts.  Products run as BF16 MFMA with FP32 accumulation;
+ * master weights and Adam moments are FP32.  Inputs and targets are
+ * standardised per column (cem_mlp_fit_norm / set_norm).  The flat parameter
+ * vector is W1 (256x16, row = output unit), b1, W2, b2, W3, b3, W4 (8x256), b4. */
+typedef struct cem_mlp cem_mlp;
+/* He-normal weights from Philox stream 2, zero biases, identity
+ * standardisation; work buffers for up to max_rows rows.  Synchronous. */
+int cem_mlp_init(uint64_t seed, int32_t max_rows, cem_mlp **out);
+void cem_mlp_free(cem_mlp *m);
+int cem_mlp_n_params(void);
+const char *cem_mlp_last_error(const cem_mlp *m);
+/* host copies of the FP32 master parameters (cem_mlp_n_params floats) */
+int cem_mlp_get_params(cem_mlp *m, float *host);
+int cem_mlp_set_params(cem_mlp *m, const float *host);
+/* standardisation, 48 host floats: x_mean[16] x_std[16] y_mean[8] y_std[8] */
+int cem_mlp_get_norm(cem_mlp *m, float *host48);
+int cem_mlp_set_norm(cem_mlp *m, const float *host48);
+/* column means / standard deviations of a dataset (n rows), on the GPU */
+int cem_mlp_fit_norm(cem_mlp *m, const float *X_dev, const float *Y_dev, int64_t n, void *stream);
+/* predictions Y_dev (n x 8, de-standardised) of raw parameter rows X_dev (n x 16) */
+int cem_mlp_forward(cem_mlp *m, const float *X_dev, int32_t n, float *Y_dev, void *stream);
+/* mean squared error over n rows and 8 standardised outputs, and its gradient
+ * w.r.t. the parameters (grad_dev, nullable) */
+int cem_mlp_loss_grad(cem_mlp *m, const float *X_dev, const float *Y_dev, int32_t n, float *grad_dev, float *loss_dev,
+                      void *stream);
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the rows given */
+int cem_mlp_train_step(cem_mlp *m, const float *X_dev, const float *Y_dev, int32_t n, float lr, float *loss_dev,
+                       void *stream);
+/* epochs over n rows in shuffled minibatches of `batch` (an affine
+ * permutation per epoch, from seed); mean minibatch loss per epoch to
+ * epoch_loss_host (nullable).  Synchronous. */
+int cem_mlp_train(cem_mlp *m, const float *X_dev, const float *Y_dev, int64_t n, int32_t batch, int32_t epochs,
+                  float lr, uint64_t seed, float *epoch_loss_host);
+/* Screening: sample the context's population (iteration iter), predict every
+ * candidate and keep the n_sim smallest (goal predicted to fail, predicted
+ * cost, index) keys - the goal test is the plan's psi_g on the predicted
+ * pose - written in index order: Zsim_dev (n_sim x 16), pred_dev (n_sim x 8,
+ * nullable). */
+int cem_screen(cem_ctx *c, cem_mlp *m, int32_t iter, int32_t n_sim, float *Zsim_dev, float *pred_dev, void *stream);
+/* Surrogate-screened CE: each iteration samples the context's population,
+ * screens it down to n_sim candidates, simulates those in full and refits
+ * from the simulated costs (the surrogate never decides a cost that enters
+ * the refit).  One captured graph per iteration.  surrogate_err_host
+ * (nullable, iters floats): mean |predicted - simulated| cost of each
+ * iteration's simulated candidates.  Synchronous. */
+int plan_solve_screened(cem_ctx *c, cem_mlp *m, int32_t iters, int32_t n_sim, cem_result *res, float *stats_host,
+                        float *surrogate_err_host, void *stream);
 
 #ifdef __cplusplus
 }

@@ -78,7 +78,11 @@ class CemResult(ctypes.Structure):
 EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem_last_error", "cem_sample", "rollout_batch",
            "rollout_trace", "cem_refit", "plan_solve", "cem_get_theta", "cem_set_theta", "cem_get_factor",
            "cem_get_instance", "cem_reset", "cem_batch_init", "cem_batch_free", "cem_batch_size",
-           "cem_batch_last_error", "cem_batch_instance", "cem_batch_autotune", "cem_batch_step", "cem_batch_solve"]
+           "cem_batch_last_error", "cem_batch_instance", "cem_batch_autotune", "cem_batch_step", "cem_batch_solve",
+           "cem_batch_record", "cem_mlp_init", "cem_mlp_free", "cem_mlp_n_params", "cem_mlp_last_error",
+           "cem_mlp_get_params", "cem_mlp_set_params", "cem_mlp_get_norm", "cem_mlp_set_norm", "cem_mlp_fit_norm",
+           "cem_mlp_forward", "cem_mlp_loss_grad", "cem_mlp_train_step", "cem_mlp_train", "cem_screen",
+           "plan_solve_screened"]
 
 _lib = None
 
@@ -121,6 +125,24 @@ def lib():
         L.cem_batch_autotune.argtypes = [vp, vp]
         L.cem_batch_step.argtypes = [vp, vp]
         L.cem_batch_solve.argtypes = [vp, _i, vp, vp]
+        i64 = ctypes.c_int64
+        L.cem_batch_record.argtypes = [vp, _i, vp, vp, i64, vp, vp]
+        L.cem_mlp_init.argtypes = [ctypes.c_uint64, _i, P(vp)]
+        L.cem_mlp_free.argtypes = [vp]
+        L.cem_mlp_free.restype = None
+        L.cem_mlp_last_error.argtypes = [vp]
+        L.cem_mlp_last_error.restype = ctypes.c_char_p
+        L.cem_mlp_get_params.argtypes = [vp, vp]
+        L.cem_mlp_set_params.argtypes = [vp, vp]
+        L.cem_mlp_get_norm.argtypes = [vp, vp]
+        L.cem_mlp_set_norm.argtypes = [vp, vp]
+        L.cem_mlp_fit_norm.argtypes = [vp, vp, vp, i64, vp]
+        L.cem_mlp_forward.argtypes = [vp, vp, _i, vp, vp]
+        L.cem_mlp_loss_grad.argtypes = [vp, vp, vp, _i, vp, vp, vp]
+        L.cem_mlp_train_step.argtypes = [vp, vp, vp, _i, ctypes.c_float, vp, vp]
+        L.cem_mlp_train.argtypes = [vp, vp, vp, i64, _i, _i, ctypes.c_float, ctypes.c_uint64, vp]
+        L.cem_screen.argtypes = [vp, vp, _i, _i, vp, vp, vp]
+        L.plan_solve_screened.argtypes = [vp, vp, _i, _i, P(CemResult), vp, vp, vp]
         for which, st in enumerate((CemScene, CemProblem, CemResult)):
             if L.cem_sizeof(which) != ctypes.sizeof(st):
                 raise RuntimeError("ABI struct layout mismatch for %s" % st.__name__)
@@ -387,3 +409,96 @@ class Batch:
         res = (CemResult * n)()
         self._check(lib().cem_batch_solve(self.h, int(iters), res, _stream(stream) if stream is not None else None))
         return [_result_dict(res[i], DIM[self.instances[i]["workload"]["scene"]["kind"]]) for i in range(n)]
+
+    def record(self, iters, X, Y):
+        """Run iters iterations, appending (parameters, outcome) rows to device tensors X, Y; returns rows."""
+        n = ctypes.c_int64()
+        self._check(lib().cem_batch_record(self.h, int(iters), _dptr(X), _dptr(Y), X.shape[0], ctypes.byref(n),
+                                           None))
+        return int(n.value)
+
+
+class Mlp:
+    """The screening surrogate (wraps cem_mlp*)."""
+
+    def __init__(self, seed=0, max_rows=65536):
+        h = ctypes.c_void_p()
+        rc = lib().cem_mlp_init(int(seed), int(max_rows), ctypes.byref(h))
+        if rc != CEM_OK:
+            raise CemError(rc, lib().cem_strerror(rc).decode())
+        self.h = h
+        self.n_params = lib().cem_mlp_n_params()
+
+    def _check(self, rc):
+        if rc != CEM_OK:
+            raise CemError(rc, lib().cem_mlp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cem_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def get_params(self):
+        P = np.zeros(self.n_params, np.float32)
+        self._check(lib().cem_mlp_get_params(self.h, _np_ptr(P)))
+        return P
+
+    def set_params(self, P):
+        P = np.ascontiguousarray(P, np.float32)
+        self._check(lib().cem_mlp_set_params(self.h, _np_ptr(P)))
+
+    def get_norm(self):
+        v = np.zeros(48, np.float32)
+        self._check(lib().cem_mlp_get_norm(self.h, _np_ptr(v)))
+        return v
+
+    def set_norm(self, v):
+        v = np.ascontiguousarray(v, np.float32)
+        self._check(lib().cem_mlp_set_norm(self.h, _np_ptr(v)))
+
+    def fit_norm(self, X, Y, n=None):
+        self._check(lib().cem_mlp_fit_norm(self.h, _dptr(X), _dptr(Y), int(n if n is not None else X.shape[0]),
+                                           _stream(None)))
+
+    def forward(self, X, Y, stream=None):
+        self._check(lib().cem_mlp_forward(self.h, _dptr(X), X.shape[0], _dptr(Y), _stream(stream)))
+
+    def loss_grad(self, X, Y, grad=None, loss=None, stream=None):
+        self._check(lib().cem_mlp_loss_grad(self.h, _dptr(X), _dptr(Y), X.shape[0], _dptr(grad), _dptr(loss),
+                                            _stream(stream)))
+
+    def train_step(self, X, Y, lr, loss=None, stream=None):
+        self._check(lib().cem_mlp_train_step(self.h, _dptr(X), _dptr(Y), X.shape[0], float(lr), _dptr(loss),
+                                             _stream(stream)))
+
+    def train(self, X, Y, n, batch, epochs, lr, seed=0):
+        losses = np.zeros(max(epochs, 1), np.float32)
+        self._check(lib().cem_mlp_train(self.h, _dptr(X), _dptr(Y), int(n), int(batch), int(epochs), float(lr),
+                                        int(seed), _np_ptr(losses)))
+        return losses[:epochs]
+
+    def screen(self, ctx, it, n_sim, Zsim, pred=None, stream=None):
+        self._check(lib().cem_screen(ctx.h, self.h, int(it), int(n_sim), _dptr(Zsim), _dptr(pred), _stream(stream)))
+
+    def plan_solve_screened(self, ctx, iters, n_sim):
+        res = CemResult()
+        stats = np.zeros((max(iters, 1), STATS_COLS), np.float32)
+        err = np.zeros(max(iters, 1), np.float32)
+        self._check(lib().plan_solve_screened(ctx.h, self.h, int(iters), int(n_sim), ctypes.byref(res),
+                                              _np_ptr(stats), _np_ptr(err), None))
+        out = _result_dict(res, ctx.D)
+        out["stats"] = stats[:iters]
+        out["surrogate_err"] = err[:iters]
+        return out

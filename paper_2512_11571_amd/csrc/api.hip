@@ -15,20 +15,6 @@
 
 using namespace cem;
 
-struct cem_ctx {
-  cem_scene scene;
-  int D = 0, pop = 0, n_elite = 0, cov_mode = 0;
-  uint64_t seed = 0;
-  uint32_t inst = 0;
-  int device = 0;
-  DevState *st = nullptr;
-  float *Z = nullptr, *cost = nullptr, *pose = nullptr, *stats = nullptr;
-  uint8_t *tier = nullptr;
-  hipStream_t own = nullptr;
-  hipGraphExec_t iter_graph = nullptr;
-  std::string err;
-};
-
 namespace {
 
 int fail(cem_ctx *c, int code, const std::string &msg) {
@@ -526,7 +512,7 @@ int cem_batch_init(const cem_problem *problems, const int32_t *iters, int32_t n,
     std::vector<InstDesc> h(n);
     for (int i = 0; i < n; ++i) {
       cem_ctx *c = b->ctx[i];
-      h[i] = desc_of(c, c->Z, c->pop, c->cost, c->tier, nullptr);
+      h[i] = desc_of(c, c->Z, c->pop, c->cost, c->tier, c->pose);
       h[i].iters = iters[i];
       b->max_pop = std::max(b->max_pop, c->pop);
     }
@@ -613,6 +599,38 @@ int cem_batch_autotune(cem_batch *b, int32_t *config_out) {
 int cem_batch_step(cem_batch *b, void *stream) {
   if (!b) return CEM_E_ARG;
   BHIPCHK(b, hipGraphLaunch(b->graph, stream ? (hipStream_t)stream : b->own));
+  return CEM_OK;
+}
+
+int cem_batch_record(cem_batch *b, int32_t iters, float *X_dev, float *Y_dev, int64_t capacity, int64_t *n_out,
+                     void *stream) {
+  if (!b) return CEM_E_ARG;
+  if (iters < 0 || !X_dev || !Y_dev || !n_out) return bfail(b, CEM_E_ARG, "bad arguments");
+  for (cem_ctx *c : b->ctx)
+    if (c->D != b->ctx[0]->D) return bfail(b, CEM_E_ARG, "recording needs one parameter dimension");
+  hipStream_t s = stream ? (hipStream_t)stream : b->own;
+  std::vector<int32_t> it(b->ctx.size());
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    BHIPCHK(b, hipMemcpyAsync(&it[i], &b->ctx[i]->st->iter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
+  BHIPCHK(b, hipStreamSynchronize(s));
+  int64_t n = 0;
+  const int D = b->ctx[0]->D;
+  for (int j = 0; j < iters; ++j) {
+    BHIPCHK(b, hipGraphLaunch(b->graph, s));
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+      cem_ctx *c = b->ctx[i];
+      if (it[i] >= b->iters[i]) continue;  // this instance did not run in this step
+      ++it[i];
+      if (n + c->pop > capacity) return bfail(b, CEM_E_ARG, "dataset capacity exceeded");
+      const float cap = c->scene.time_weight * c->scene.dt * (float)c->scene.horizon;
+      BHIPCHK(b, launch_pack_dataset(desc_of(c, c->Z, c->pop, c->cost, c->tier, c->pose), cap, X_dev + n * D,
+                                     Y_dev + n * 8, s));
+      n += c->pop;
+    }
+  }
+  BHIPCHK(b, hipStreamSynchronize(s));
+  *n_out = n;
   return CEM_OK;
 }
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/cemtamp.h"
 
 namespace cem {
@@ -52,6 +54,8 @@ hipError_t launch_instance_draw(const cem_scene &sc, uint64_t seed, uint32_t ins
 hipError_t launch_sample(uint64_t seed, uint32_t inst, int32_t iter, const DevState *st, int pop, int D, float *Z,
                          hipStream_t s);
 hipError_t launch_sample_batch(const InstDesc *insts, int n_inst, int max_pop, hipStream_t s);
+hipError_t launch_mlp_init(uint64_t seed, const long *w0, const long *nw, const int *fan_in, long n_params,
+                           float *P, hipStream_t s);
 hipError_t launch_factor(DevState *st, hipStream_t s);
 hipError_t launch_select_refit(DevState *st, const float *Z, const float *cost, const uint8_t *tier, int pop,
                                int32_t *elite_idx, int32_t *sel_info, float *stats, int stats_cap,
@@ -60,5 +64,21 @@ hipError_t launch_select_refit_batch(const InstDesc *insts, int n_inst, int stat
 hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s);
 hipError_t launch_rollout_batch(const InstDesc *insts, const WorkItem *items, int n_items, int *queue, int grid,
                                 hipStream_t s);
+hipError_t launch_pack_dataset(const InstDesc &d, float cost_cap, float *X, float *Y, hipStream_t s);
 
 }  // namespace cem
+
+// Host-side context of one CE problem (the opaque cem_ctx of the ABI).
+struct cem_ctx {
+  cem_scene scene;
+  int D = 0, pop = 0, n_elite = 0, cov_mode = 0;
+  uint64_t seed = 0;
+  uint32_t inst = 0;
+  int device = 0;
+  cem::DevState *st = nullptr;
+  float *Z = nullptr, *cost = nullptr, *pose = nullptr, *stats = nullptr;
+  uint8_t *tier = nullptr;
+  hipStream_t own = nullptr;
+  hipGraphExec_t iter_graph = nullptr;
+  std::string err;
+};

@@ -1,0 +1,834 @@
+// Learned surrogate for candidate screening: a 16 -> 256 -> 256 -> 256 -> 8
+// perceptron (GELU, tanh form) predicting a plan's cost and final object pose
+// from its controller parameters, trained on rollouts the simulator produced.
+// Not part of the paper's method; its limitation paragraph (full rollouts are
+// expensive) motivates it: CE samples a 16x larger population, the network
+// ranks it, and only the most promising candidates are simulated in full -
+// the simulation stays the judge of every cost that enters the refit.
+//
+// All matrix products run on the MFMA units: BF16 operands, FP32
+// accumulation (v_mfma_f32_16x16x16_bf16), 64x64 output tiles per workgroup
+// of four waves, each wave a 32x32 quadrant of 2x2 MFMA tiles, the K
+// dimension staged through LDS 16 at a time; bias, GELU and its derivative are
+// fused into the epilogue.  Master weights and Adam moments are FP32; the
+// BF16 copy of the weights is refreshed by the Adam kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cem {
+namespace {
+
+constexpr int IN = 16, HID = 256, OUT = 8, NL = 4;
+constexpr int DIMS[NL + 1] = {IN, HID, HID, HID, OUT};
+
+__host__ __device__ constexpr long w_off(int l) {
+  long o = 0;
+  for (int k = 0; k < l; ++k) o += (long)DIMS[k] * DIMS[k + 1] + DIMS[k + 1];
+  return o;
+}
+__host__ __device__ constexpr long b_off(int l) { return w_off(l) + (long)DIMS[l] * DIMS[l + 1]; }
+constexpr long N_PARAMS = w_off(NL);
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (inf/nan kept).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float gelu(float x) {
+  const float c = 0.7978845608028654f;  // sqrt(2/pi)
+  return 0.5f * x * (1.0f + tanhf(c * (x + 0.044715f * x * x * x)));
+}
+__device__ __forceinline__ float gelu_grad(float x) {
+  const float c = 0.7978845608028654f;
+  const float t = tanhf(c * (x + 0.044715f * x * x * x));
+  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * x * x);
+}
+
+enum Epi : int {
+  EPI_STORE = 0,      // C = acc (fp32)
+  EPI_BIAS = 1,       // C = acc + bias[n] (fp32)
+  EPI_BIAS_GELU = 2,  // Z = acc + bias[n] (fp32, optional), H = bf16(gelu(Z))
+  EPI_DGELU = 3       // dZ = acc * gelu'(Zin[m][n]): fp32 (optional) and bf16
+};
+
+struct GemmArgs {
+  const uint16_t *A;  // A(m, k) = A[m * a_m + k * a_k]
+  long a_m, a_k;
+  const uint16_t *B;  // B(k, n) = B[k * b_k + n * b_n]
+  long b_k, b_n;
+  int M, N, K;
+  int epi;
+  const float *bias;  // [N]
+  const float *Zin;   // [M x N] (DGELU)
+  float *C;           // fp32 out, C[m * ldc + n]
+  uint16_t *H;        // bf16 out, H[m * ldc + n]
+  int ldc;
+};
+
+// 64x64 tile of C per workgroup (256 threads = 4 waves, 32x32 each).
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+  __shared__ uint16_t As[64][16 + 4];
+  __shared__ uint16_t Bs[16][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    // stage A (64x16) and B (16x64): 4 elements per thread each, zero outside
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid * 4 + e;
+      const int am = idx >> 4, ak = idx & 15;
+      const int m = m0 + am, k = k0 + ak;
+      As[am][ak] = (m < g.M && k < g.K) ? g.A[(long)m * g.a_m + (long)k * g.a_k] : (uint16_t)0;
+      const int bk = idx >> 6, bn = idx & 63;
+      const int kk = k0 + bk, n = n0 + bn;
+      Bs[bk][bn] = (kk < g.K && n < g.N) ? g.B[(long)kk * g.b_k + (long)n * g.b_n] : (uint16_t)0;
+    }
+    __syncthreads();
+    const int r = lane & 15, q = lane >> 4;
+    bf16x4 af[2], bfr[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) af[i][t] = (short)As[wm + 16 * i + r][4 * q + t];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bfr[j][t] = (short)Bs[4 * q + t][wn + 16 * j + r];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  // lane holds D[4q + t][r] of each 16x16 tile
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int m = m0 + wm + 16 * i + 4 * q + t, n = n0 + wn + 16 * j + r;
+        if (m >= g.M || n >= g.N) continue;
+        const long o = (long)m * g.ldc + n;
+        float v = acc[i][j][t];
+        if (g.epi == EPI_STORE) {
+          g.C[o] = v;
+        } else if (g.epi == EPI_BIAS) {
+          g.C[o] = v + g.bias[n];
+        } else if (g.epi == EPI_BIAS_GELU) {
+          v += g.bias[n];
+          if (g.C) g.C[o] = v;
+          g.H[o] = f2bf(gelu(v));
+        } else {
+          v *= gelu_grad(g.Zin[o]);
+          if (g.C) g.C[o] = v;
+          g.H[o] = f2bf(v);
+        }
+      }
+}
+
+hipError_t gemm(const GemmArgs &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.N + 63) / 64, (g.M + 63) / 64), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// ---- small elementwise / reduction kernels ----
+
+__global__ void fill_kernel(float *p, long n, float v) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// x -> bf16((x - mean) / std), n x 16
+__global__ void norm_in_kernel(const float *__restrict__ X, int n, const float *__restrict__ mean,
+                               const float *__restrict__ sd, uint16_t *__restrict__ Xn) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n * IN) return;
+  const int c = (int)(i % IN);
+  Xn[i] = f2bf((X[i] - mean[c]) / sd[c]);
+}
+
+// y = yn * std + mean, n x 8
+__global__ void denorm_out_kernel(const float *__restrict__ Yn, int n, const float *__restrict__ mean,
+                                  const float *__restrict__ sd, float *__restrict__ Y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n * OUT) return;
+  const int c = (int)(i % OUT);
+  Y[i] = Yn[i] * sd[c] + mean[c];
+}
+
+// dL/dy_n for the mean squared error on normalised targets, its BF16 copy, and
+// the per-row squared error (summed by the loss kernel).
+__global__ void mse_grad_kernel(const float *__restrict__ Yn, const float *__restrict__ T, int n,
+                                const float *__restrict__ mean, const float *__restrict__ sd,
+                                float *__restrict__ dY, uint16_t *__restrict__ dYb, float *__restrict__ sq) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n * OUT) return;
+  const int c = (int)(i % OUT);
+  const float e = Yn[i] - (T[i] - mean[c]) / sd[c];
+  const float g = 2.0f * e / ((float)n * (float)OUT);
+  dY[i] = g;
+  dYb[i] = f2bf(g);
+  sq[i] = e * e;
+}
+
+// Deterministic sum of v[0..n) / scale into *out (one workgroup).
+__global__ void __launch_bounds__(1024) sum_kernel(const float *__restrict__ v, long n, float scale,
+                                                   float *__restrict__ out) {
+  __shared__ double part[1024];
+  double s = 0.0;
+  for (long i = threadIdx.x; i < n; i += 1024) s += (double)v[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = (float)(part[0] / (double)scale);
+}
+
+// Column sums (bias gradients): out[c] = sum_r M[r * cols + c], one thread per column.
+__global__ void colsum_kernel(const float *__restrict__ M, int rows, int cols, float *__restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.0f;
+  for (int r = 0; r < rows; ++r) s += M[(long)r * cols + c];
+  out[c] = s;
+}
+
+// Adam (Kingma & Ba) with bias correction; refreshes the BF16 weight copy.
+__global__ void adam_kernel(float *__restrict__ P, const float *__restrict__ G, float *__restrict__ m,
+                            float *__restrict__ v, uint16_t *__restrict__ Pb, long n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = G[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * g;
+  const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float p = P[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  P[i] = p;
+  Pb[i] = f2bf(p);
+}
+
+__global__ void to_bf16_kernel(const float *__restrict__ P, uint16_t *__restrict__ Pb, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Pb[i] = f2bf(P[i]);
+}
+
+// Mean and standard deviation of each column of M (rows x cols), FP64 sums.
+__global__ void colstats_kernel(const float *__restrict__ M, long rows, int cols, float *__restrict__ mean,
+                                float *__restrict__ sd) {
+  const int c = blockIdx.x;
+  __shared__ double s1[256], s2[256];
+  double a = 0.0, b = 0.0;
+  for (long r = threadIdx.x; r < rows; r += 256) {
+    const double x = M[r * cols + c];
+    a += x;
+    b += x * x;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mu = s1[0] / (double)rows;
+    const double var = s2[0] / (double)rows - mu * mu;
+    mean[c] = (float)mu;
+    sd[c] = (float)sqrt(var > 1e-12 ? var : 1e-12);
+  }
+}
+
+// Training minibatch: rows (a * (j0 + r) + c) mod N of X and Y (an affine
+// permutation of the dataset, a coprime to N).
+__global__ void gather_batch_kernel(const float *__restrict__ X, const float *__restrict__ Y, long N, long a, long c,
+                                    long j0, int rows, float *__restrict__ Xb, float *__restrict__ Yb) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)rows * (IN + OUT)) return;
+  const long r = i / (IN + OUT);
+  const int col = (int)(i % (IN + OUT));
+  // a, j0 + r < N <= 2^24 (checked on the host), so the product fits in 64 bits
+  const long src = (long)(((unsigned long long)a * (unsigned long long)(j0 + r) + (unsigned long long)c) %
+                          (unsigned long long)N);
+  if (col < IN) Xb[r * IN + col] = X[src * IN + col];
+  else Yb[r * OUT + (col - IN)] = Y[src * OUT + (col - IN)];
+}
+
+// ---- screening -------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t ordered(float c) {
+  if (c != c) c = __int_as_float(0x7F800000);
+  if (c == 0.0f) c = 0.0f;
+  const uint32_t b = __float_as_uint(c);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Screening key of candidate i: (goal predicted to fail, predicted cost, i).
+// The goal test is the plan's psi_g (object on the goal table's top face)
+// applied to the predicted final pose; without a goal table it always holds.
+__global__ void screen_keys_kernel(const float *__restrict__ Y, int n, const DevState *__restrict__ st,
+                                   uint64_t *__restrict__ keys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const cem_scene &sc = st->scene;
+  const float *y = Y + (long)i * OUT;
+  uint64_t miss = 0;
+  if (sc.kind == CEM_SCENE_PICKPLACE && sc.goal_static >= 0 && sc.goal_static < sc.n_static) {
+    const int b = sc.goal_static;
+    const float top = sc.st_center[b][2] + sc.st_half[b][2];
+    const bool goal = fabsf(y[1] - sc.st_center[b][0]) <= sc.st_half[b][0] &&
+                      fabsf(y[2] - sc.st_center[b][1]) <= sc.st_half[b][1] && y[3] >= top - sc.obj_half[2] &&
+                      y[3] <= top + 3.0f * sc.obj_half[2];
+    miss = goal ? 0 : 1;
+  }
+  keys[i] = (miss << 62) | ((uint64_t)ordered(y[0]) << 30) | (uint64_t)i;
+}
+
+// The k smallest of n unique keys, listed in index order: an 8-pass MSB radix
+// select of the k-th key with LDS histograms, then an order-preserving
+// compaction (per-thread contiguous chunks, block prefix sum).  One workgroup.
+__global__ void __launch_bounds__(1024) topk_kernel(const uint64_t *__restrict__ keys, int n, int k,
+                                                    int32_t *__restrict__ sel) {
+  __shared__ unsigned hist[256];
+  __shared__ unsigned long long prefix_s, mask_s;
+  __shared__ int rank_s;
+  __shared__ int scan[1024];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    prefix_s = 0;
+    mask_s = 0;
+    rank_s = k;
+  }
+  __syncthreads();
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+    const unsigned long long prefix = prefix_s, mask = mask_s;
+    for (int i = tid; i < n; i += 1024) {
+      const unsigned long long key = keys[i];
+      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int rank = rank_s;
+      unsigned cum = 0;
+      for (int b = 0; b < 256; ++b) {
+        if (cum + hist[b] >= (unsigned)rank) {
+          prefix_s = prefix | ((unsigned long long)b << shift);
+          rank_s = rank - (int)cum;
+          break;
+        }
+        cum += hist[b];
+      }
+      mask_s = mask | (255ull << shift);
+    }
+    __syncthreads();
+  }
+  const unsigned long long thr = prefix_s;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = tid * chunk, hi = min(n, lo + chunk);
+  int cnt = 0;
+  for (int i = lo; i < hi; ++i) cnt += keys[i] <= thr ? 1 : 0;
+  scan[tid] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan (Hillis-Steele)
+    const int v = tid >= off ? scan[tid - off] : 0;
+    __syncthreads();
+    scan[tid] += v;
+    __syncthreads();
+  }
+  int out = scan[tid] - cnt;
+  for (int i = lo; i < hi; ++i)
+    if (keys[i] <= thr && out < k) sel[out++] = i;
+}
+
+__global__ void gather_rows_kernel(const float *__restrict__ Z, int D, const float *__restrict__ Y,
+                                   const int32_t *__restrict__ sel, int k, float *__restrict__ Zs,
+                                   float *__restrict__ Ys) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  const long s = sel[j];
+  for (int d = 0; d < D; ++d) Zs[(long)j * D + d] = Z[s * D + d];
+  if (Ys)
+    for (int c = 0; c < OUT; ++c) Ys[(long)j * OUT + c] = Y[s * OUT + c];
+}
+
+// Surrogate error of one screened iteration: mean |predicted - simulated| cost
+// over the simulated rows with a finite cost.
+__global__ void __launch_bounds__(256) screen_error_kernel(const float *__restrict__ pred, const float *__restrict__ cost,
+                                                           int k, const DevState *__restrict__ st,
+                                                           float *__restrict__ err, int cap) {
+  __shared__ double s1[256], s2[256];
+  double a = 0.0, b = 0.0;
+  for (int j = threadIdx.x; j < k; j += 256) {
+    const float c = cost[j];
+    if (isfinite(c)) {
+      a += fabs((double)pred[(long)j * OUT] - (double)c);
+      b += 1.0;
+    }
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  const int it = st->iter;  // read before the refit of this iteration advances it
+  if (threadIdx.x == 0 && it >= 0 && it < cap) err[it] = s2[0] > 0.0 ? (float)(s1[0] / s2[0]) : -1.0f;
+}
+
+}  // namespace
+}  // namespace cem
+
+// ---- host side ---------------------------------------------------------------
+
+using namespace cem;
+
+struct cem_mlp {
+  int max_rows = 0;
+  float *P = nullptr, *G = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t *Pb = nullptr;
+  float *norm = nullptr;  // x_mean[16] x_std[16] y_mean[8] y_std[8]
+  uint16_t *Xn = nullptr, *H[3] = {nullptr, nullptr, nullptr}, *dYb = nullptr, *dZb[2] = {nullptr, nullptr};
+  float *Zp[3] = {nullptr, nullptr, nullptr}, *Yn = nullptr, *dY = nullptr, *sq = nullptr, *dZf = nullptr;
+  float *Ypred = nullptr, *loss = nullptr, *Xb = nullptr, *Yb = nullptr, *Zs = nullptr, *Ps = nullptr;
+  float *err = nullptr;
+  uint64_t *keys = nullptr;
+  int32_t *sel = nullptr;
+  int step = 0;
+  hipStream_t own = nullptr;
+  hipGraphExec_t screen_graph = nullptr;
+  cem_ctx *graph_ctx = nullptr;
+  int graph_nsim = 0;
+  std::string err_text;
+};
+
+namespace {
+
+int mfail(cem_mlp *m, int code, const std::string &msg) {
+  if (m) m->err_text = msg;
+  return code;
+}
+#define MHIPCHK(m, expr)                                                                          \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return mfail(m, CEM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+unsigned blocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+GemmArgs gargs(const uint16_t *A, long a_m, long a_k, const uint16_t *B, long b_k, long b_n, int M, int N, int K,
+               int epi, const float *bias, const float *Zin, float *C, uint16_t *H, int ldc) {
+  GemmArgs g;
+  g.A = A; g.a_m = a_m; g.a_k = a_k;
+  g.B = B; g.b_k = b_k; g.b_n = b_n;
+  g.M = M; g.N = N; g.K = K; g.epi = epi;
+  g.bias = bias; g.Zin = Zin; g.C = C; g.H = H; g.ldc = ldc;
+  return g;
+}
+
+// Forward pass of n rows of raw parameters X; keeps the pre-activations when
+// `train`; leaves normalised outputs in m->Yn.
+hipError_t forward_n(cem_mlp *m, const float *X, int n, bool train, hipStream_t s) {
+  hipLaunchKernelGGL(norm_in_kernel, dim3(blocks((long)n * IN, 256)), dim3(256), 0, s, X, n, m->norm, m->norm + IN,
+                     m->Xn);
+  const uint16_t *in = m->Xn;
+  long a_m = IN;
+  for (int l = 0; l < NL; ++l) {
+    const int ni = DIMS[l], no = DIMS[l + 1];
+    const uint16_t *W = m->Pb + w_off(l);  // W[o][i]: B(k = i, n = o) = W[o * ni + i]
+    const float *bias = m->P + b_off(l);
+    GemmArgs g;
+    if (l < NL - 1)
+      g = gargs(in, a_m, 1, W, 1, ni, n, no, ni, EPI_BIAS_GELU, bias, nullptr, train ? m->Zp[l] : nullptr, m->H[l], no);
+    else
+      g = gargs(in, a_m, 1, W, 1, ni, n, no, ni, EPI_BIAS, bias, nullptr, m->Yn, nullptr, no);
+    hipError_t e = gemm(g, s);
+    if (e != hipSuccess) return e;
+    if (l < NL - 1) {
+      in = m->H[l];
+      a_m = no;
+    }
+  }
+  return hipGetLastError();
+}
+
+// Loss and gradient (into m->G) of the mean squared error on normalised targets.
+hipError_t loss_grad_n(cem_mlp *m, const float *X, const float *T, int n, hipStream_t s) {
+  hipError_t e = forward_n(m, X, n, true, s);
+  if (e != hipSuccess) return e;
+  const float *ym = m->norm + 2 * IN, *ys = m->norm + 2 * IN + OUT;
+  hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks((long)n * OUT, 256)), dim3(256), 0, s, m->Yn, T, n, ym, ys, m->dY,
+                     m->dYb, m->sq);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, s, m->sq, (long)n * OUT, (float)n * (float)OUT, m->loss);
+  // output layer
+  const uint16_t *Hin[NL] = {m->Xn, m->H[0], m->H[1], m->H[2]};
+  const uint16_t *dZ = m->dYb;
+  const float *dZf = m->dY;
+  int nz = OUT;
+  for (int l = NL - 1; l >= 0; --l) {
+    const int ni = DIMS[l];
+    // dW_l[o][i] = sum_b dZ[b][o] Hin[b][i]
+    e = gemm(gargs(dZ, 1, nz, Hin[l], ni, 1, nz, ni, n, EPI_STORE, nullptr, nullptr, m->G + w_off(l), nullptr, ni), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(nz, 256)), dim3(256), 0, s, dZf, n, nz, m->G + b_off(l));
+    if (l == 0) break;
+    // dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1})
+    uint16_t *out = m->dZb[(NL - 1 - l) & 1];
+    e = gemm(gargs(dZ, nz, 1, m->Pb + w_off(l), ni, 1, n, ni, nz, EPI_DGELU, nullptr, m->Zp[l - 1], m->dZf, out, ni), s);
+    if (e != hipSuccess) return e;
+    dZ = out;
+    dZf = m->dZf;
+    nz = ni;
+  }
+  return hipGetLastError();
+}
+
+void mlp_release(cem_mlp *m) {
+  if (m->screen_graph) (void)hipGraphExecDestroy(m->screen_graph);
+  if (m->own) (void)hipStreamDestroy(m->own);
+  void *ptrs[] = {m->P, m->G, m->m, m->v, m->Pb, m->norm, m->Xn, m->H[0], m->H[1], m->H[2], m->dYb, m->dZb[0],
+                  m->dZb[1], m->Zp[0], m->Zp[1], m->Zp[2], m->Yn, m->dY, m->sq, m->dZf, m->Ypred, m->loss,
+                  m->Xb, m->Yb, m->Zs, m->Ps, m->err, m->keys, m->sel};
+  for (void *p : ptrs) (void)hipFree(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cem_mlp_n_params(void) { return (int)N_PARAMS; }
+
+const char *cem_mlp_last_error(const cem_mlp *m) { return m ? m->err_text.c_str() : "null network"; }
+
+int cem_mlp_init(uint64_t seed, int32_t max_rows, cem_mlp **out) {
+  if (!out) return CEM_E_ARG;
+  *out = nullptr;
+  if (max_rows < 1 || max_rows > (1 << 22)) return CEM_E_ARG;
+  cem_mlp *m = new (std::nothrow) cem_mlp();
+  if (!m) return CEM_E_ALLOC;
+  m->max_rows = max_rows;
+  const size_t R = (size_t)max_rows;
+  bool ok = hipStreamCreateWithFlags(&m->own, hipStreamNonBlocking) == hipSuccess;
+  auto alloc = [&](void **p, size_t bytes) { ok = ok && hipMalloc(p, bytes) == hipSuccess; };
+  alloc((void **)&m->P, sizeof(float) * N_PARAMS);
+  alloc((void **)&m->G, sizeof(float) * N_PARAMS);
+  alloc((void **)&m->m, sizeof(float) * N_PARAMS);
+  alloc((void **)&m->v, sizeof(float) * N_PARAMS);
+  alloc((void **)&m->Pb, sizeof(uint16_t) * N_PARAMS);
+  alloc((void **)&m->norm, sizeof(float) * (2 * IN + 2 * OUT));
+  alloc((void **)&m->Xn, sizeof(uint16_t) * R * IN);
+  for (int l = 0; l < 3; ++l) {
+    alloc((void **)&m->H[l], sizeof(uint16_t) * R * HID);
+    alloc((void **)&m->Zp[l], sizeof(float) * R * HID);
+  }
+  alloc((void **)&m->dZb[0], sizeof(uint16_t) * R * HID);
+  alloc((void **)&m->dZb[1], sizeof(uint16_t) * R * HID);
+  alloc((void **)&m->dZf, sizeof(float) * R * HID);
+  alloc((void **)&m->dYb, sizeof(uint16_t) * R * OUT);
+  alloc((void **)&m->Yn, sizeof(float) * R * OUT);
+  alloc((void **)&m->dY, sizeof(float) * R * OUT);
+  alloc((void **)&m->sq, sizeof(float) * R * OUT);
+  alloc((void **)&m->Ypred, sizeof(float) * R * OUT);
+  alloc((void **)&m->loss, sizeof(float));
+  alloc((void **)&m->Xb, sizeof(float) * R * IN);
+  alloc((void **)&m->Yb, sizeof(float) * R * OUT);
+  alloc((void **)&m->Zs, sizeof(float) * R * IN);
+  alloc((void **)&m->Ps, sizeof(float) * R * OUT);
+  alloc((void **)&m->err, sizeof(float) * MAX_STATS_ITERS);
+  alloc((void **)&m->keys, sizeof(uint64_t) * R);
+  alloc((void **)&m->sel, sizeof(int32_t) * R);
+  if (!ok) {
+    mlp_release(m);
+    delete m;
+    return CEM_E_ALLOC;
+  }
+  long w0[4], nw[4];
+  int fan[4];
+  for (int l = 0; l < 4; ++l) {
+    w0[l] = w_off(l);
+    nw[l] = (long)DIMS[l] * DIMS[l + 1];
+    fan[l] = DIMS[l];
+  }
+  hipStream_t s = m->own;
+  bool k = launch_mlp_init(seed, w0, nw, fan, N_PARAMS, m->P, s) == hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks(N_PARAMS, 256)), dim3(256), 0, s, m->m, N_PARAMS, 0.0f);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks(N_PARAMS, 256)), dim3(256), 0, s, m->v, N_PARAMS, 0.0f);
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, m->norm, (long)IN, 0.0f);          // x mean 0
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, m->norm + IN, (long)IN, 1.0f);     // x std 1
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, m->norm + 2 * IN, (long)OUT, 0.0f);
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, m->norm + 2 * IN + OUT, (long)OUT, 1.0f);
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(N_PARAMS, 256)), dim3(256), 0, s, m->P, m->Pb, N_PARAMS);
+  k = k && hipStreamSynchronize(s) == hipSuccess;
+  if (!k) {
+    mlp_release(m);
+    delete m;
+    return CEM_E_HIP;
+  }
+  *out = m;
+  return CEM_OK;
+}
+
+void cem_mlp_free(cem_mlp *m) {
+  if (!m) return;
+  (void)hipStreamSynchronize(m->own);
+  mlp_release(m);
+  delete m;
+}
+
+int cem_mlp_get_params(cem_mlp *m, float *host) {
+  if (!m || !host) return CEM_E_ARG;
+  MHIPCHK(m, hipMemcpy(host, m->P, sizeof(float) * N_PARAMS, hipMemcpyDeviceToHost));
+  return CEM_OK;
+}
+
+int cem_mlp_set_params(cem_mlp *m, const float *host) {
+  if (!m || !host) return CEM_E_ARG;
+  MHIPCHK(m, hipMemcpy(m->P, host, sizeof(float) * N_PARAMS, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(N_PARAMS, 256)), dim3(256), 0, m->own, m->P, m->Pb, N_PARAMS);
+  MHIPCHK(m, hipStreamSynchronize(m->own));
+  return CEM_OK;
+}
+
+int cem_mlp_get_norm(cem_mlp *m, float *host48) {
+  if (!m || !host48) return CEM_E_ARG;
+  MHIPCHK(m, hipMemcpy(host48, m->norm, sizeof(float) * (2 * IN + 2 * OUT), hipMemcpyDeviceToHost));
+  return CEM_OK;
+}
+
+int cem_mlp_set_norm(cem_mlp *m, const float *host48) {
+  if (!m || !host48) return CEM_E_ARG;
+  for (int i = 0; i < IN; ++i)
+    if (!(host48[IN + i] > 0.0f)) return mfail(m, CEM_E_ARG, "input std must be positive");
+  for (int i = 0; i < OUT; ++i)
+    if (!(host48[2 * IN + OUT + i] > 0.0f)) return mfail(m, CEM_E_ARG, "target std must be positive");
+  MHIPCHK(m, hipMemcpy(m->norm, host48, sizeof(float) * (2 * IN + 2 * OUT), hipMemcpyHostToDevice));
+  return CEM_OK;
+}
+
+int cem_mlp_fit_norm(cem_mlp *m, const float *X_dev, const float *Y_dev, int64_t n, void *stream) {
+  if (!m || !X_dev || !Y_dev || n < 1) return CEM_E_ARG;
+  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  hipLaunchKernelGGL(colstats_kernel, dim3(IN), dim3(256), 0, s, X_dev, (long)n, IN, m->norm, m->norm + IN);
+  hipLaunchKernelGGL(colstats_kernel, dim3(OUT), dim3(256), 0, s, Y_dev, (long)n, OUT, m->norm + 2 * IN,
+                     m->norm + 2 * IN + OUT);
+  MHIPCHK(m, hipGetLastError());
+  return CEM_OK;
+}
+
+int cem_mlp_forward(cem_mlp *m, const float *X_dev, int32_t n, float *Y_dev, void *stream) {
+  if (!m) return CEM_E_ARG;
+  if (n < 0 || n > m->max_rows) return mfail(m, CEM_E_ARG, "n out of range [0, max_rows]");
+  if (n == 0) return CEM_OK;
+  if (!X_dev || !Y_dev) return mfail(m, CEM_E_ARG, "null buffer");
+  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  MHIPCHK(m, forward_n(m, X_dev, n, false, s));
+  hipLaunchKernelGGL(denorm_out_kernel, dim3(blocks((long)n * OUT, 256)), dim3(256), 0, s, m->Yn, n,
+                     m->norm + 2 * IN, m->norm + 2 * IN + OUT, Y_dev);
+  MHIPCHK(m, hipGetLastError());
+  return CEM_OK;
+}
+
+int cem_mlp_loss_grad(cem_mlp *m, const float *X_dev, const float *Y_dev, int32_t n, float *grad_dev, float *loss_dev,
+                      void *stream) {
+  if (!m) return CEM_E_ARG;
+  if (n < 1 || n > m->max_rows) return mfail(m, CEM_E_ARG, "n out of range [1, max_rows]");
+  if (!X_dev || !Y_dev) return mfail(m, CEM_E_ARG, "null buffer");
+  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  MHIPCHK(m, loss_grad_n(m, X_dev, Y_dev, n, s));
+  if (grad_dev) MHIPCHK(m, hipMemcpyAsync(grad_dev, m->G, sizeof(float) * N_PARAMS, hipMemcpyDeviceToDevice, s));
+  if (loss_dev) MHIPCHK(m, hipMemcpyAsync(loss_dev, m->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
+  return CEM_OK;
+}
+
+int cem_mlp_train_step(cem_mlp *m, const float *X_dev, const float *Y_dev, int32_t n, float lr, float *loss_dev,
+                       void *stream) {
+  int rc = cem_mlp_loss_grad(m, X_dev, Y_dev, n, nullptr, loss_dev, stream);
+  if (rc != CEM_OK) return rc;
+  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  m->step += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = (float)(1.0 - std::pow(b1, m->step)), c2 = (float)(1.0 - std::pow(b2, m->step));
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks(N_PARAMS, 256)), dim3(256), 0, s, m->P, m->G, m->m, m->v, m->Pb,
+                     N_PARAMS, lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+  MHIPCHK(m, hipGetLastError());
+  return CEM_OK;
+}
+
+int cem_mlp_train(cem_mlp *m, const float *X_dev, const float *Y_dev, int64_t n, int32_t batch, int32_t epochs,
+                  float lr, uint64_t seed, float *epoch_loss_host) {
+  if (!m || !X_dev || !Y_dev) return CEM_E_ARG;
+  if (n < 1 || n > (1 << 24) || batch < 1 || batch > m->max_rows || epochs < 0)
+    return mfail(m, CEM_E_ARG, "bad sizes");
+  hipStream_t s = m->own;
+  const long steps = (long)(n / batch);
+  if (steps < 1) return mfail(m, CEM_E_ARG, "dataset smaller than one batch");
+  std::vector<float> losses(steps);
+  float *dloss = nullptr;
+  MHIPCHK(m, hipMalloc(&dloss, sizeof(float) * steps));
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  auto next = [&]() {  // splitmix64 for the epoch's shuffle parameters
+    x += 0x9E3779B97F4A7C15ull;
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto gcd = [](uint64_t a, uint64_t b) {
+    while (b) {
+      const uint64_t t = a % b;
+      a = b;
+      b = t;
+    }
+    return a;
+  };
+  int rc = CEM_OK;
+  for (int e = 0; e < epochs && rc == CEM_OK; ++e) {
+    uint64_t a = next() % (uint64_t)n;
+    while (a == 0 || gcd(a, (uint64_t)n) != 1) a = (a + 1) % (uint64_t)n;
+    const uint64_t c = next() % (uint64_t)n;
+    for (long j = 0; j < steps && rc == CEM_OK; ++j) {
+      hipLaunchKernelGGL(gather_batch_kernel, dim3(blocks((long)batch * (IN + OUT), 256)), dim3(256), 0, s, X_dev,
+                         Y_dev, (long)n, (long)a, (long)c, j * (long)batch, batch, m->Xb, m->Yb);
+      rc = cem_mlp_train_step(m, m->Xb, m->Yb, batch, lr, dloss + j, s);
+    }
+    if (rc == CEM_OK && epoch_loss_host) {
+      if (hipMemcpyAsync(losses.data(), dloss, sizeof(float) * steps, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        rc = mfail(m, CEM_E_HIP, "loss copy");
+        break;
+      }
+      double acc = 0.0;
+      for (float v : losses) acc += v;
+      epoch_loss_host[e] = (float)(acc / (double)steps);
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(dloss);
+  return rc;
+}
+
+// One screening pass: sample the context's population (iteration iter, or the
+// device counter when iter < 0), predict every candidate, keep the n_sim with
+// the smallest (goal predicted to fail, predicted cost, index) keys, written
+// in index order to Zsim (n_sim x D) and their predictions to pred (n_sim x 8).
+static int screen_into(cem_ctx *c, cem_mlp *m, int32_t iter, int32_t n_sim, float *Zsim, float *pred, hipStream_t s) {
+  hipError_t e = launch_sample(c->seed, c->inst, iter, c->st, c->pop, c->D, c->Z, s);
+  if (e != hipSuccess) return mfail(m, CEM_E_HIP, "sample");
+  e = forward_n(m, c->Z, c->pop, false, s);
+  if (e != hipSuccess) return mfail(m, CEM_E_HIP, "forward");
+  hipLaunchKernelGGL(denorm_out_kernel, dim3(blocks((long)c->pop * OUT, 256)), dim3(256), 0, s, m->Yn, c->pop,
+                     m->norm + 2 * IN, m->norm + 2 * IN + OUT, m->Ypred);
+  hipLaunchKernelGGL(screen_keys_kernel, dim3(blocks(c->pop, 256)), dim3(256), 0, s, m->Ypred, c->pop, c->st, m->keys);
+  hipLaunchKernelGGL(topk_kernel, dim3(1), dim3(1024), 0, s, m->keys, c->pop, n_sim, m->sel);
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks(n_sim, 256)), dim3(256), 0, s, c->Z, c->D, m->Ypred, m->sel,
+                     n_sim, Zsim, pred);
+  e = hipGetLastError();
+  return e == hipSuccess ? CEM_OK : mfail(m, CEM_E_HIP, "screen launch");
+}
+
+int cem_screen(cem_ctx *c, cem_mlp *m, int32_t iter, int32_t n_sim, float *Zsim_dev, float *pred_dev, void *stream) {
+  if (!c || !m) return CEM_E_ARG;
+  if (c->D != IN) return mfail(m, CEM_E_ARG, "the network takes 16 parameters");
+  if (c->pop > m->max_rows) return mfail(m, CEM_E_ARG, "population exceeds the network's max_rows");
+  if (n_sim < 1 || n_sim > c->pop) return mfail(m, CEM_E_ARG, "n_sim out of range [1, pop]");
+  if (!Zsim_dev || iter < 0) return mfail(m, CEM_E_ARG, "null Zsim or iter < 0");
+  return screen_into(c, m, iter, n_sim, Zsim_dev, pred_dev, stream ? (hipStream_t)stream : m->own);
+}
+
+int plan_solve_screened(cem_ctx *c, cem_mlp *m, int32_t iters, int32_t n_sim, cem_result *res, float *stats_host,
+                        float *surrogate_err_host, void *stream) {
+  if (!c || !m || !res) return CEM_E_ARG;
+  if (c->D != IN) return mfail(m, CEM_E_ARG, "the network takes 16 parameters");
+  if (c->pop > m->max_rows) return mfail(m, CEM_E_ARG, "population exceeds the network's max_rows");
+  if (n_sim < 1 || n_sim > c->pop || n_sim < c->n_elite) return mfail(m, CEM_E_ARG, "n_sim out of range [n_elite, pop]");
+  if (iters < 0) return mfail(m, CEM_E_ARG, "iters < 0");
+  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  int32_t it0 = 0;
+  MHIPCHK(m, hipMemcpyAsync(&it0, &c->st->iter, sizeof it0, hipMemcpyDeviceToHost, s));
+  MHIPCHK(m, hipStreamSynchronize(s));
+  if (it0 + iters > MAX_STATS_ITERS) return mfail(m, CEM_E_ARG, "iteration counter would exceed 4096");
+  if (!m->screen_graph || m->graph_ctx != c || m->graph_nsim != n_sim) {
+    if (m->screen_graph) (void)hipGraphExecDestroy(m->screen_graph);
+    m->screen_graph = nullptr;
+    hipGraph_t g = nullptr;
+    MHIPCHK(m, hipStreamBeginCapture(m->own, hipStreamCaptureModeThreadLocal));
+    int rc = screen_into(c, m, -1, n_sim, m->Zs, m->Ps, m->own);
+    InstDesc d{};
+    d.st = c->st; d.Z = m->Zs; d.cost = c->cost; d.tier = c->tier; d.pose = nullptr; d.stats = c->stats;
+    d.kind = c->scene.kind; d.pop = n_sim; d.D = c->D; d.iters = 1 << 30;
+    hipError_t e2 = launch_rollout_single(d, nullptr, 0, m->own);
+    hipLaunchKernelGGL(screen_error_kernel, dim3(1), dim3(256), 0, m->own, m->Ps, c->cost, n_sim, c->st, m->err,
+                       MAX_STATS_ITERS);
+    hipError_t e3 = launch_select_refit(c->st, m->Zs, c->cost, c->tier, n_sim, nullptr, nullptr, c->stats,
+                                        MAX_STATS_ITERS, 1, m->own);
+    hipError_t e4 = hipStreamEndCapture(m->own, &g);
+    if (rc != CEM_OK || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return mfail(m, CEM_E_HIP, "graph capture of the screened CE iteration failed");
+    }
+    hipError_t e5 = hipGraphInstantiate(&m->screen_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e5 != hipSuccess) {
+      m->screen_graph = nullptr;
+      return mfail(m, CEM_E_HIP, "hipGraphInstantiate");
+    }
+    m->graph_ctx = c;
+    m->graph_nsim = n_sim;
+  }
+  for (int j = 0; j < iters; ++j) MHIPCHK(m, hipGraphLaunch(m->screen_graph, s));
+  DevState h;
+  MHIPCHK(m, hipMemcpyAsync(&h, c->st, sizeof h, hipMemcpyDeviceToHost, s));
+  if (stats_host && iters > 0)
+    MHIPCHK(m, hipMemcpyAsync(stats_host, c->stats + (size_t)it0 * CEM_STATS_COLS,
+                              sizeof(float) * iters * CEM_STATS_COLS, hipMemcpyDeviceToHost, s));
+  if (surrogate_err_host && iters > 0)
+    MHIPCHK(m, hipMemcpyAsync(surrogate_err_host, m->err + it0, sizeof(float) * iters, hipMemcpyDeviceToHost, s));
+  MHIPCHK(m, hipStreamSynchronize(s));
+  std::memset(res, 0, sizeof *res);
+  res->dim = c->D;
+  for (int d = 0; d < c->D; ++d) {
+    res->best_z[d] = h.best_z[d];
+    res->mu[d] = h.mu[d];
+  }
+  for (int t = 0; t < c->D * c->D; ++t) res->cov[t] = h.S[t];
+  res->best_cost = h.best_cost;
+  res->best_tier = h.best_tier;
+  res->iters_done = h.iter;
+  return h.factor_status ? CEM_E_NUMERIC : CEM_OK;
+}
+
+}  // extern "C"

@@ -60,6 +60,39 @@ __global__ void reset_counter_kernel(int *q) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
 }
 
+// Training pairs of one instance: X row = its parameter row, Y row = (cost,
+// final object position, orientation with w >= 0).  A diverged rollout (non
+// finite cost or pose) is recorded with cost_cap and the object's start pose.
+__global__ void pack_dataset_kernel(const float *__restrict__ Z, const float *__restrict__ cost,
+                                    const float *__restrict__ pose, int pop, int D, float cost_cap,
+                                    const DevState *__restrict__ st, float *__restrict__ X, float *__restrict__ Y) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= pop) return;
+  for (int d = 0; d < D; ++d) X[(long)r * D + d] = Z[(long)r * D + d];
+  float p[7];
+  bool fin = isfinite(cost[r]);
+  for (int j = 0; j < 7; ++j) {
+    p[j] = pose[(long)r * 7 + j];
+    fin = fin && isfinite(p[j]);
+  }
+  const float s = p[3] < 0.0f ? -1.0f : 1.0f;
+  float *y = Y + (long)r * 8;
+  if (fin) {
+    y[0] = cost[r];
+    for (int j = 0; j < 3; ++j) y[1 + j] = p[j];
+    for (int j = 3; j < 7; ++j) y[1 + j] = s * p[j];
+  } else {
+    y[0] = cost_cap;
+    y[1] = st->scene.obj_pos0[0];
+    y[2] = st->scene.obj_pos0[1];
+    y[3] = st->scene.obj_pos0[2];
+    y[4] = 1.0f;
+    y[5] = 0.0f;
+    y[6] = 0.0f;
+    y[7] = 0.0f;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s) {
@@ -71,6 +104,13 @@ hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_step
   else
     hipLaunchKernelGGL(rollout_items_kernel<false>, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items,
                        nullptr, 0, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_dataset(const InstDesc &d, float cost_cap, float *X, float *Y, hipStream_t s) {
+  if (d.pop <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pack_dataset_kernel, dim3((d.pop + 255) / 256), dim3(256), 0, s, d.Z, d.cost, d.pose, d.pop, d.D,
+                     cost_cap, d.st, X, Y);
   return hipGetLastError();
 }
 

@@ -139,6 +139,35 @@ __global__ void __launch_bounds__(256) sample_batch_kernel(const InstDesc *__res
   sample_row(d.st->seed, d.st->inst_id, (uint32_t)d.st->iter, d.st, d.D, i, const_cast<float *>(d.Z));
 }
 
+// He-normal initial weights of the surrogate network: entry p of a weight
+// matrix with fan-in f is eps_p sqrt(2 / f), eps_p the normal p % 4 of Philox
+// stream 2 block p / 4 (sample 0, iteration 0, instance 0), computed in FP64
+// and rounded once to FP32; biases are zero.  Layers: [w0, w0 + nw) weights.
+struct InitLayers {
+  long w0[4], nw[4];
+  int fan_in[4];
+  long n_params;
+};
+__global__ void __launch_bounds__(256) mlp_init_kernel(uint64_t seed, InitLayers L, float *__restrict__ P) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= L.n_params) return;
+  int layer = -1;
+  for (int l = 0; l < 4; ++l)
+    if (p >= L.w0[l] && p < L.w0[l] + L.nw[l]) layer = l;
+  if (layer < 0) {
+    P[p] = 0.0f;
+    return;
+  }
+  const U4 w = draw(seed, 2u, (uint32_t)(p / 4), 0u, 0u, 0u);
+  const uint32_t ws[4] = {w.a, w.b, w.c, w.d};
+  const int h = (int)(p % 4) / 2;
+  const float r = sqrtf(-2.0f * ln_f32(unit(ws[2 * h])));
+  float sn, cs;
+  sincos_2pi(unit(ws[2 * h + 1]), sn, cs);
+  const float e = (p % 2 == 0) ? r * cs : r * sn;
+  P[p] = (float)((double)e * sqrt(2.0 / (double)L.fan_in[layer]));
+}
+
 // Per-instance draws on the scene stream (tag 1): the push goal
 // g = start + rho (cos phi, sin phi), rho and phi uniform in their ranges.
 __global__ void instance_draw_kernel(cem_scene sc, uint64_t seed, uint32_t inst, DevState *st) {
@@ -157,6 +186,19 @@ hipError_t launch_sample(uint64_t seed, uint32_t inst, int32_t iter, const DevSt
                          hipStream_t s) {
   const int bs = 256;
   hipLaunchKernelGGL(sample_kernel, dim3((pop + bs - 1) / bs), dim3(bs), 0, s, seed, inst, iter, st, pop, D, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_init(uint64_t seed, const long *w0, const long *nw, const int *fan_in, long n_params,
+                           float *P, hipStream_t s) {
+  InitLayers L;
+  for (int l = 0; l < 4; ++l) {
+    L.w0[l] = w0[l];
+    L.nw[l] = nw[l];
+    L.fan_in[l] = fan_in[l];
+  }
+  L.n_params = n_params;
+  hipLaunchKernelGGL(mlp_init_kernel, dim3((unsigned)((n_params + 255) / 256)), dim3(256), 0, s, seed, L, P);
   return hipGetLastError();
 }
 
