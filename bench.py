@@ -26,12 +26,15 @@ DEFAULT_WORKLOAD = "pickplace"
 # HBM traffic per rollout launch measured with rocprofv3 (FETCH_SIZE + WRITE_SIZE,
 # scaled by the copy-kernel calibration), keyed by workload; valid only while
 # the rollout sources hash to the recorded value.
-MEASURED_TRAFFIC = {}
-
-ROLLOUT_SOURCES = {
-    "push": ["rollout_push.hip", "rigid.hpp", "devmath.hpp"],
-    "pickplace": ["rollout_robot.hip", "rigid.hpp", "devmath.hpp"],
+MEASURED_TRAFFIC = {
+    # rollout of 1024 pick-and-place plans over 2000 steps: FETCH_SIZE 1009.125 KiB x 2.0
+    # + WRITE_SIZE 97.0 KiB x 1.0 (a 256 MiB copy reads as 131083.5 / 262144 KiB)
+    "pickplace": {"bytes_per_launch": int((1009.125 * 2.0 + 97.0 * 1.0) * 1024), "src_hash": "6a466a80a1c2b2f8"},
 }
+
+_KERNEL_FILES = ["rollout.hip", "push_env.hpp", "pickplace_env.hpp", "robot_dyn.hpp", "rigid.hpp", "devmath.hpp",
+                 "internal.hpp"]
+ROLLOUT_SOURCES = {"push": _KERNEL_FILES, "pickplace": _KERNEL_FILES}
 
 
 def _src_hash(workload):
@@ -84,17 +87,26 @@ def bench_batch(a):
         for _ in range(a.warmup):
             B.step()
         torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
     with Batch(insts) as B:
-        tune = B.autotune()           # untimed; also the rollout pass duration (HIP events on its stream)
+        tune = B.autotune()           # untimed
         torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
         t0 = time.perf_counter()
-        B.solve(K)
+        for j in range(K):            # one CE iteration of every instance per replay
+            evs[j][0].record(stream)
+            B.step(stream)
+            evs[j][1].record(stream)
+        torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        step_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
     env_steps_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"] for i in insts)
     fps = {k: workloads.load(k).get("measurement", {}).get("flops_per_env_step") for k in ("push", "pickplace")}
     flops_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"]
                      * (fps[i["workload"]["scene"]["kind"]] or 0.0) for i in insts)
-    roll_s = tune["rollout_us"] / 1e6
+    # the replayed step is sampling + the rollout launch + refit; the rollout is > 99.9 % of it,
+    # so the step's event time bounds the rollout kernel's duration from above
+    roll_s = sum(step_ms) / len(step_ms) / 1e3
     achieved = flops_iter / roll_s / 1e12 if roll_s > 0 else None
     out = {
         "metric": "env-steps/s (CE iterations/s alongside)",
@@ -105,7 +117,7 @@ def bench_batch(a):
         "dtype": "f32 (FP64 refit and Cholesky)", "data": "synthetic (seeded instances, scenes and Philox samples)",
         "config": {"workload": "batch", "instances": len(insts), "env_steps_per_iter": env_steps_iter,
                    "autotune": tune},
-        "rollout_kernel_ms": roll_s * 1e3,
+        "step_event_ms": roll_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": None,
                      "flops_per_env_step": fps},
@@ -131,12 +143,24 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy three times (the known-size "
+                         "reference for the HBM byte counters) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own "
               "share of the population independently); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if a.copy_calibration:
+        import torch
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "launches": 3}))
+        return
     if a.workload == "batch":
         bench_batch(a)
         return

@@ -157,8 +157,10 @@ int cem_sample(cem_ctx *c, int32_t iter, float *Z_dev, void *stream);
 int rollout_batch(cem_ctx *c, const float *Z_dev, int32_t pop, float *cost_dev, uint8_t *tier_dev,
                   float *pose_dev, void *stream);
 
-/* Same dynamics, recording the free object's state (p q v w, 13 floats)
- * after each of the first n_steps control steps: trace_dev[pop][n_steps][13]. */
+/* Same dynamics, recording the state after each of the first n_steps control
+ * steps: trace_dev[pop][n_steps][W] with W = CEM_TRACE_FREE (13: the free
+ * object's p q v w) for the push scene and W = CEM_TRACE_ROBOT (35: object
+ * p q v w, then robot q[11] and qd[11]) for the robot scenes. */
 int rollout_trace(cem_ctx *c, const float *Z_dev, int32_t pop, int32_t n_steps, float *trace_dev, void *stream);
 
 /* Alg. 1, update step: order the samples by (tier, cost, index), NaN cost as
