@@ -32,9 +32,9 @@ MEASURED_TRAFFIC = {
     "pickplace": {"bytes_per_launch": int((1009.125 * 2.0 + 97.0 * 1.0) * 1024), "src_hash": "6a466a80a1c2b2f8"},
 }
 
-_KERNEL_FILES = ["rollout.hip", "push_env.hpp", "pickplace_env.hpp", "robot_dyn.hpp", "rigid.hpp", "devmath.hpp",
+_KERNEL_FILES = ["rollout.hip", "push_env.hpp", "robot_env.hpp", "robot_dyn.hpp", "rigid.hpp", "devmath.hpp",
                  "internal.hpp"]
-ROLLOUT_SOURCES = {"push": _KERNEL_FILES, "pickplace": _KERNEL_FILES}
+ROLLOUT_SOURCES = {"push": _KERNEL_FILES, "pickplace": _KERNEL_FILES, "movepush": _KERNEL_FILES}
 
 
 def _src_hash(workload):

@@ -102,6 +102,16 @@ typedef struct cem_scene {
   float pregrasp, finger_open, finger_closed, rest_speed;
   int32_t goal_static;
   float joint_speed_max, accel_max;
+  /* move-push (Sec. IV-A, plan pi_m&p): the push action's speed clamp
+   * [push_vmin, push_vmax] (m/s), longest push push_dmax (m) and timeout (s);
+   * the friction coefficient of every contact of the object, drawn per
+   * instance as U[obj_mu_lo, obj_mu_hi] on the scene stream when
+   * obj_mu_hi > 0 (otherwise the per-class coefficients apply); and, when
+   * goal_static < 0, the goal region psi_g: the object's centre inside the
+   * axis-aligned box goal_box_center +- goal_box_half, at rest. */
+  float push_vmin, push_vmax, push_dmax, timeout_push;
+  float obj_mu_lo, obj_mu_hi;
+  float goal_box_center[3], goal_box_half[3];
 } cem_scene;
 
 /* One CE problem (Alg. 1 inputs).  mu0 has D entries, cov0 D x D row-major
@@ -186,8 +196,10 @@ int cem_get_theta(cem_ctx *c, double *mu, double *cov);
 int cem_set_theta(cem_ctx *c, const double *mu, const double *cov);
 /* Cholesky factor currently used by cem_sample (host L[D*D]). Synchronous. */
 int cem_get_factor(cem_ctx *c, double *L);
-/* Per-instance draws (push: goal xy). Synchronous. */
-int cem_get_instance(cem_ctx *c, double *goal_xy);
+/* Per-instance scene draws (Philox scene stream, counter word 3 = instance),
+ * host draws[3] = (goal x, goal y, object friction coefficient or 0 when the
+ * scene does not draw one). Synchronous. */
+int cem_get_instance(cem_ctx *c, double *draws);
 /* Reset the best-so-far record and the iteration counter. Synchronous. */
 int cem_reset(cem_ctx *c);
 

@@ -43,6 +43,8 @@ class RefScene(ctypes.Structure):
         ("t_release", _d), ("timeout_move", _d), ("timeout_pick", _d), ("timeout_place", _d),
         ("pregrasp", _d), ("finger_open", _d), ("finger_closed", _d), ("rest_speed", _d),
         ("goal_static", _i), ("joint_speed_max", _d), ("accel_max", _d),
+        ("push_vmin", _d), ("push_vmax", _d), ("push_dmax", _d), ("timeout_push", _d),
+        ("obj_mu_lo", _d), ("obj_mu_hi", _d), ("goal_box_center", _d * 3), ("goal_box_half", _d * 3),
     ]
 
 
@@ -125,6 +127,11 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def default_threads():
+    """Host threads for the parallel oracle loops: the machine's cores, at most 16."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def param_dim(workload):
     return {"push": 3, "pickplace": 16, "movepush": 12}[workload["scene"]["kind"]]
 
@@ -182,8 +189,16 @@ def make_scene(workload):
                   "timeout_move", "timeout_pick", "timeout_place", "pregrasp", "finger_open", "finger_closed",
                   "joint_speed_max", "accel_max"):
             setattr(s, f, ct[f])
+        for f in ("push_vmin", "push_vmax", "push_dmax", "timeout_push"):
+            setattr(s, f, ct.get(f, 0.0))
         s.rest_speed = sc["rest_speed"]
         s.goal_static = sc["goal_static"]
+        gb = sc.get("goal_box")
+        if gb:
+            for k in range(3):
+                s.goal_box_center[k] = gb["center"][k]
+                s.goal_box_half[k] = gb["half"][k]
+    s.obj_mu_lo, s.obj_mu_hi = ob.get("mu", (0.0, 0.0))
     return s
 
 
@@ -239,8 +254,9 @@ def sample(seed, it, inst, pop, mu, L):
 
 
 def draw_instance(workload, seed, inst=0):
+    """Per-instance scene draws: (goal x, goal y, object friction or 0)."""
     s = make_scene(workload)
-    g = np.zeros(2, np.float64)
+    g = np.zeros(3, np.float64)
     lib().ref_draw_instance(ctypes.byref(s), seed, inst, _ptr(g))
     return g
 
@@ -255,7 +271,7 @@ def rollout(workload, seed, Z, inst=0, trace_steps=0, threads=None):
     pose = np.zeros((pop, 7), np.float64)
     tw = 13 if workload["scene"]["kind"] == "push" else 35
     trace = np.zeros((pop, trace_steps, tw), np.float64) if trace_steps else None
-    threads = threads or os.cpu_count() or 1
+    threads = threads or default_threads()
     rc = lib().ref_rollout(ctypes.byref(s), seed, inst, pop, _ptr(Z), _ptr(cost), _ptr(tier), _ptr(pose),
                            _ptr(trace) if trace is not None else None, trace_steps, threads)
     if rc != 0:
@@ -326,7 +342,7 @@ def plan_solve(workload, seed, inst=0, threads=None, iters=None, pop=None):
     mu = np.zeros(D, np.float64)
     S = np.zeros((D, D), np.float64)
     stats = np.zeros((iters, 8), np.float64)
-    threads = threads or os.cpu_count() or 1
+    threads = threads or default_threads()
     lib().ref_plan_solve(ctypes.byref(s), seed, inst, pop, cem["n_elite"], iters, cov_mode, _ptr(mu0), _ptr(cov0),
                          threads, _ptr(best_z), _ptr(best_cost), _ptr(best_tier), _ptr(mu), _ptr(S), _ptr(stats))
     return dict(best_z=best_z, best_cost=float(best_cost[0]), best_tier=int(best_tier[0]), mu=mu, S=S, stats=stats)

@@ -98,10 +98,12 @@ void ref_sample(uint64_t seed, uint32_t iter, uint32_t inst, int pop, int D, con
   for (int i = 0; i < pop; ++i) cem_sample_row(seed, (uint32_t)i, iter, inst, D, mu, L, Z + (long)i * D, nullptr);
 }
 
-void ref_draw_instance(const RefScene *s, uint64_t seed, uint32_t inst, double goal[2]) {
+// out = (goal x, goal y, object friction) of instance inst.
+void ref_draw_instance(const RefScene *s, uint64_t seed, uint32_t inst, double out[3]) {
   Instance in = draw_instance(*s, seed, inst);
-  goal[0] = in.goal[0];
-  goal[1] = in.goal[1];
+  out[0] = in.goal[0];
+  out[1] = in.goal[1];
+  out[2] = in.obj_mu;
 }
 
 // Roll out pop parameter rows; trace (optional) gets trace_steps states per env.
@@ -109,7 +111,7 @@ int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const 
                 uint8_t *tier, double *pose, double *trace, int trace_steps, int threads) {
   const int D = param_dim(*s);
   const Instance in = draw_instance(*s, seed, inst);
-  if (s->kind != SCENE_PUSH && s->kind != SCENE_PICKPLACE) return 1;
+  if (s->kind != SCENE_PUSH && s->kind != SCENE_PICKPLACE && s->kind != SCENE_MOVEPUSH) return 1;
   const int tw = s->kind == SCENE_PUSH ? TRACE_FREE : TRACE_ROBOT;
   parallel_for(pop, threads, [&](int i) {
     RolloutOut o = rollout_one(*s, in, Z + (long)i * D, trace ? trace + (long)i * trace_steps * tw : nullptr,

@@ -10,6 +10,16 @@
 // gripper enclosing the object (Eqs. 5-6 and text).  The goal psi_g holds when
 // the object rests on the top face of the goal table at T.
 //
+// Move-and-push (Sec. IV-A, plan pi_m&p):
+//   move_to(x, y, psi, v) -> push(start point, heading, distance, speed,
+//   approach height, gripper yaw)
+// The push controller reaches a start pose above and then at the start point
+// with closed fingers, moves the end effector along the push line, then opens
+// the gripper; it succeeds when the end effector is at the end of the line
+// after the release.  psi_g: the pushed block rests with its centre inside
+// the container's inner volume at T.  Every contact of the block uses the
+// block's friction coefficient, drawn per instance.
+//
 // Controllers (the paper's geometric fabrics and A* are replaced, see the
 // design notes): straight-line base reference at a commanded speed tracked by
 // joint PD; arm joint targets from damped-least-squares IK solved at action
@@ -158,7 +168,7 @@ template <class T> inline M3<T> static_rot(const RefScene &s, int k) {
   return matmul(Rz, Ry);
 }
 
-enum Act { MOVE = 0, PICK = 1, PLACE = 2 };
+enum Act { MOVE = 0, PICK = 1, PLACE = 2, PUSH = 3 };
 
 // Smooth 0 -> 1 blend of the references: x^2 (3 - 2x) on [0, 1], clamped.
 template <class T> inline T smooth(T x) {
@@ -168,7 +178,6 @@ template <class T> inline T smooth(T x) {
 
 template <class T>
 RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z, double *trace, int trace_steps) {
-  (void)inst;
   const Tree tr = tree_of(s);
   const T h = T(s.dt) / T((double)s.substeps);
   const T dt = T(s.dt);
@@ -190,11 +199,19 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
     SH[b] = V3<T>(T(s.st_half[b][0]), T(s.st_half[b][1]), T(s.st_half[b][2]));
   }
 
-  // plan: move, pick, move, place with four parameters each
-  const int acts[4] = {MOVE, PICK, MOVE, PLACE};
-  const int n_act = 4;
+  // friction of the object's contacts: the instance's draw, else the per-class values
+  const bool mu_drawn = inst.obj_mu > 0.0;
+  const double mu_obj_ground = mu_drawn ? inst.obj_mu : s.mu_ground;
+  const double mu_obj_tool = mu_drawn ? inst.obj_mu : s.mu_tool;
+
+  // plan: pick-and-place = move, pick, move, place with four parameters each;
+  // move-push = move (4 parameters), push (8 parameters)
+  const bool pnp = s.kind == SCENE_PICKPLACE;
+  const int acts[4] = {MOVE, pnp ? PICK : PUSH, MOVE, PLACE};
+  const int n_act = pnp ? 4 : 2;
+  const int n_par = pnp ? 16 : 12;
   T zp[16];
-  for (int i = 0; i < 16; ++i) zp[i] = T((double)z[i]);
+  for (int i = 0; i < 16; ++i) zp[i] = T(i < n_par ? (double)z[i] : 0.0);
 
   T q[NJ], qd[NJ];
   for (int j = 0; j < NJ; ++j) { q[j] = T(s.q0[j]); qd[j] = T(0.0); }
@@ -206,10 +223,10 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
   bool ok[4] = {false, false, false, false};
   T qref[NJ];
   for (int j = 0; j < NJ; ++j) qref[j] = q[j];
-  T qstart[NJ], qa[NJ], qb[NJ];  // interpolation anchors
+  T qstart[NJ], qa[NJ], qb[NJ], qc[NJ];  // interpolation anchors
   V3<T> ptarget;                 // EE target used in the success test
   T base_from[3], base_to[3], t_move = T(1.0);
-  T Ta = T(s.t_approach), Td = T(s.t_descend), Tl = T(s.t_lift), Tp = T(s.t_transfer);
+  T Ta = T(s.t_approach), Td = T(s.t_descend), Tl = T(s.t_lift), Tp = T(s.t_transfer), Tq = dt;
   const T Tc = T(s.t_close), Tr = T(s.t_release), qd_max = T(s.joint_speed_max);
   // phase duration: the nominal one, stretched so no arm joint reference moves faster than qd_max
   auto span = [&](const T *from, const T *to, T nominal) {
@@ -247,6 +264,31 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       Ta = span(qstart, qa, T(s.t_approach));
       Td = span(qa, qb, T(s.t_descend));
       Tl = span(qb, qa, T(s.t_lift));
+    } else if (acts[a] == PUSH) {
+      // push: EE start point ps, heading phi, distance d, speed v, approach
+      // height dz, gripper yaw gamma; top-down gripper with closed fingers.
+      // Joint targets by IK: above the start (qa), at the start (qb), at the
+      // end ps + d (cos phi, sin phi, 0) (qc); the push phase lasts d / v.
+      const T cg = r_cos(pz[7]), sg = r_sin(pz[7]);
+      M3<T> Rt;
+      Rt.m[0][0] = cg; Rt.m[0][1] = sg; Rt.m[0][2] = T(0.0);
+      Rt.m[1][0] = sg; Rt.m[1][1] = -cg; Rt.m[1][2] = T(0.0);
+      Rt.m[2][0] = T(0.0); Rt.m[2][1] = T(0.0); Rt.m[2][2] = T(-1.0);
+      const V3<T> ps(pz[0], pz[1], pz[2]);
+      const T dist = r_max(T(0.0), r_min(T(s.push_dmax), pz[4]));
+      const T vp = r_max(T(s.push_vmin), r_min(T(s.push_vmax), pz[5]));
+      const T dz = r_max(T(0.0), pz[6]);
+      const V3<T> pe = ps + dist * V3<T>(r_cos(pz[3]), r_sin(pz[3]), T(0.0));
+      for (int j = 0; j < NJ; ++j) qa[j] = q[j];
+      ik_dls(s, tr, qa, ps + V3<T>(T(0.0), T(0.0), dz), Rt);
+      for (int j = 0; j < NJ; ++j) qb[j] = qa[j];
+      ik_dls(s, tr, qb, ps, Rt);
+      for (int j = 0; j < NJ; ++j) qc[j] = qb[j];
+      ik_dls(s, tr, qc, pe, Rt);
+      ptarget = pe;
+      Ta = span(qstart, qa, T(s.t_approach));
+      Td = span(qa, qb, T(s.t_descend));
+      Tq = r_max(span(qb, qc, dist / vp), dt);
     } else {
       const T cy = r_cos(pz[3]), sy = r_sin(pz[3]);
       // top-down: EE z axis along -z, yaw psi about z: Rz(psi) Rx(pi)
@@ -283,12 +325,15 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       const bool between = ob_palm.y < q[FL] && ob_palm.y > -q[FR];
       return touch[0] && touch[1] && between && err <= T(s.ee_tol);
     }
-    const T tend = Tp + Tr;
+    const T tend = acts[a] == PUSH ? Ta + Td + Tq + Tr : Tp + Tr;
     return tau >= tend && err <= T(s.ee_tol);
   };
 
   auto timeout_of = [&](int a) -> double {
-    return acts[a] == MOVE ? s.timeout_move : (acts[a] == PICK ? s.timeout_pick : s.timeout_place);
+    return acts[a] == MOVE ? s.timeout_move
+           : acts[a] == PICK ? s.timeout_pick
+           : acts[a] == PUSH ? s.timeout_push
+                             : s.timeout_place;
   };
 
   start_action(0, 0);
@@ -325,6 +370,17 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
           qref[j] = r;
         }
         finger_cmd = tau < Ta + Td ? T(s.finger_open) : T(s.finger_closed);
+      } else if (acts[act] == PUSH) {
+        for (int c = 0; c < 3; ++c) qref[c] = qstart[c];
+        for (int j = ARM0; j < ARM0 + NARM; ++j) {
+          T r;
+          if (tau < Ta) r = qstart[j] + smooth(tau / Ta) * (qa[j] - qstart[j]);
+          else if (tau < Ta + Td) r = qa[j] + smooth((tau - Ta) / Td) * (qb[j] - qa[j]);
+          else if (tau < Ta + Td + Tq) r = qb[j] + smooth((tau - Ta - Td) / Tq) * (qc[j] - qb[j]);
+          else r = qc[j];
+          qref[j] = r;
+        }
+        finger_cmd = tau < Ta + Td + Tq ? T(s.finger_closed) : T(s.finger_open);
       } else {
         for (int c = 0; c < 3; ++c) qref[c] = qstart[c];
         for (int j = ARM0; j < ARM0 + NARM; ++j)
@@ -363,10 +419,10 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       // object on the ground
       int nc = box_plane(ob.p, oR, ohe, cs);
       for (int i = 0; i < nc; ++i)
-        add_force(W, ob.p, cs[i].x, penalty_force(cs[i], obj_vel(cs[i].x), V3<T>(), k, damp, T(s.mu_ground), eps_v));
+        add_force(W, ob.p, cs[i].x, penalty_force(cs[i], obj_vel(cs[i].x), V3<T>(), k, damp, T(mu_obj_ground), eps_v));
       // object against static boxes, both ways
       for (int b = 0; b < s.n_static; ++b) {
-        const T mu = T(s.st_ramp[b] ? s.mu_ramp : s.mu_static);
+        const T mu = T(mu_drawn ? inst.obj_mu : (s.st_ramp[b] ? s.mu_ramp : s.mu_static));
         if (!spheres_overlap(ob.p, ohe, SP[b], SH[b])) continue;
         nc = box_verts_in_box(ob.p, oR, ohe, SP[b], SR[b], SH[b], cs);
         for (int i = 0; i < nc; ++i)
@@ -385,14 +441,14 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
         const bool nearf = spheres_overlap(fc, fh, ob.p, ohe);
         nc = nearf ? box_verts_in_box(fc, Rw[j], fh, ob.p, oR, ohe, cs) : 0;
         for (int i = 0; i < nc; ++i) {
-          const V3<T> F = penalty_force(cs[i], link_vel(j, cs[i].x), obj_vel(cs[i].x), k, damp, T(s.mu_tool), eps_v);
+          const V3<T> F = penalty_force(cs[i], link_vel(j, cs[i].x), obj_vel(cs[i].x), k, damp, T(mu_obj_tool), eps_v);
           link_force(j, cs[i].x, F);
           add_force(W, ob.p, cs[i].x, -F);
           any = true;
         }
         nc = nearf ? box_verts_in_box(ob.p, oR, ohe, fc, Rw[j], fh, cs) : 0;
         for (int i = 0; i < nc; ++i) {
-          const V3<T> F = penalty_force(cs[i], obj_vel(cs[i].x), link_vel(j, cs[i].x), k, damp, T(s.mu_tool), eps_v);
+          const V3<T> F = penalty_force(cs[i], obj_vel(cs[i].x), link_vel(j, cs[i].x), k, damp, T(mu_obj_tool), eps_v);
           add_force(W, ob.p, cs[i].x, F);
           link_force(j, cs[i].x, -F);
           any = true;
@@ -439,15 +495,20 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
     }
     if (!r_finite(ob.p.x) || !r_finite(q[0])) { diverged = true; break; }
   }
-  // goal: object resting on the goal table's top face
+  // goal psi_g at T, the object at rest and either on the goal table's top
+  // face (pick-and-place) or with its centre inside the goal box (move-push:
+  // the container's inner volume)
   bool goal = false;
+  const double px = r_val(ob.p.x), py = r_val(ob.p.y), pz = r_val(ob.p.z);
+  const bool rest = std::sqrt(r_val(dot(ob.v, ob.v))) < s.rest_speed;
   if (s.goal_static >= 0 && s.goal_static < s.n_static) {
     const int b = s.goal_static;
     const double top = s.st_center[b][2] + s.st_half[b][2];
-    const double px = r_val(ob.p.x), py = r_val(ob.p.y), pz = r_val(ob.p.z);
-    const double sp = std::sqrt(r_val(dot(ob.v, ob.v)));
     goal = std::fabs(px - s.st_center[b][0]) <= s.st_half[b][0] && std::fabs(py - s.st_center[b][1]) <= s.st_half[b][1] &&
-           pz >= top && pz <= top + 2.0 * s.obj_half[2] && sp < s.rest_speed;
+           pz >= top && pz <= top + 2.0 * s.obj_half[2] && rest;
+  } else if (s.goal_static < 0) {
+    const double *c = s.goal_box_center, *hb = s.goal_box_half;
+    goal = std::fabs(px - c[0]) <= hb[0] && std::fabs(py - c[1]) <= hb[1] && std::fabs(pz - c[2]) <= hb[2] && rest;
   }
   RolloutOut out;
   const T cost = T(s.time_weight) * dt * T((double)unsuccessful);
@@ -458,7 +519,8 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
   for (int i = 0; i < 7; ++i) fin = fin && std::isfinite(out.pose[i]);
   for (int j = 0; j < NJ; ++j) fin = fin && std::isfinite(r_val(q[j])) && std::fabs(r_val(q[j])) < 1e3;
   fin = fin && std::fabs(out.pose[0]) < 1e3 && std::fabs(out.pose[1]) < 1e3 && std::fabs(out.pose[2]) < 1e3;
-  const bool all_ok = ok[0] && ok[1] && ok[2] && ok[3];
+  bool all_ok = true;
+  for (int a = 0; a < n_act; ++a) all_ok = all_ok && ok[a];
   out.tier = !fin ? 3 : (all_ok ? (goal ? 0 : 1) : 2);
   if (!fin) out.cost = INFINITY;
   return out;

@@ -47,13 +47,23 @@ struct RefScene {
   double pregrasp, finger_open, finger_closed, rest_speed;
   int32_t goal_static;   // static box whose top face is the goal region
   double joint_speed_max, accel_max;  // arm reference speed limit; torque limit I_nom * accel_max
+  // move-push: push speed clamp, longest push, the push action's timeout
+  double push_vmin, push_vmax, push_dmax, timeout_push;
+  // friction of every contact of the object, drawn per instance when obj_mu_hi > 0
+  double obj_mu_lo, obj_mu_hi;
+  // goal region used when goal_static < 0: the object's centre inside this box, at rest
+  double goal_box_center[3], goal_box_half[3];
 };
 
-// Per-instance draws (scene stream 1, sample 0, iteration 0, instance b):
-// goal = object start + rho (cos phi, sin phi), rho ~ U[rho_lo, rho_hi],
-// phi ~ U[phi_lo, phi_hi].
+// Per-instance draws (scene stream 1, sample 0, iteration 0, instance b), one
+// Philox block, words 0-2:
+//   goal = object start + rho (cos phi, sin phi), rho ~ U[rho_lo, rho_hi],
+//   phi ~ U[phi_lo, phi_hi]  (words 0, 1);
+//   the object's friction coefficient obj_mu ~ U[obj_mu_lo, obj_mu_hi] if
+//   obj_mu_hi > 0, else 0 = "use the per-class coefficients"  (word 2).
 struct Instance {
   double goal[2];
+  double obj_mu;
 };
 
 inline Instance draw_instance(const RefScene &s, uint64_t seed, uint32_t b) {
@@ -65,6 +75,7 @@ inline Instance draw_instance(const RefScene &s, uint64_t seed, uint32_t b) {
   Instance in;
   in.goal[0] = s.obj_pos0[0] + rho * std::cos(phi);
   in.goal[1] = s.obj_pos0[1] + rho * std::sin(phi);
+  in.obj_mu = s.obj_mu_hi > 0.0 ? s.obj_mu_lo + (s.obj_mu_hi - s.obj_mu_lo) * (double)u01(x.w[2]) : 0.0;
   return in;
 }
 

@@ -56,6 +56,8 @@ class CemScene(ctypes.Structure):
         ("t_release", _f), ("timeout_move", _f), ("timeout_pick", _f), ("timeout_place", _f),
         ("pregrasp", _f), ("finger_open", _f), ("finger_closed", _f), ("rest_speed", _f),
         ("goal_static", _i), ("joint_speed_max", _f), ("accel_max", _f),
+        ("push_vmin", _f), ("push_vmax", _f), ("push_dmax", _f), ("timeout_push", _f),
+        ("obj_mu_lo", _f), ("obj_mu_hi", _f), ("goal_box_center", _f * 3), ("goal_box_half", _f * 3),
     ]
 
 
@@ -209,8 +211,16 @@ def make_scene(workload):
         s.ik_iters = ct["ik_iters"]
         for f in CONTROLLER_FIELDS:
             setattr(s, f, ct[f])
+        for f in ("push_vmin", "push_vmax", "push_dmax", "timeout_push"):
+            setattr(s, f, ct.get(f, 0.0))
         s.rest_speed = sc["rest_speed"]
         s.goal_static = sc["goal_static"]
+        gb = sc.get("goal_box")
+        if gb:
+            for k in range(3):
+                s.goal_box_center[k] = gb["center"][k]
+                s.goal_box_half[k] = gb["half"][k]
+    s.obj_mu_lo, s.obj_mu_hi = ob.get("mu", (0.0, 0.0))
     return s
 
 
@@ -341,7 +351,8 @@ class Context:
         return L
 
     def get_instance(self):
-        g = np.zeros(2)
+        """Per-instance scene draws: (goal x, goal y, object friction or 0)."""
+        g = np.zeros(3)
         self._check(lib().cem_get_instance(self.h, _np_ptr(g)))
         return g
 

@@ -46,13 +46,14 @@ bool nonneg(float x) { return std::isfinite(x) && x >= 0.0f; }
 
 const char *check_scene(const cem_scene &s) {
   if (dim_of(s.kind) == 0) return "unknown scene kind";
-  if (s.kind == CEM_SCENE_MOVEPUSH) return "scene kind not supported by this build";
   if (s.substeps < 1 || s.substeps > 1000) return "substeps out of range [1, 1000]";
   if (s.horizon < 1 || s.horizon > 100000) return "horizon out of range [1, 100000]";
   if (!pos(s.dt) || !nonneg(s.gravity) || !nonneg(s.k_contact) || !nonneg(s.c_contact) || !pos(s.eps_v))
     return "invalid physical constants";
   if (!nonneg(s.mu_ground) || !nonneg(s.mu_tool) || !nonneg(s.mu_static) || !nonneg(s.mu_ramp))
     return "invalid friction coefficient";
+  if (!nonneg(s.obj_mu_lo) || !nonneg(s.obj_mu_hi) || (s.obj_mu_hi > 0.0f && !(s.obj_mu_lo <= s.obj_mu_hi)))
+    return "invalid object friction range";
   if (!pos(s.obj_half[0]) || !pos(s.obj_half[1]) || !pos(s.obj_half[2]) || !pos(s.obj_mass))
     return "invalid object";
   if (s.n_static < 0 || s.n_static > CEM_MAX_STATIC) return "n_static out of range";
@@ -61,7 +62,7 @@ const char *check_scene(const cem_scene &s) {
     if (!nonneg(s.goal_tol) || !nonneg(s.time_weight)) return "invalid goal tolerance or time weight";
     if (!(s.goal_rho_lo <= s.goal_rho_hi) || !(s.goal_phi_lo <= s.goal_phi_hi)) return "invalid goal ranges";
   }
-  if (s.kind == CEM_SCENE_PICKPLACE) {
+  if (s.kind == CEM_SCENE_PICKPLACE || s.kind == CEM_SCENE_MOVEPUSH) {
     // the kernels unroll the fixed tree: base x, y, yaw; a serial arm 3..8; fingers 9, 10 on body 8
     if (s.n_joints != 11) return "robot must have 11 joints";
     for (int j = 0; j < 11; ++j) {
@@ -82,7 +83,17 @@ const char *check_scene(const cem_scene &s) {
     if (!pos(s.t_approach) || !pos(s.t_descend) || !nonneg(s.t_close) || !pos(s.t_lift) || !pos(s.t_transfer) ||
         !nonneg(s.t_release))
       return "invalid phase durations";
-    if (s.goal_static < 0 || s.goal_static >= s.n_static) return "goal_static must index a static box";
+    if (s.kind == CEM_SCENE_PICKPLACE) {
+      if (s.goal_static < 0 || s.goal_static >= s.n_static) return "goal_static must index a static box";
+    } else {
+      if (s.goal_static >= s.n_static) return "goal_static out of range";
+      if (s.goal_static < 0 && !(pos(s.goal_box_half[0]) && pos(s.goal_box_half[1]) && pos(s.goal_box_half[2]) &&
+                                 std::isfinite(s.goal_box_center[0]) && std::isfinite(s.goal_box_center[1]) &&
+                                 std::isfinite(s.goal_box_center[2])))
+        return "invalid goal box";
+      if (!pos(s.push_vmin) || !(s.push_vmax >= s.push_vmin) || !nonneg(s.push_dmax) || !pos(s.timeout_push))
+        return "invalid push limits";
+    }
   }
   return nullptr;
 }
@@ -376,11 +387,14 @@ int cem_get_factor(cem_ctx *c, double *L) {
   return CEM_OK;
 }
 
-int cem_get_instance(cem_ctx *c, double *goal_xy) {
+int cem_get_instance(cem_ctx *c, double *draws) {
   if (!c) return CEM_E_ARG;
-  if (!goal_xy) return fail(c, CEM_E_ARG, "null output");
-  HIPCHK(c, hipMemcpyAsync(goal_xy, c->st->goal, sizeof(double) * 2, hipMemcpyDeviceToHost, c->own));
+  if (!draws) return fail(c, CEM_E_ARG, "null output");
+  float mu = 0.0f;
+  HIPCHK(c, hipMemcpyAsync(draws, c->st->goal, sizeof(double) * 2, hipMemcpyDeviceToHost, c->own));
+  HIPCHK(c, hipMemcpyAsync(&mu, &c->st->obj_mu, sizeof(float), hipMemcpyDeviceToHost, c->own));
   HIPCHK(c, hipStreamSynchronize(c->own));
+  draws[2] = (double)mu;
   return CEM_OK;
 }
 

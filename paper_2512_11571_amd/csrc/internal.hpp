@@ -20,7 +20,8 @@ struct DevState {
   double S[MAX_D * MAX_D];     // covariance
   double L[MAX_D * MAX_D];     // its Cholesky factor (lower, row-major)
   double cov0[MAX_D * MAX_D];  // initial covariance (its diagonal feeds the single-elite noise)
-  double goal[2];              // per-instance draw (push goal)
+  double goal[2];              // per-instance draw: the push goal
+  float obj_mu;                // per-instance draw: the object's friction (0: per-class values)
   int32_t iter;                // CE iteration counter for the replayed iteration
   int32_t D, cov_mode, n_elite;
   float best_z[MAX_D];

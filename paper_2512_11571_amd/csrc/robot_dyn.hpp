@@ -375,7 +375,7 @@ __device__ __forceinline__ bool spheres_overlap(V3f pa, V3f ha, V3f pb, V3f hb) 
   return dot(d, d) <= r * r;
 }
 
-enum : int { MOVE = 0, PICK = 1, PLACE = 2 };
+enum : int { MOVE = 0, PICK = 1, PLACE = 2, PUSH = 3 };
 // The plan's parameter row as four named 4-vectors (one per action), so that
 // choosing the active action's parameters is a value select, not an indexed load.
 struct Params4 {
@@ -388,7 +388,11 @@ __device__ __forceinline__ void action_params(const Params4 &zp, int a, float (&
     pz[i] = a == 0 ? p0 : (a == 1 ? p1 : (a == 2 ? p2 : p3));
   }
 }
-__device__ __forceinline__ int act_kind(int a) { return (a == 0 || a == 2) ? MOVE : (a == 1 ? PICK : PLACE); }
+// Action a of the plan: pick-and-place = move, pick, move, place;
+// move-push = move, push (the push takes parameter blocks 1 and 2).
+__device__ __forceinline__ int act_kind(bool pnp, int a) {
+  return (a == 0 || a == 2) ? MOVE : (a == 1 ? (pnp ? PICK : PUSH) : PLACE);
+}
 
 }  // namespace
 }  // namespace cem

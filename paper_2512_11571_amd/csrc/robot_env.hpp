@@ -1,11 +1,18 @@
-// One environment of the mobile-manipulator pick-and-place plan (device function).
+// One environment of a mobile-manipulator plan (device function).
 //
-// pick-and-place plan (Sec. IV-A, pi_p&p without the final move to Exit):
+// pick-and-place (Sec. IV-A, pi_p&p without the final move to Exit):
 //   move_to(x, y, psi, v) -> grasp(q) -> move_to(x, y, psi, v) -> place(x, y, z, psi)
+// move-and-push (Sec. IV-A, pi_m&p):
+//   move_to(x, y, psi, v) -> push(start xyz, heading, distance, speed,
+//   approach height, gripper yaw): closed fingers reach a pose above the start
+//   point, descend to it, sweep the end effector along the push line, then
+//   the gripper opens.
 // Problem 2 cost: dt per control step while the active action is not yet
-// successful; tier 0 if every action succeeded and the object rests on the
-// goal table's top at T (psi_g), 1 if every action succeeded but psi_g fails,
-// 2 otherwise, 3 diverged.
+// successful; tier 0 if every action succeeded and psi_g holds at T (the
+// object rests on the goal table's top face, or with its centre inside the
+// goal box), 1 if every action succeeded but psi_g fails, 2 otherwise, 3
+// diverged.  The object's contacts use its per-instance friction draw when
+// the scene has one.
 //
 // Each action runs from the step after the previous one ends (Problem 1,
 // t_{0,i+1} = T_i + 1) until success or timeout.  Controllers: straight-line
@@ -24,9 +31,9 @@
 //
 // One environment per lane.  The per-body quantities the three passes hand to
 // each other (joint state, bias accelerations, bias forces / U columns, D^-1,
-// u) live in LDS, one lane-contiguous row per quantity, so the passes loop
-// over bodies without unrolling and without scratch; the rest of the state
-// stays in VGPRs.  HBM is touched only for z in and (cost, tier, pose) out;
+// u) and the push's third joint-space anchor live in LDS, one lane-contiguous
+// row per quantity, so the passes loop over bodies without unrolling and
+// without scratch; the rest of the state stays in VGPRs.  HBM is touched only for z in and (cost, tier, pose) out;
 // the scene is read through wave-uniform scalar loads.
 #pragma once
 #include "robot_dyn.hpp"
@@ -36,9 +43,9 @@ namespace {
 
 constexpr int PP_LANES = 64;  // lanes sharing one LDS block of rows
 // LDS rows (each BS floats): q, qd, qref, bias acceleration c (6 per body),
-// bias force pA then U (6 per body), 1/D, u
+// bias force pA then U (6 per body), 1/D, u, the push's end-of-line arm targets
 constexpr int R_Q = 0, R_QD = R_Q + NJ, R_QREF = R_QD + NJ, R_C = R_QREF + NJ, R_P = R_C + 6 * NJ,
-              R_DI = R_P + 6 * NJ, R_UU = R_DI + NJ, R_ROWS = R_UU + NJ;
+              R_DI = R_P + 6 * NJ, R_UU = R_DI + NJ, R_QC = R_UU + NJ, R_ROWS = R_QC + NARM;
 
 struct Lds {
   float *m;
@@ -63,15 +70,21 @@ __device__ __forceinline__ Xf joint_X(const cem_scene &sc, int j, float q) {
   return X;
 }
 
-// Rolls out row `env` of Z (16 parameters) and writes its cost, tier, pose and
-// (TRACE) per-step trace.  `lds_mem` is the block's R_ROWS x PP_LANES float
-// array and `lane` this lane's column in it.
+// Rolls out row `env` of Z (16 parameters for pick-and-place, 12 for
+// move-push) and writes its cost, tier, pose and (TRACE) per-step trace.
+// `lds_mem` is the block's R_ROWS x PP_LANES float array and `lane` this
+// lane's column in it; `mu_obj` is the instance's object friction draw (0:
+// the per-class coefficients).
 template <bool TRACE>
-__device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *__restrict__ Z, long env,
-                                              float *lds_mem, int lane, float *__restrict__ cost_out,
-                                              uint8_t *__restrict__ tier_out, float *__restrict__ pose_out,
-                                              float *__restrict__ trace, int trace_steps) {
+__device__ __forceinline__ void robot_env(const cem_scene &sc, float mu_obj, const float *__restrict__ Z, long env,
+                                          float *lds_mem, int lane, float *__restrict__ cost_out,
+                                          uint8_t *__restrict__ tier_out, float *__restrict__ pose_out,
+                                          float *__restrict__ trace, int trace_steps) {
   const Lds L{lds_mem, lane};
+  const bool pnp = sc.kind == CEM_SCENE_PICKPLACE;
+  const int n_act = pnp ? 4 : 2, n_par = pnp ? 16 : 12;
+  const bool mu_drawn = mu_obj > 0.0f;
+  const float mu_o_ground = mu_drawn ? mu_obj : sc.mu_ground, mu_o_tool = mu_drawn ? mu_obj : sc.mu_tool;
   const float h = sc.dt / (float)sc.substeps;
   const float dt = sc.dt;
   const float g = sc.gravity;
@@ -87,7 +100,7 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) zp.v[a][i] = Z[(long)env * 16 + 4 * a + i];
+    for (int i = 0; i < 4; ++i) zp.v[a][i] = 4 * a + i < n_par ? Z[(long)env * n_par + 4 * a + i] : 0.0f;
 
   for (int j = 0; j < NJ; ++j) {
     L.at(R_Q + j) = sc.q0[j];
@@ -110,7 +123,7 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
   float qstart[NARM + 3], qa[NARM], qb[NARM];
   V3f ptarget = v3(0.0f, 0.0f, 0.0f);
   float base_from[3] = {0.0f, 0.0f, 0.0f}, base_to[3] = {0.0f, 0.0f, 0.0f}, t_move = 1.0f;
-  float Ta = sc.t_approach, Td = sc.t_descend, Tl = sc.t_lift, Tp = sc.t_transfer;
+  float Ta = sc.t_approach, Td = sc.t_descend, Tl = sc.t_lift, Tp = sc.t_transfer, Tq = dt;
   float finger_cmd = sc.finger_open;
   bool touchL = false, touchR = false;
   int unsuccessful = 0;
@@ -136,7 +149,7 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
     for (int j = 0; j < NARM + 3; ++j) qstart[j] = q[j];
     float pz[4];
     action_params(zp, a, pz);
-    const int kind = act_kind(a);
+    const int kind = act_kind(pnp, a);
     if (kind == MOVE) {
       base_from[0] = q[0]; base_from[1] = q[1]; base_from[2] = q[2];
       const float dpsi = wrap_pi(pz[2] - q[2]);
@@ -145,6 +158,42 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
       const float dx = pz[0] - q[0], dy = pz[1] - q[1];
       const float Lm = sqrtf(dx * dx + dy * dy);
       t_move = fmaxf(fmaxf(Lm / v, fabsf(dpsi) / sc.base_wmax), dt);
+    } else if (kind == PUSH) {
+      // parameters: block 1 = start point xyz, heading; block 2 = distance, speed, approach height, gripper yaw
+      float pw[4];
+      action_params(zp, 2, pw);
+      float sg, cg, sh, ch;
+      sincosf(pw[3], &sg, &cg);
+      sincosf(pz[3], &sh, &ch);
+      M3f Rt;
+      Rt.r0 = v3(cg, sg, 0.0f);
+      Rt.r1 = v3(sg, -cg, 0.0f);
+      Rt.r2 = v3(0.0f, 0.0f, -1.0f);
+      const V3f ps = v3(pz[0], pz[1], pz[2]);
+      const float dist = fmaxf(0.0f, fminf(sc.push_dmax, pw[0]));
+      const float vp = fmaxf(sc.push_vmin, fminf(sc.push_vmax, pw[1]));
+      const float dz = fmaxf(0.0f, pw[2]);
+      const V3f pe = ps + dist * v3(ch, sh, 0.0f);
+      float qs[NARM];
+#pragma unroll
+      for (int j = 0; j < NARM; ++j) qs[j] = q[ARM0 + j];
+      ik_dls(sc, q, ps + v3(0.0f, 0.0f, dz), Rt);
+#pragma unroll
+      for (int j = 0; j < NARM; ++j) qa[j] = q[ARM0 + j];
+      ik_dls(sc, q, ps, Rt);
+#pragma unroll
+      for (int j = 0; j < NARM; ++j) qb[j] = q[ARM0 + j];
+      ik_dls(sc, q, pe, Rt);
+      float qc[NARM];
+#pragma unroll
+      for (int j = 0; j < NARM; ++j) {
+        qc[j] = q[ARM0 + j];
+        L.at(R_QC + j) = qc[j];
+      }
+      Ta = span(qs, qa, sc.t_approach);
+      Td = span(qa, qb, sc.t_descend);
+      Tq = fmaxf(span(qb, qc, dist / vp), dt);
+      ptarget = pe;
     } else {
       M3f Rt;
       V3f pfin, pgoal;
@@ -189,7 +238,6 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
     }
   };
 
-  const int n_act = 4;
   start_action(0, 0);
   bool diverged = false;
   for (int t = 0; t < sc.horizon; ++t) {
@@ -198,7 +246,7 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
       float q[NJ];
       load_q(q);
       const float tau = (float)(t - t_start) * dt;
-      const int kind = act_kind(act);
+      const int kind = act_kind(pnp, act);
       bool succ;
       if (kind == MOVE) {
         float pz[4];
@@ -217,11 +265,16 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
           const V3f op = mulT(Rw[PALM], ob.p - pw[PALM]);
           const bool between = op.y < q[FL] && op.y > -q[FR];
           succ = tau >= tend && touchL && touchR && between && near;
+        } else if (kind == PUSH) {
+          succ = tau >= Ta + Td + Tq + sc.t_release && near;
         } else {
           succ = tau >= Tp + sc.t_release && near;
         }
       }
-      const float tout = kind == MOVE ? sc.timeout_move : (kind == PICK ? sc.timeout_pick : sc.timeout_place);
+      const float tout = kind == MOVE   ? sc.timeout_move
+                         : kind == PICK ? sc.timeout_pick
+                         : kind == PUSH ? sc.timeout_push
+                                        : sc.timeout_place;
       if (succ || tau >= tout) {
         if (succ) ok_bits |= 1u << act;
         ++act;
@@ -232,7 +285,7 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
     // ---- references ----
     if (act < n_act) {
       const float tau = (float)(t - t_start) * dt;
-      const int kind = act_kind(act);
+      const int kind = act_kind(pnp, act);
       float r[NARM + 3];
       if (kind == MOVE) {
         const float sft = smooth01(tau / t_move);
@@ -256,6 +309,20 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
           r[3 + j] = v;
         }
         finger_cmd = tau < Ta + Td ? sc.finger_open : sc.finger_closed;
+      } else if (kind == PUSH) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[c] = qstart[c];
+#pragma unroll
+        for (int j = 0; j < NARM; ++j) {
+          float v;
+          const float s0 = qstart[ARM0 + j], qcj = L.at(R_QC + j);
+          if (tau < Ta) v = s0 + smooth01(tau / Ta) * (qa[j] - s0);
+          else if (tau < Ta + Td) v = qa[j] + smooth01((tau - Ta) / Td) * (qb[j] - qa[j]);
+          else if (tau < Ta + Td + Tq) v = qb[j] + smooth01((tau - Ta - Td) / Tq) * (qcj - qb[j]);
+          else v = qcj;
+          r[3 + j] = v;
+        }
+        finger_cmd = tau < Ta + Td + Tq ? sc.finger_closed : sc.finger_open;
       } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = qstart[c];
@@ -277,12 +344,12 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
       // ---- the object against the world (ground, static boxes) ----
       const M3f oR = rot_of(ob.q);
       Wrench W{v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)};
-      box_ground(ob, oR, ohe, kc, damp, sc.mu_ground, eps2, W);
+      box_ground(ob, oR, ohe, kc, damp, mu_o_ground, eps2, W);
       for (int b = 0; b < sc.n_static; ++b) {
         const M3f SR = static_rot(sc, b);
         const V3f SP = v3(sc.st_center[b][0], sc.st_center[b][1], sc.st_center[b][2]);
         const V3f SH = v3(sc.st_half[b][0], sc.st_half[b][1], sc.st_half[b][2]);
-        const float mu = sc.st_ramp[b] ? sc.mu_ramp : sc.mu_static;
+        const float mu = mu_drawn ? mu_obj : (sc.st_ramp[b] ? sc.mu_ramp : sc.mu_static);
         if (!spheres_overlap(ob.p, ohe, SP, SH)) continue;
         verts_in_box(ob.p, oR, ohe, SP, SR, SH, [&](bool in, V3f x, V3f n, float d) {
           const V3f r = x - ob.p;
@@ -351,7 +418,7 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
             // finger vertices in the object (A = finger, B = object)
             verts_in_box(bc, Rb, bh, ob.p, oR, ohe, [&](bool in, V3f x, V3f n, float d) {
               const V3f ro = x - ob.p;
-              const V3f F = contact_force(in, n, d, link_v(x) - (ob.v + cross(ob.w, ro)), kc, damp, sc.mu_tool, eps2);
+              const V3f F = contact_force(in, n, d, link_v(x) - (ob.v + cross(ob.w, ro)), kc, damp, mu_o_tool, eps2);
               link_f(x, F);
               apply(W, ro, -F);
               any = any || in;
@@ -359,7 +426,7 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
             // object vertices in the finger (A = object, B = finger)
             verts_in_box(ob.p, oR, ohe, bc, Rb, bh, [&](bool in, V3f x, V3f n, float d) {
               const V3f ro = x - ob.p;
-              const V3f F = contact_force(in, n, d, (ob.v + cross(ob.w, ro)) - link_v(x), kc, damp, sc.mu_tool, eps2);
+              const V3f F = contact_force(in, n, d, (ob.v + cross(ob.w, ro)) - link_v(x), kc, damp, mu_o_tool, eps2);
               apply(W, ro, F);
               link_f(x, -F);
               any = any || in;
@@ -459,14 +526,18 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
       break;
     }
   }
-  // goal: the object rests on the goal table's top face
+  // goal psi_g: the object at rest, on the goal table's top face or with its centre inside the goal box
   bool goal = false;
+  const bool rest = sqrtf(dot(ob.v, ob.v)) < sc.rest_speed;
   if (sc.goal_static >= 0 && sc.goal_static < sc.n_static) {
     const int b = sc.goal_static;
     const float top = sc.st_center[b][2] + sc.st_half[b][2];
-    const float sp = sqrtf(dot(ob.v, ob.v));
     goal = fabsf(ob.p.x - sc.st_center[b][0]) <= sc.st_half[b][0] && fabsf(ob.p.y - sc.st_center[b][1]) <= sc.st_half[b][1] &&
-           ob.p.z >= top && ob.p.z <= top + 2.0f * sc.obj_half[2] && sp < sc.rest_speed;
+           ob.p.z >= top && ob.p.z <= top + 2.0f * sc.obj_half[2] && rest;
+  } else if (sc.goal_static < 0) {
+    goal = fabsf(ob.p.x - sc.goal_box_center[0]) <= sc.goal_box_half[0] &&
+           fabsf(ob.p.y - sc.goal_box_center[1]) <= sc.goal_box_half[1] &&
+           fabsf(ob.p.z - sc.goal_box_center[2]) <= sc.goal_box_half[2] && rest;
   }
   const float pose[7] = {ob.p.x, ob.p.y, ob.p.z, ob.q.w, ob.q.x, ob.q.y, ob.q.z};
   bool fin = !diverged;
@@ -474,7 +545,7 @@ __device__ __forceinline__ void pickplace_env(const cem_scene &sc, const float *
   for (int i = 0; i < 7; ++i) fin = fin && isfinite(pose[i]);
   for (int j = 0; j < NJ; ++j) fin = fin && isfinite(L.at(R_Q + j)) && fabsf(L.at(R_Q + j)) < 1e3f;
   fin = fin && fabsf(ob.p.x) < 1e3f && fabsf(ob.p.y) < 1e3f && fabsf(ob.p.z) < 1e3f;
-  const bool all_ok = ok_bits == 0xFu;
+  const bool all_ok = ok_bits == (1u << n_act) - 1u;
   const int tier = !fin ? 3 : (all_ok ? (goal ? 0 : 1) : 2);
   const float cost = fin ? sc.time_weight * dt * (float)unsuccessful : __int_as_float(0x7F800000);
   if (cost_out) cost_out[env] = cost;

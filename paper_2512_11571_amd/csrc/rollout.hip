@@ -10,7 +10,7 @@
 // per-environment code in the same kernel, so an instance's results do not
 // depend on whether it ran alone or in a batch.
 #include "internal.hpp"
-#include "pickplace_env.hpp"
+#include "robot_env.hpp"
 #include "push_env.hpp"
 
 namespace cem {
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
       if (d.kind == CEM_SCENE_PUSH)
         push_env<TRACE>(sc, d.st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
       else
-        pickplace_env<TRACE>(sc, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
+        robot_env<TRACE>(sc, d.st->obj_mu, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
     }
     if (!queue) break;
   }

@@ -168,8 +168,10 @@ __global__ void __launch_bounds__(256) mlp_init_kernel(uint64_t seed, InitLayers
   P[p] = (float)((double)e * sqrt(2.0 / (double)L.fan_in[layer]));
 }
 
-// Per-instance draws on the scene stream (tag 1): the push goal
-// g = start + rho (cos phi, sin phi), rho and phi uniform in their ranges.
+// Per-instance draws on the scene stream (tag 1), one Philox block: the push
+// goal g = start + rho (cos phi, sin phi), rho and phi uniform in their ranges
+// (words 0, 1), and the object's friction coefficient U[obj_mu_lo, obj_mu_hi]
+// when obj_mu_hi > 0 (word 2).
 __global__ void instance_draw_kernel(cem_scene sc, uint64_t seed, uint32_t inst, DevState *st) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const U4 w = draw(seed, 1u, 0u, 0u, 0u, inst);
@@ -178,6 +180,9 @@ __global__ void instance_draw_kernel(cem_scene sc, uint64_t seed, uint32_t inst,
   const double phi = (double)sc.goal_phi_lo + ((double)sc.goal_phi_hi - (double)sc.goal_phi_lo) * u1;
   st->goal[0] = (double)sc.obj_pos0[0] + rho * cos(phi);
   st->goal[1] = (double)sc.obj_pos0[1] + rho * sin(phi);
+  st->obj_mu = sc.obj_mu_hi > 0.0f
+                   ? (float)((double)sc.obj_mu_lo + ((double)sc.obj_mu_hi - (double)sc.obj_mu_lo) * (double)unit(w.c))
+                   : 0.0f;
 }
 
 }  // namespace

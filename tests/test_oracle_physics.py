@@ -209,7 +209,7 @@ def test_push_goal_draw_ranges(oracle, push):
     rho, phi = [], []
     for s in range(400):
         g = oracle.draw_instance(push, s)
-        rho.append(math.hypot(*g))
+        rho.append(math.hypot(g[0], g[1]))
         phi.append(math.atan2(g[1], g[0]))
     go = push["scene"]["goal"]
     assert go["rho"][0] <= min(rho) and max(rho) <= go["rho"][1]
