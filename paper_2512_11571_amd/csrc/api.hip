@@ -254,8 +254,9 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
       break;
     }
     if ((rc = upload_theta(c, p->mu0, p->cov0, true, c->own)) != CEM_OK) break;
-    if (launch_instance_draw(c->scene, c->seed, c->inst, c->st, c->own) != hipSuccess) {
-      rc = fail(c, CEM_E_HIP, "instance draw launch");
+    if (launch_instance_draw(c->scene, c->seed, c->inst, c->st, c->own) != hipSuccess ||
+        launch_scene_consts(c->st, c->own) != hipSuccess) {
+      rc = fail(c, CEM_E_HIP, "instance set-up launch");
       break;
     }
     rc = factor_and_check(c, c->own);

@@ -14,6 +14,13 @@ constexpr int MAX_ELITE = 256;
 constexpr int MAX_POP = 65536;
 constexpr int MAX_STATS_ITERS = 4096;
 
+// Per-context constants derived from the scene once at set-up (by a device
+// kernel), so the rollout does not recompute them every substep.
+struct SceneConsts {
+  float st_R[CEM_MAX_STATIC][9];       // static box rotations (box -> world), row-major
+  float I_body[CEM_MAX_JOINTS][21];    // spatial inertia of body j about its frame origin: A(6) B(9) C(6)
+};
+
 // Device-resident CE state of one context (one task instance).
 struct DevState {
   double mu[MAX_D];
@@ -33,6 +40,7 @@ struct DevState {
   uint32_t inst_id;            // Philox counter word 3
   int32_t pop;
   cem_scene scene;             // device copy of the scene (read by the rollout kernels)
+  SceneConsts sk;              // derived from scene by launch_scene_consts
 };
 
 // One task instance as the launches see it: its device state and buffers.
@@ -65,6 +73,7 @@ hipError_t launch_select_refit_batch(const InstDesc *insts, int n_inst, int stat
 hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s);
 hipError_t launch_rollout_batch(const InstDesc *insts, const WorkItem *items, int n_items, int *queue, int grid,
                                 hipStream_t s);
+hipError_t launch_scene_consts(DevState *st, hipStream_t s);
 hipError_t launch_pack_dataset(const InstDesc &d, float cost_cap, float *X, float *Y, hipStream_t s);
 
 }  // namespace cem

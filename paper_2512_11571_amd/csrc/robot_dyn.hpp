@@ -172,13 +172,12 @@ __device__ __forceinline__ V3f unit_axis(int a) {
   return v3(k == 0 ? s : 0.0f, k == 1 ? s : 0.0f, k == 2 ? s : 0.0f);
 }
 
-// Joint j at coordinate q: rotation R (child -> parent) and child origin r (parent coords).
-__device__ __forceinline__ void joint_tf(const cem_scene &sc, int j, float q, M3f &R, V3f &r) {
+// Joint j at coordinate q (with s = sin q, c = cos q for a revolute joint):
+// rotation R (child -> parent) and child origin r (parent coords).
+__device__ __forceinline__ void joint_tf_sc(const cem_scene &sc, int j, float q, float s, float c, M3f &R, V3f &r) {
   const V3f o = v3(sc.j_origin[j][0], sc.j_origin[j][1], sc.j_origin[j][2]);
   const V3f a = unit_axis(sc.j_axis[j]);
   if (sc.j_type[j] == 0) {
-    float s, c;
-    sincosf(q, &s, &c);
     const float t = 1.0f - c;
     R.r0 = v3(c + a.x * a.x * t, a.x * a.y * t - a.z * s, a.x * a.z * t + a.y * s);
     R.r1 = v3(a.y * a.x * t + a.z * s, c + a.y * a.y * t, a.y * a.z * t - a.x * s);
@@ -190,6 +189,11 @@ __device__ __forceinline__ void joint_tf(const cem_scene &sc, int j, float q, M3
     R.r2 = v3(0.0f, 0.0f, 1.0f);
     r = o + q * a;
   }
+}
+__device__ __forceinline__ void joint_tf(const cem_scene &sc, int j, float q, M3f &R, V3f &r) {
+  float s = 0.0f, c = 1.0f;
+  if (sc.j_type[j] == 0) sincosf(q, &s, &c);
+  joint_tf_sc(sc, j, q, s, c, R, r);
 }
 __device__ __forceinline__ M3f transpose3(const M3f &R) {
   M3f T;
@@ -340,39 +344,104 @@ __device__ __forceinline__ M3f static_rot(const cem_scene &sc, int k) {
   return R;
 }
 
-// Vertex-face: vertices of box A (pa, Ra, ha) strictly inside box B (pb, Rb, hb);
+// ---- box-box contact (vertex-face both ways) ----
+// A box: centre p, rotation R (box -> world), half extents h.
+struct Box {
+  V3f p;
+  M3f R;
+  V3f h;
+};
+__device__ __forceinline__ V3f col(const M3f &R, int k) {
+  return k == 0 ? v3(R.r0.x, R.r1.x, R.r2.x) : (k == 1 ? v3(R.r0.y, R.r1.y, R.r2.y) : v3(R.r0.z, R.r1.z, R.r2.z));
+}
+__device__ __forceinline__ V3f vabs(V3f a) { return v3(fabsf(a.x), fabsf(a.y), fabsf(a.z)); }
+// Box A seen from box B: M = RB^T RA (A's axes in B's frame), t = RB^T (pA - pB).
+struct Rel {
+  M3f M;
+  V3f t;
+};
+__device__ __forceinline__ Rel rel_of(const Box &A, const Box &B) {
+  const V3f b0 = col(B.R, 0), b1 = col(B.R, 1), b2 = col(B.R, 2);
+  const V3f a0 = col(A.R, 0), a1 = col(A.R, 1), a2 = col(A.R, 2);
+  Rel r;
+  r.M.r0 = v3(dot(b0, a0), dot(b0, a1), dot(b0, a2));
+  r.M.r1 = v3(dot(b1, a0), dot(b1, a1), dot(b1, a2));
+  r.M.r2 = v3(dot(b2, a0), dot(b2, a1), dot(b2, a2));
+  r.t = mulT(B.R, A.p - B.p);
+  return r;
+}
+// B seen from A: M^T and -M^T t.
+__device__ __forceinline__ Rel rel_swap(const Rel &r) {
+  Rel o;
+  o.M.r0 = col(r.M, 0);
+  o.M.r1 = col(r.M, 1);
+  o.M.r2 = col(r.M, 2);
+  o.t = -mulT(r.M, r.t);
+  return o;
+}
+// True when one of the six face normals separates the boxes: then no vertex
+// of either lies inside the other, so the vertex-face tests would find nothing.
+__device__ __forceinline__ bool face_separated(const Rel &r, V3f hA, V3f hB) {
+  const V3f m0 = vabs(r.M.r0), m1 = vabs(r.M.r1), m2 = vabs(r.M.r2);
+  const V3f ta = vabs(mulT(r.M, r.t));
+  return fabsf(r.t.x) > hB.x + dot(m0, hA) || fabsf(r.t.y) > hB.y + dot(m1, hA) || fabsf(r.t.z) > hB.z + dot(m2, hA) ||
+         ta.x > hA.x + (m0.x * hB.x + m1.x * hB.y + m2.x * hB.z) ||
+         ta.y > hA.y + (m0.y * hB.x + m1.y * hB.y + m2.y * hB.z) ||
+         ta.z > hA.z + (m0.z * hB.x + m1.z * hB.y + m2.z * hB.z);
+}
+// Vertex-face: the vertices of box A strictly inside box B (r = rel_of(A, B));
 // for each, depth = distance to B's nearest face, n = that face's outward
-// normal (world), calling f(x, n, d).  Faces +x -x +y -y +z -z, first on ties.
+// normal (world), x = the vertex (world), calling f(x, n, d).  Faces +x -x +y
+// -y +z -z, first on ties.  Vertices are built in B's frame from the scaled
+// axes of A; the face search and the world-frame quantities are computed only
+// where a lane has the vertex inside.
 template <class F>
-__device__ __forceinline__ void verts_in_box(V3f pa, const M3f &Ra, V3f ha, V3f pb, const M3f &Rb, V3f hb, F &&f) {
+__device__ __forceinline__ void verts_in_box(const Rel &r, V3f hA, const Box &B, F &&f) {
+  const V3f c0 = hA.x * col(r.M, 0), c1 = hA.y * col(r.M, 1), c2 = hA.z * col(r.M, 2);
+  const V3f hb = B.h;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const V3f loc = v3((i & 1) ? ha.x : -ha.x, (i & 2) ? ha.y : -ha.y, (i & 4) ? ha.z : -ha.z);
-    const V3f x = pa + mul(Ra, loc);
-    const V3f xb = mulT(Rb, x - pb);
+    const V3f xb = (r.t + ((i & 4) ? c2 : -c2) + ((i & 2) ? c1 : -c1)) + ((i & 1) ? c0 : -c0);
     const bool in = fabsf(xb.x) < hb.x && fabsf(xb.y) < hb.y && fabsf(xb.z) < hb.z;
-    const float ds[6] = {hb.x - xb.x, hb.x + xb.x, hb.y - xb.y, hb.y + xb.y, hb.z - xb.z, hb.z + xb.z};
-    int fb = 0;
-    float dmin = ds[0];
+    if (in) {  // skipped by the whole wave when no lane has this vertex inside
+      const float ds[6] = {hb.x - xb.x, hb.x + xb.x, hb.y - xb.y, hb.y + xb.y, hb.z - xb.z, hb.z + xb.z};
+      int fb = 0;
+      float dmin = ds[0];
 #pragma unroll
-    for (int k = 1; k < 6; ++k) {
-      const bool lt = ds[k] < dmin;
-      fb = lt ? k : fb;
-      dmin = lt ? ds[k] : dmin;
+      for (int k = 1; k < 6; ++k) {
+        const bool lt = ds[k] < dmin;
+        fb = lt ? k : fb;
+        dmin = lt ? ds[k] : dmin;
+      }
+      const float sgn = (fb & 1) ? -1.0f : 1.0f;
+      const int ax = fb >> 1;
+      const V3f nl = v3(ax == 0 ? sgn : 0.0f, ax == 1 ? sgn : 0.0f, ax == 2 ? sgn : 0.0f);
+      f(B.p + mul(B.R, xb), mul(B.R, nl), dmin);
     }
-    const float sgn = (fb & 1) ? -1.0f : 1.0f;
-    const int ax = fb >> 1;
-    const V3f nl = v3(ax == 0 ? sgn : 0.0f, ax == 1 ? sgn : 0.0f, ax == 2 ? sgn : 0.0f);
-    if (in) f(in, x, mul(Rb, nl), dmin);  // skipped by the whole wave when no lane has this vertex inside
   }
 }
 
-// Broadphase: two boxes can touch only if their bounding spheres (radius =
-// half diagonal) overlap.
-__device__ __forceinline__ bool spheres_overlap(V3f pa, V3f ha, V3f pb, V3f hb) {
-  const V3f d = pa - pb;
-  const float r = sqrtf(dot(ha, ha)) + sqrtf(dot(hb, hb));
-  return dot(d, d) <= r * r;
+__device__ __forceinline__ Box static_box(const cem_scene &sc, const SceneConsts &k, int b) {
+  Box B;
+  B.p = v3(sc.st_center[b][0], sc.st_center[b][1], sc.st_center[b][2]);
+  B.h = v3(sc.st_half[b][0], sc.st_half[b][1], sc.st_half[b][2]);
+  const float *m = k.st_R[b];
+  B.R.r0 = v3(m[0], m[1], m[2]);
+  B.R.r1 = v3(m[3], m[4], m[5]);
+  B.R.r2 = v3(m[6], m[7], m[8]);
+  return B;
+}
+__device__ __forceinline__ Sym6 inertia_of(const SceneConsts &k, int j) {
+  Sym6 I;
+  const float *m = k.I_body[j];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    I.A[i] = m[i];
+    I.C[i] = m[15 + i];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) I.B[i] = m[6 + i];
+  return I;
 }
 
 enum : int { MOVE = 0, PICK = 1, PLACE = 2, PUSH = 3 };

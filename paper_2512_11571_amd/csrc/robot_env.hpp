@@ -42,10 +42,15 @@ namespace cem {
 namespace {
 
 constexpr int PP_LANES = 64;  // lanes sharing one LDS block of rows
-// LDS rows (each BS floats): q, qd, qref, bias acceleration c (6 per body),
-// bias force pA then U (6 per body), 1/D, u, the push's end-of-line arm targets
-constexpr int R_Q = 0, R_QD = R_Q + NJ, R_QREF = R_QD + NJ, R_C = R_QREF + NJ, R_P = R_C + 6 * NJ,
-              R_DI = R_P + 6 * NJ, R_UU = R_DI + NJ, R_QC = R_UU + NJ, R_ROWS = R_QC + NARM;
+// LDS rows (each PP_LANES floats): q, qd, qref; bias acceleration c (6 per
+// body, bodies 2..10: the first two bodies only translate, so their c is
+// zero); bias force pA then U (6 per body); 1/D; u; the push's end-of-line arm
+// targets; sin and cos of joints 2..8 for the current substep.  195 rows x 256 B
+// keeps three waves per CU.
+constexpr int C0 = 2;  // first body with a stored bias acceleration
+constexpr int R_Q = 0, R_QD = R_Q + NJ, R_QREF = R_QD + NJ, R_C = R_QREF + NJ, R_P = R_C + 6 * (NJ - C0),
+              R_DI = R_P + 6 * NJ, R_UU = R_DI + NJ, R_QC = R_UU + NJ, R_CS = R_QC + NARM,
+              R_ROWS = R_CS + 2 * (PALM - C0 + 1);
 
 struct Lds {
   float *m;
@@ -60,26 +65,40 @@ struct Lds {
   }
 };
 
-__device__ __forceinline__ Xf joint_X(const cem_scene &sc, int j, float q) {
+// Parent -> child transform of joint j at q, with the substep's sine and
+// cosine of joints C0..PALM taken from their LDS rows (the other joints are
+// prismatic).
+__device__ __forceinline__ Xf joint_X(const cem_scene &sc, const Lds &L, int j, float q) {
+  float s = 0.0f, c = 1.0f;
+  if (j >= C0 && j <= PALM) {
+    s = L.at(R_CS + 2 * (j - C0));
+    c = L.at(R_CS + 2 * (j - C0) + 1);
+  }
   M3f Rj;
   V3f rj;
-  joint_tf(sc, j, q, Rj, rj);
+  joint_tf_sc(sc, j, q, s, c, Rj, rj);
   Xf X;
   X.E = transpose3(Rj);
   X.r = rj;
   return X;
 }
+__device__ __forceinline__ SV c_at(const Lds &L, int j) {
+  return j >= C0 ? L.sv_at(R_C + 6 * (j - C0)) : sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));
+}
 
 // Rolls out row `env` of Z (16 parameters for pick-and-place, 12 for
 // move-push) and writes its cost, tier, pose and (TRACE) per-step trace.
 // `lds_mem` is the block's R_ROWS x PP_LANES float array and `lane` this
-// lane's column in it; `mu_obj` is the instance's object friction draw (0:
-// the per-class coefficients).
+// lane's column in it.  The scene, its derived constants and the instance's
+// object friction draw (0: the per-class coefficients) come from `st`.
 template <bool TRACE>
-__device__ __forceinline__ void robot_env(const cem_scene &sc, float mu_obj, const float *__restrict__ Z, long env,
+__device__ __forceinline__ void robot_env(const DevState *__restrict__ st, const float *__restrict__ Z, long env,
                                           float *lds_mem, int lane, float *__restrict__ cost_out,
                                           uint8_t *__restrict__ tier_out, float *__restrict__ pose_out,
                                           float *__restrict__ trace, int trace_steps) {
+  const cem_scene &sc = st->scene;
+  const SceneConsts &sk = st->sk;
+  const float mu_obj = st->obj_mu;
   const Lds L{lds_mem, lane};
   const bool pnp = sc.kind == CEM_SCENE_PICKPLACE;
   const int n_act = pnp ? 4 : 2, n_par = pnp ? 16 : 12;
@@ -342,23 +361,26 @@ __device__ __forceinline__ void robot_env(const cem_scene &sc, float mu_obj, con
     for (int si = 0; si < sc.substeps; ++si) {
       const bool last = si == sc.substeps - 1;
       // ---- the object against the world (ground, static boxes) ----
-      const M3f oR = rot_of(ob.q);
+      Box OB;
+      OB.p = ob.p;
+      OB.R = rot_of(ob.q);
+      OB.h = ohe;
       Wrench W{v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)};
-      box_ground(ob, oR, ohe, kc, damp, mu_o_ground, eps2, W);
+      box_ground(ob, OB.R, ohe, kc, damp, mu_o_ground, eps2, W);
       for (int b = 0; b < sc.n_static; ++b) {
-        const M3f SR = static_rot(sc, b);
-        const V3f SP = v3(sc.st_center[b][0], sc.st_center[b][1], sc.st_center[b][2]);
-        const V3f SH = v3(sc.st_half[b][0], sc.st_half[b][1], sc.st_half[b][2]);
+        const Box SB = static_box(sc, sk, b);
         const float mu = mu_drawn ? mu_obj : (sc.st_ramp[b] ? sc.mu_ramp : sc.mu_static);
-        if (!spheres_overlap(ob.p, ohe, SP, SH)) continue;
-        verts_in_box(ob.p, oR, ohe, SP, SR, SH, [&](bool in, V3f x, V3f n, float d) {
-          const V3f r = x - ob.p;
-          apply(W, r, contact_force(in, n, d, ob.v + cross(ob.w, r), kc, damp, mu, eps2));
+        const Rel r = rel_of(OB, SB);
+        if (face_separated(r, ohe, SB.h)) continue;
+        // object vertices in the static box (A = object)
+        verts_in_box(r, ohe, SB, [&](V3f x, V3f n, float d) {
+          const V3f ro = x - ob.p;
+          apply(W, ro, contact_force(true, n, d, ob.v + cross(ob.w, ro), kc, damp, mu, eps2));
         });
-        verts_in_box(SP, SR, SH, ob.p, oR, ohe, [&](bool in, V3f x, V3f n, float d) {
-          const V3f r = x - ob.p;
-          // A = static box, B = object: the object receives the negative
-          apply(W, r, -contact_force(in, n, d, v3(0.0f, 0.0f, 0.0f) - (ob.v + cross(ob.w, r)), kc, damp, mu, eps2));
+        // static-box vertices in the object (A = static box, the object receives the negative)
+        verts_in_box(rel_swap(r), SB.h, OB, [&](V3f x, V3f n, float d) {
+          const V3f ro = x - ob.p;
+          apply(W, ro, -contact_force(true, n, d, v3(0.0f, 0.0f, 0.0f) - (ob.v + cross(ob.w, ro)), kc, damp, mu, eps2));
         });
       }
 
@@ -372,9 +394,16 @@ __device__ __forceinline__ void robot_env(const cem_scene &sc, float mu_obj, con
       SV v8 = vprev;
       for (int j = 0; j < NJ; ++j) {
         const bool finger = j >= FL;
+        const float qj = L.at(R_Q + j);
+        float s = 0.0f, c = 1.0f;
+        if (sc.j_type[j] == 0) sincosf(qj, &s, &c);
+        if (j >= C0 && j <= PALM) {
+          L.at(R_CS + 2 * (j - C0)) = s;
+          L.at(R_CS + 2 * (j - C0) + 1) = c;
+        }
         M3f Rj;
         V3f rj;
-        joint_tf(sc, j, L.at(R_Q + j), Rj, rj);
+        joint_tf_sc(sc, j, qj, s, c, Rj, rj);
         Xf X;
         X.E = transpose3(Rj);
         X.r = rj;
@@ -385,12 +414,14 @@ __device__ __forceinline__ void robot_env(const cem_scene &sc, float mu_obj, con
         const V3f pb = pp + mul(Rp, rj);
         const SV vJ = s_vec(sc, j, L.at(R_QD + j));
         const SV vb = (j == 0 ? sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)) : x_motion(X, vp)) + vJ;
-        L.sv_put(R_C + 6 * j, j == 0 ? sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)) : crm(vb, vJ));
-        SV pAj = crf(vb, sym_mul(body_inertia(sc, j), vb));
+        if (j >= C0) L.sv_put(R_C + 6 * (j - C0), crm(vb, vJ));
+        SV pAj = crf(vb, sym_mul(inertia_of(sk, j), vb));
         if (j == BASEB || finger) {
           // contacts on this link: world forces -> body spatial force, subtracted from pA
-          const V3f bc = pb + mul(Rb, v3(sc.b_com[j][0], sc.b_com[j][1], sc.b_com[j][2]));
-          const V3f bh = v3(sc.b_half[j][0], sc.b_half[j][1], sc.b_half[j][2]);
+          Box LB;
+          LB.p = pb + mul(Rb, v3(sc.b_com[j][0], sc.b_com[j][1], sc.b_com[j][2]));
+          LB.R = Rb;
+          LB.h = v3(sc.b_half[j][0], sc.b_half[j][1], sc.b_half[j][2]);
           SV fe = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));
           auto link_v = [&](V3f x) {
             const V3f xb = mulT(Rb, x - pb);
@@ -402,42 +433,41 @@ __device__ __forceinline__ void robot_env(const cem_scene &sc, float mu_obj, con
           };
           if (j == BASEB) {
             for (int b = 0; b < sc.n_static; ++b) {
-              const M3f SR = static_rot(sc, b);
-              const V3f SP = v3(sc.st_center[b][0], sc.st_center[b][1], sc.st_center[b][2]);
-              const V3f SH = v3(sc.st_half[b][0], sc.st_half[b][1], sc.st_half[b][2]);
-              if (!spheres_overlap(bc, bh, SP, SH)) continue;
-              verts_in_box(bc, Rb, bh, SP, SR, SH, [&](bool in, V3f x, V3f n, float d) {
-                link_f(x, contact_force(in, n, d, link_v(x), kc, damp, sc.mu_static, eps2));
+              const Box SB = static_box(sc, sk, b);
+              const Rel r = rel_of(LB, SB);
+              if (face_separated(r, LB.h, SB.h)) continue;
+              verts_in_box(r, LB.h, SB, [&](V3f x, V3f n, float d) {
+                link_f(x, contact_force(true, n, d, link_v(x), kc, damp, sc.mu_static, eps2));
               });
-              verts_in_box(SP, SR, SH, bc, Rb, bh, [&](bool in, V3f x, V3f n, float d) {
-                link_f(x, -contact_force(in, n, d, v3(0.0f, 0.0f, 0.0f) - link_v(x), kc, damp, sc.mu_static, eps2));
+              verts_in_box(rel_swap(r), SB.h, LB, [&](V3f x, V3f n, float d) {
+                link_f(x, -contact_force(true, n, d, v3(0.0f, 0.0f, 0.0f) - link_v(x), kc, damp, sc.mu_static, eps2));
               });
             }
-          } else if (spheres_overlap(bc, bh, ob.p, ohe)) {
+          } else {
+            const Rel r = rel_of(LB, OB);
             bool any = false;
-            // finger vertices in the object (A = finger, B = object)
-            verts_in_box(bc, Rb, bh, ob.p, oR, ohe, [&](bool in, V3f x, V3f n, float d) {
-              const V3f ro = x - ob.p;
-              const V3f F = contact_force(in, n, d, link_v(x) - (ob.v + cross(ob.w, ro)), kc, damp, mu_o_tool, eps2);
-              link_f(x, F);
-              apply(W, ro, -F);
-              any = any || in;
-            });
-            // object vertices in the finger (A = object, B = finger)
-            verts_in_box(ob.p, oR, ohe, bc, Rb, bh, [&](bool in, V3f x, V3f n, float d) {
-              const V3f ro = x - ob.p;
-              const V3f F = contact_force(in, n, d, (ob.v + cross(ob.w, ro)) - link_v(x), kc, damp, mu_o_tool, eps2);
-              apply(W, ro, F);
-              link_f(x, -F);
-              any = any || in;
-            });
+            if (!face_separated(r, LB.h, ohe)) {
+              // finger vertices in the object (A = finger, B = object)
+              verts_in_box(r, LB.h, OB, [&](V3f x, V3f n, float d) {
+                const V3f ro = x - ob.p;
+                const V3f F = contact_force(true, n, d, link_v(x) - (ob.v + cross(ob.w, ro)), kc, damp, mu_o_tool, eps2);
+                link_f(x, F);
+                apply(W, ro, -F);
+                any = true;
+              });
+              // object vertices in the finger (A = object, B = finger)
+              verts_in_box(rel_swap(r), ohe, LB, [&](V3f x, V3f n, float d) {
+                const V3f ro = x - ob.p;
+                const V3f F = contact_force(true, n, d, (ob.v + cross(ob.w, ro)) - link_v(x), kc, damp, mu_o_tool, eps2);
+                apply(W, ro, F);
+                link_f(x, -F);
+                any = true;
+              });
+            }
             if (last) {
               if (j == FL) touchL = any;
               else touchR = any;
             }
-          } else if (last) {  // finger far from the object: no contact
-            if (j == FL) touchL = false;
-            else touchR = false;
           }
           pAj = pAj - fe;
         }
@@ -455,13 +485,13 @@ __device__ __forceinline__ void robot_env(const cem_scene &sc, float mu_obj, con
       }
 
       // ---- ABA pass 2 (leaves to root): articulated inertias, U, D, u ----
-      Sym6 IA8 = body_inertia(sc, PALM);
+      Sym6 IA8 = inertia_of(sk, PALM);
       Sym6 IAc = IA8;
       for (int j = NJ - 1; j >= 0; --j) {
         Sym6 IA;
         {
           // element-wise select (a struct-level select would be lowered through memory)
-          const Sym6 Ib = body_inertia(sc, j);
+          const Sym6 Ib = inertia_of(sk, j);
           const bool leaf = j >= FL, palm = j == PALM;
 #pragma unroll
           for (int i = 0; i < 6; ++i) {
@@ -483,14 +513,15 @@ __device__ __forceinline__ void robot_env(const cem_scene &sc, float mu_obj, con
         L.at(R_UU + j) = u;
         if (j > 0) {
           sym_rank1(IA, Uj, di);
-          const SV pa = pAj + sym_mul(IA, L.sv_at(R_C + 6 * j)) + (u * di) * Uj;
-          const Xf X = joint_X(sc, j, qj);
+          SV pa = pAj + (u * di) * Uj;
+          if (j >= C0) pa = pa + sym_mul(IA, L.sv_at(R_C + 6 * (j - C0)));
+          const Xf X = joint_X(sc, L, j, qj);
           const Sym6 Ip = congruence(X, IA);
           const int p = parent_of(j);
           L.sv_put(R_P + 6 * p, L.sv_at(R_P + 6 * p) + x_force_T(X, pa));
           if (p == PALM) sym_add(IA8, Ip);
           else {
-            IAc = body_inertia(sc, p);
+            IAc = inertia_of(sk, p);
             sym_add(IAc, Ip);
           }
         }
@@ -501,8 +532,8 @@ __device__ __forceinline__ void robot_env(const cem_scene &sc, float mu_obj, con
       SV a8 = a_prev;
       for (int j = 0; j < NJ; ++j) {
         const float qj = L.at(R_Q + j);
-        const Xf X = joint_X(sc, j, qj);
-        const SV ap = x_motion(X, j >= FL ? a8 : a_prev) + L.sv_at(R_C + 6 * j);
+        const Xf X = joint_X(sc, L, j, qj);
+        const SV ap = x_motion(X, j >= FL ? a8 : a_prev) + c_at(L, j);
         const float qdd = (L.at(R_UU + j) - dot6(L.sv_at(R_P + 6 * j), ap)) * L.at(R_DI + j);
         const SV aj = ap + s_vec(sc, j, qdd);
         if (j < FL) a_prev = aj;

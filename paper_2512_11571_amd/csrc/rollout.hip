@@ -50,9 +50,31 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
       if (d.kind == CEM_SCENE_PUSH)
         push_env<TRACE>(sc, d.st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
       else
-        robot_env<TRACE>(sc, d.st->obj_mu, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
+        robot_env<TRACE>(d.st, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
     }
     if (!queue) break;
+  }
+}
+
+// Scene constants used every substep, derived once per context: the static
+// boxes' rotations Rz(yaw) Ry(pitch) and each body's spatial inertia about its
+// frame origin (a solid box of the body's mass about its centre of mass).
+__global__ void scene_consts_kernel(DevState *st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const cem_scene &sc = st->scene;
+  SceneConsts &k = st->sk;
+  for (int b = 0; b < CEM_MAX_STATIC; ++b) {
+    const M3f R = static_rot(sc, b);
+    const float m[9] = {R.r0.x, R.r0.y, R.r0.z, R.r1.x, R.r1.y, R.r1.z, R.r2.x, R.r2.y, R.r2.z};
+    for (int i = 0; i < 9; ++i) k.st_R[b][i] = m[i];
+  }
+  for (int j = 0; j < CEM_MAX_JOINTS; ++j) {
+    const Sym6 I = body_inertia(sc, j);
+    for (int i = 0; i < 6; ++i) {
+      k.I_body[j][i] = I.A[i];
+      k.I_body[j][15 + i] = I.C[i];
+    }
+    for (int i = 0; i < 9; ++i) k.I_body[j][6 + i] = I.B[i];
   }
 }
 
@@ -104,6 +126,11 @@ hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_step
   else
     hipLaunchKernelGGL(rollout_items_kernel<false>, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items,
                        nullptr, 0, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_scene_consts(DevState *st, hipStream_t s) {
+  hipLaunchKernelGGL(scene_consts_kernel, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 
