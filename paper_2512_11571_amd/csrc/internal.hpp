@@ -58,6 +58,16 @@ struct WorkItem {
   int32_t inst, env0, n, pad;
 };
 
+// Read-only views for the device code.  The scene, its derived constants and
+// the rest of a context's state do not change while a rollout runs; reading
+// them through the constant address space lets the compiler issue scalar
+// loads for the wave-uniform accesses.
+typedef const __attribute__((address_space(4))) cem_scene CScene;
+typedef const __attribute__((address_space(4))) SceneConsts CConsts;
+typedef const __attribute__((address_space(4))) DevState CDevState;
+typedef const __attribute__((address_space(4))) InstDesc CInstDesc;
+typedef const __attribute__((address_space(4))) WorkItem CWorkItem;
+
 // Launchers (each file owns its kernels).
 hipError_t launch_instance_draw(const cem_scene &sc, uint64_t seed, uint32_t inst, DevState *st, hipStream_t s);
 hipError_t launch_sample(uint64_t seed, uint32_t inst, int32_t iter, const DevState *st, int pop, int D, float *Z,

@@ -21,7 +21,7 @@ namespace {
 
 // Rolls out row i of Z (theta, o, s) and writes its cost, tier, pose and (TRACE) trace.
 template <bool TRACE>
-__device__ __forceinline__ void push_env(const cem_scene &sc, const DevState *__restrict__ st,
+__device__ __forceinline__ void push_env(CScene &sc, CDevState *st,
                                          const float *__restrict__ Z, long i, float *__restrict__ cost_out,
                                          uint8_t *__restrict__ tier_out, float *__restrict__ pose_out,
                                          float *__restrict__ trace, int trace_steps) {

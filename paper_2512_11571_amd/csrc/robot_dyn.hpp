@@ -147,7 +147,7 @@ __device__ __forceinline__ Sym6 congruence(const Xf &X, const Sym6 &I) {
 }
 
 // Spatial inertia of body j about its origin: A = Ic + m (|c|^2 1 - c c^T), B = m cx, C = m 1.
-__device__ __forceinline__ Sym6 body_inertia(const cem_scene &sc, int j) {
+__device__ __forceinline__ Sym6 body_inertia(CScene &sc, int j) {
   const float m = sc.b_mass[j];
   const float hx = sc.b_half[j][0], hy = sc.b_half[j][1], hz = sc.b_half[j][2];
   const V3f c = v3(sc.b_com[j][0], sc.b_com[j][1], sc.b_com[j][2]);
@@ -174,7 +174,7 @@ __device__ __forceinline__ V3f unit_axis(int a) {
 
 // Joint j at coordinate q (with s = sin q, c = cos q for a revolute joint):
 // rotation R (child -> parent) and child origin r (parent coords).
-__device__ __forceinline__ void joint_tf_sc(const cem_scene &sc, int j, float q, float s, float c, M3f &R, V3f &r) {
+__device__ __forceinline__ void joint_tf_sc(CScene &sc, int j, float q, float s, float c, M3f &R, V3f &r) {
   const V3f o = v3(sc.j_origin[j][0], sc.j_origin[j][1], sc.j_origin[j][2]);
   const V3f a = unit_axis(sc.j_axis[j]);
   if (sc.j_type[j] == 0) {
@@ -190,7 +190,7 @@ __device__ __forceinline__ void joint_tf_sc(const cem_scene &sc, int j, float q,
     r = o + q * a;
   }
 }
-__device__ __forceinline__ void joint_tf(const cem_scene &sc, int j, float q, M3f &R, V3f &r) {
+__device__ __forceinline__ void joint_tf(CScene &sc, int j, float q, M3f &R, V3f &r) {
   float s = 0.0f, c = 1.0f;
   if (sc.j_type[j] == 0) sincosf(q, &s, &c);
   joint_tf_sc(sc, j, q, s, c, R, r);
@@ -212,22 +212,22 @@ __device__ __forceinline__ M3f matmul3(const M3f &A, const M3f &B) {
 }
 __device__ __forceinline__ int parent_of(int j) { return j <= PALM ? j - 1 : PALM; }
 // motion subspace: index of the nonzero entry (0..5) and its sign
-__device__ __forceinline__ int s_index(const cem_scene &sc, int j) { return (sc.j_type[j] == 0 ? 0 : 3) + sc.j_axis[j] % 3; }
-__device__ __forceinline__ float s_sign(const cem_scene &sc, int j) { return sc.j_axis[j] < 3 ? 1.0f : -1.0f; }
-__device__ __forceinline__ SV s_vec(const cem_scene &sc, int j, float x) {
+__device__ __forceinline__ int s_index(CScene &sc, int j) { return (sc.j_type[j] == 0 ? 0 : 3) + sc.j_axis[j] % 3; }
+__device__ __forceinline__ float s_sign(CScene &sc, int j) { return sc.j_axis[j] < 3 ? 1.0f : -1.0f; }
+__device__ __forceinline__ SV s_vec(CScene &sc, int j, float x) {
   const int k = s_index(sc, j);
   const float v = s_sign(sc, j) * x;
   return sv(v3(k == 0 ? v : 0.0f, k == 1 ? v : 0.0f, k == 2 ? v : 0.0f),
             v3(k == 3 ? v : 0.0f, k == 4 ? v : 0.0f, k == 5 ? v : 0.0f));
 }
-__device__ __forceinline__ float s_comp(const cem_scene &sc, int j, SV x) {
+__device__ __forceinline__ float s_comp(CScene &sc, int j, SV x) {
   const int k = s_index(sc, j);
   const float c = k == 0 ? x.a.x : k == 1 ? x.a.y : k == 2 ? x.a.z : k == 3 ? x.b.x : k == 4 ? x.b.y : x.b.z;
   return s_sign(sc, j) * c;
 }
 
 // World poses of bodies 0..PALM (chain) for the arm kinematics.
-__device__ __forceinline__ void chain_fk(const cem_scene &sc, const float *q, M3f *Rw, V3f *pw) {
+__device__ __forceinline__ void chain_fk(CScene &sc, const float *q, M3f *Rw, V3f *pw) {
   M3f Rp;
   Rp.r0 = v3(1.0f, 0.0f, 0.0f); Rp.r1 = v3(0.0f, 1.0f, 0.0f); Rp.r2 = v3(0.0f, 0.0f, 1.0f);
   V3f pp = v3(0.0f, 0.0f, 0.0f);
@@ -243,13 +243,13 @@ __device__ __forceinline__ void chain_fk(const cem_scene &sc, const float *q, M3
   }
 }
 
-__device__ __forceinline__ V3f ee_point(const cem_scene &sc, const M3f &Rp, V3f pp) {
+__device__ __forceinline__ V3f ee_point(CScene &sc, const M3f &Rp, V3f pp) {
   return pp + mul(Rp, v3(sc.ee_offset[0], sc.ee_offset[1], sc.ee_offset[2]));
 }
 
 // Damped least squares on the arm joints 3..8 toward (pt, Rt):
 // dq = J^T (J J^T + lambda^2 I)^-1 e, e = (pt - p_ee, 1/2 sum_k r_k x rt_k).
-__device__ __forceinline__ void ik_dls(const cem_scene &sc, float *q, V3f pt, const M3f &Rt) {
+__device__ __forceinline__ void ik_dls(CScene &sc, float *q, V3f pt, const M3f &Rt) {
   const float lam2 = sc.ik_lambda * sc.ik_lambda;
   for (int it = 0; it < sc.ik_iters; ++it) {
     M3f Rw[PALM + 1];
@@ -333,7 +333,7 @@ __device__ __forceinline__ float wrap_pi(float a) {
 }
 
 // Static box k pose: Rz(yaw) Ry(pitch).
-__device__ __forceinline__ M3f static_rot(const cem_scene &sc, int k) {
+__device__ __forceinline__ M3f static_rot(CScene &sc, int k) {
   float sy, cy, sp, cp;
   sincosf(sc.st_yaw[k], &sy, &cy);
   sincosf(sc.st_pitch[k], &sp, &cp);
@@ -421,19 +421,19 @@ __device__ __forceinline__ void verts_in_box(const Rel &r, V3f hA, const Box &B,
   }
 }
 
-__device__ __forceinline__ Box static_box(const cem_scene &sc, const SceneConsts &k, int b) {
+__device__ __forceinline__ Box static_box(CScene &sc, CConsts &k, int b) {
   Box B;
   B.p = v3(sc.st_center[b][0], sc.st_center[b][1], sc.st_center[b][2]);
   B.h = v3(sc.st_half[b][0], sc.st_half[b][1], sc.st_half[b][2]);
-  const float *m = k.st_R[b];
+  const __attribute__((address_space(4))) float *m = k.st_R[b];
   B.R.r0 = v3(m[0], m[1], m[2]);
   B.R.r1 = v3(m[3], m[4], m[5]);
   B.R.r2 = v3(m[6], m[7], m[8]);
   return B;
 }
-__device__ __forceinline__ Sym6 inertia_of(const SceneConsts &k, int j) {
+__device__ __forceinline__ Sym6 inertia_of(CConsts &k, int j) {
   Sym6 I;
-  const float *m = k.I_body[j];
+  const __attribute__((address_space(4))) float *m = k.I_body[j];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     I.A[i] = m[i];

@@ -68,7 +68,7 @@ struct Lds {
 // Parent -> child transform of joint j at q, with the substep's sine and
 // cosine of joints C0..PALM taken from their LDS rows (the other joints are
 // prismatic).
-__device__ __forceinline__ Xf joint_X(const cem_scene &sc, const Lds &L, int j, float q) {
+__device__ __forceinline__ Xf joint_X(CScene &sc, const Lds &L, int j, float q) {
   float s = 0.0f, c = 1.0f;
   if (j >= C0 && j <= PALM) {
     s = L.at(R_CS + 2 * (j - C0));
@@ -92,12 +92,12 @@ __device__ __forceinline__ SV c_at(const Lds &L, int j) {
 // lane's column in it.  The scene, its derived constants and the instance's
 // object friction draw (0: the per-class coefficients) come from `st`.
 template <bool TRACE>
-__device__ __forceinline__ void robot_env(const DevState *__restrict__ st, const float *__restrict__ Z, long env,
+__device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict__ Z, long env,
                                           float *lds_mem, int lane, float *__restrict__ cost_out,
                                           uint8_t *__restrict__ tier_out, float *__restrict__ pose_out,
                                           float *__restrict__ trace, int trace_steps) {
-  const cem_scene &sc = st->scene;
-  const SceneConsts &sk = st->sk;
+  CScene &sc = st->scene;
+  CConsts &sk = st->sk;
   const float mu_obj = st->obj_mu;
   const Lds L{lds_mem, lane};
   const bool pnp = sc.kind == CEM_SCENE_PICKPLACE;

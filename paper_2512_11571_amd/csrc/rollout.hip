@@ -28,14 +28,22 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
     if (queue) {
       int v = 0;
       if (lane == 0) v = atomicAdd(queue, 1);
-      it = __shfl(v, 0, 64);
+      it = __builtin_amdgcn_readfirstlane(v);  // lane 0's ticket, provably wave-uniform
     }
     if (it >= n_items) break;  // every wave of the grid reaches this once the queue is drained
     InstDesc d;
     int env0, n;
     if (insts) {
-      const WorkItem w = items[it];
-      d = insts[w.inst];
+      const CWorkItem &w = ((CWorkItem *)items)[it];
+      const CInstDesc &di = ((CInstDesc *)insts)[w.inst];
+      d.st = di.st;
+      d.Z = di.Z;
+      d.cost = di.cost;
+      d.tier = di.tier;
+      d.pose = di.pose;
+      d.kind = di.kind;
+      d.pop = di.pop;
+      d.iters = di.iters;
       env0 = w.env0;
       n = w.n;
     } else {
@@ -43,14 +51,14 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
       env0 = it * 64;
       n = min(64, d.pop - env0);
     }
-    const bool active = !(check_iter && d.st->iter >= d.iters);
+    CDevState *st = (CDevState *)d.st;
+    const bool active = !(check_iter && st->iter >= d.iters);
     if (active && lane < n) {
       const long env = env0 + lane;
-      const cem_scene &sc = d.st->scene;
       if (d.kind == CEM_SCENE_PUSH)
-        push_env<TRACE>(sc, d.st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
+        push_env<TRACE>(st->scene, st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
       else
-        robot_env<TRACE>(d.st, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
+        robot_env<TRACE>(st, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
     }
     if (!queue) break;
   }
@@ -61,7 +69,7 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
 // frame origin (a solid box of the body's mass about its centre of mass).
 __global__ void scene_consts_kernel(DevState *st) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const cem_scene &sc = st->scene;
+  CScene &sc = *(CScene *)&st->scene;
   SceneConsts &k = st->sk;
   for (int b = 0; b < CEM_MAX_STATIC; ++b) {
     const M3f R = static_rot(sc, b);
