@@ -42,15 +42,19 @@ namespace cem {
 namespace {
 
 constexpr int PP_LANES = 64;  // lanes sharing one LDS block of rows
-// LDS rows (each PP_LANES floats): q, qd, qref; bias acceleration c (6 per
-// body, bodies 2..10: the first two bodies only translate, so their c is
-// zero); bias force pA then U (6 per body); 1/D; u; the push's end-of-line arm
-// targets; sin and cos of joints 2..8 for the current substep.  195 rows x 256 B
-// keeps three waves per CU.
-constexpr int C0 = 2;  // first body with a stored bias acceleration
-constexpr int R_Q = 0, R_QD = R_Q + NJ, R_QREF = R_QD + NJ, R_C = R_QREF + NJ, R_P = R_C + 6 * (NJ - C0),
-              R_DI = R_P + 6 * NJ, R_UU = R_DI + NJ, R_QC = R_UU + NJ, R_CS = R_QC + NARM,
-              R_ROWS = R_CS + 2 * (PALM - C0 + 1);
+// LDS rows (each PP_LANES floats):
+//   q, qd (11 each); qref (10: joints 0..8, one row for both fingers);
+//   the bias accelerations c_j = v_j x (S_j qd_j) that are not identically zero:
+//     bodies 0, 1 only translate, so c_0 = c_1 = 0; body 2's angular velocity
+//     is its own joint's, so c_2 has a zero angular part; the fingers slide,
+//     so theirs is zero too: 3 rows for body 2, 6 for each of bodies 3..8, 3
+//     for each finger (45);
+//   the bias force pA (pass 1), then U / D (passes 2, 3) (6 per body);
+//   u / D (11).
+// 154 rows x 256 B = 39,424 B per wave: four waves fit in a CU's LDS.
+constexpr int R_Q = 0, R_QD = R_Q + NJ, R_QREF = R_QD + NJ, R_C = R_QREF + PALM + 2, R_P = R_C + 3 + 6 * NARM + 6,
+              R_UD = R_P + 6 * NJ, R_ROWS = R_UD + NJ;
+static_assert(R_ROWS * PP_LANES * 4 <= 40960, "four waves per CU");
 
 struct Lds {
   float *m;
@@ -65,26 +69,37 @@ struct Lds {
   }
 };
 
-// Parent -> child transform of joint j at q, with the substep's sine and
-// cosine of joints C0..PALM taken from their LDS rows (the other joints are
-// prismatic).
-__device__ __forceinline__ Xf joint_X(CScene &sc, const Lds &L, int j, float q) {
-  float s = 0.0f, c = 1.0f;
-  if (j >= C0 && j <= PALM) {
-    s = L.at(R_CS + 2 * (j - C0));
-    c = L.at(R_CS + 2 * (j - C0) + 1);
-  }
+__device__ __forceinline__ Xf joint_X(CScene &sc, int j, float q) {
   M3f Rj;
   V3f rj;
-  joint_tf_sc(sc, j, q, s, c, Rj, rj);
+  joint_tf(sc, j, q, Rj, rj);
   Xf X;
   X.E = transpose3(Rj);
   X.r = rj;
   return X;
 }
+// Bias acceleration c_j from its stored components (see the row layout).
 __device__ __forceinline__ SV c_at(const Lds &L, int j) {
-  return j >= C0 ? L.sv_at(R_C + 6 * (j - C0)) : sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));
+  const V3f z = v3(0.0f, 0.0f, 0.0f);
+  if (j < 2) return sv(z, z);
+  if (j == 2) return sv(z, v3(L.at(R_C), L.at(R_C + 1), L.at(R_C + 2)));
+  if (j <= PALM) return L.sv_at(R_C + 3 + 6 * (j - 3));
+  const int r = R_C + 3 + 6 * NARM + 3 * (j - FL);
+  return sv(z, v3(L.at(r), L.at(r + 1), L.at(r + 2)));
 }
+__device__ __forceinline__ void c_put(const Lds &L, int j, SV c) {
+  if (j < 2) return;
+  if (j == 2) {
+    L.at(R_C) = c.b.x; L.at(R_C + 1) = c.b.y; L.at(R_C + 2) = c.b.z;
+  } else if (j <= PALM) {
+    L.sv_put(R_C + 3 + 6 * (j - 3), c);
+  } else {
+    const int r = R_C + 3 + 6 * NARM + 3 * (j - FL);
+    L.at(r) = c.b.x; L.at(r + 1) = c.b.y; L.at(r + 2) = c.b.z;
+  }
+}
+// Joint reference row (both fingers share one).
+__device__ __forceinline__ int qref_row(int j) { return R_QREF + (j < FL ? j : FL); }
 
 // Rolls out row `env` of Z (16 parameters for pick-and-place, 12 for
 // move-push) and writes its cost, tier, pose and (TRACE) per-step trace.
@@ -124,7 +139,7 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
   for (int j = 0; j < NJ; ++j) {
     L.at(R_Q + j) = sc.q0[j];
     L.at(R_QD + j) = 0.0f;
-    L.at(R_QREF + j) = sc.q0[j];
+    if (j <= FL) L.at(R_QREF + j) = sc.q0[j];
   }
   FreeBody ob;
   ob.p = v3(sc.obj_pos0[0], sc.obj_pos0[1], sc.obj_pos0[2] - om * g / (4.0f * kc));
@@ -143,6 +158,8 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
   V3f ptarget = v3(0.0f, 0.0f, 0.0f);
   float base_from[3] = {0.0f, 0.0f, 0.0f}, base_to[3] = {0.0f, 0.0f, 0.0f}, t_move = 1.0f;
   float Ta = sc.t_approach, Td = sc.t_descend, Tl = sc.t_lift, Tp = sc.t_transfer, Tq = dt;
+  float push_nominal = 0.0f;
+  bool push_ready = false;
   float finger_cmd = sc.finger_open;
   bool touchL = false, touchR = false;
   int unsuccessful = 0;
@@ -202,16 +219,13 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
       ik_dls(sc, q, ps, Rt);
 #pragma unroll
       for (int j = 0; j < NARM; ++j) qb[j] = q[ARM0 + j];
-      ik_dls(sc, q, pe, Rt);
-      float qc[NARM];
-#pragma unroll
-      for (int j = 0; j < NARM; ++j) {
-        qc[j] = q[ARM0 + j];
-        L.at(R_QC + j) = qc[j];
-      }
+      // the end-of-line anchor (IK from (base at action start, qb) toward pe)
+      // is solved when the push phase begins, into qa, which that phase no
+      // longer needs
       Ta = span(qs, qa, sc.t_approach);
       Td = span(qa, qb, sc.t_descend);
-      Tq = fmaxf(span(qb, qc, dist / vp), dt);
+      push_nominal = dist / vp;
+      push_ready = false;
       ptarget = pe;
     } else {
       M3f Rt;
@@ -329,16 +343,39 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
         }
         finger_cmd = tau < Ta + Td ? sc.finger_open : sc.finger_closed;
       } else if (kind == PUSH) {
+        if (tau >= Ta + Td && !push_ready) {
+          float pw[4];
+          action_params(zp, 2, pw);
+          float sg, cg;
+          sincosf(pw[3], &sg, &cg);
+          M3f Rt;
+          Rt.r0 = v3(cg, sg, 0.0f);
+          Rt.r1 = v3(sg, -cg, 0.0f);
+          Rt.r2 = v3(0.0f, 0.0f, -1.0f);
+          float qq[NJ];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) qq[c] = qstart[c];
+#pragma unroll
+          for (int j = 0; j < NARM; ++j) qq[ARM0 + j] = qb[j];
+          qq[FL] = 0.0f;
+          qq[FR] = 0.0f;
+          ik_dls(sc, qq, ptarget, Rt);
+#pragma unroll
+          for (int j = 0; j < NARM; ++j) qa[j] = qq[ARM0 + j];
+          Tq = fmaxf(span(qb, qa, push_nominal), dt);
+          push_ready = true;
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = qstart[c];
 #pragma unroll
         for (int j = 0; j < NARM; ++j) {
+          // qa: the pre-push pose until the push phase, then the end-of-line anchor
           float v;
-          const float s0 = qstart[ARM0 + j], qcj = L.at(R_QC + j);
+          const float s0 = qstart[ARM0 + j];
           if (tau < Ta) v = s0 + smooth01(tau / Ta) * (qa[j] - s0);
           else if (tau < Ta + Td) v = qa[j] + smooth01((tau - Ta) / Td) * (qb[j] - qa[j]);
-          else if (tau < Ta + Td + Tq) v = qb[j] + smooth01((tau - Ta - Td) / Tq) * (qcj - qb[j]);
-          else v = qcj;
+          else if (tau < Ta + Td + Tq) v = qb[j] + smooth01((tau - Ta - Td) / Tq) * (qa[j] - qb[j]);
+          else v = qa[j];
           r[3 + j] = v;
         }
         finger_cmd = tau < Ta + Td + Tq ? sc.finger_closed : sc.finger_open;
@@ -356,7 +393,6 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
       for (int j = 0; j < NARM + 3; ++j) L.at(R_QREF + j) = r[j];
     }
     L.at(R_QREF + FL) = finger_cmd;
-    L.at(R_QREF + FR) = finger_cmd;
 
     for (int si = 0; si < sc.substeps; ++si) {
       const bool last = si == sc.substeps - 1;
@@ -395,15 +431,9 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
       for (int j = 0; j < NJ; ++j) {
         const bool finger = j >= FL;
         const float qj = L.at(R_Q + j);
-        float s = 0.0f, c = 1.0f;
-        if (sc.j_type[j] == 0) sincosf(qj, &s, &c);
-        if (j >= C0 && j <= PALM) {
-          L.at(R_CS + 2 * (j - C0)) = s;
-          L.at(R_CS + 2 * (j - C0) + 1) = c;
-        }
         M3f Rj;
         V3f rj;
-        joint_tf_sc(sc, j, qj, s, c, Rj, rj);
+        joint_tf(sc, j, qj, Rj, rj);
         Xf X;
         X.E = transpose3(Rj);
         X.r = rj;
@@ -414,7 +444,7 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
         const V3f pb = pp + mul(Rp, rj);
         const SV vJ = s_vec(sc, j, L.at(R_QD + j));
         const SV vb = (j == 0 ? sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)) : x_motion(X, vp)) + vJ;
-        if (j >= C0) L.sv_put(R_C + 6 * (j - C0), crm(vb, vJ));
+        c_put(L, j, crm(vb, vJ));
         SV pAj = crf(vb, sym_mul(inertia_of(sk, j), vb));
         if (j == BASEB || finger) {
           // contacts on this link: world forces -> body spatial force, subtracted from pA
@@ -504,18 +534,17 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
         const SV pAj = L.sv_at(R_P + 6 * j);
         const float qj = L.at(R_Q + j), qdj = L.at(R_QD + j);
         const float lim = sc.j_inom[j] * sc.accel_max;
-        const float tq = fmaxf(-lim, fminf(lim, sc.j_inom[j] * (wc * wc * (L.at(R_QREF + j) - qj) - 2.0f * zeta * wc * qdj)));
+        const float tq = fmaxf(-lim, fminf(lim, sc.j_inom[j] * (wc * wc * (L.at(qref_row(j)) - qj) - 2.0f * zeta * wc * qdj)));
         const SV Uj = s_sign(sc, j) * sym_col(IA, s_index(sc, j));
         const float di = 1.0f / s_comp(sc, j, Uj);
         const float u = tq - s_comp(sc, j, pAj);
-        L.sv_put(R_P + 6 * j, Uj);  // pA of body j is consumed: its row now holds U
-        L.at(R_DI + j) = di;
-        L.at(R_UU + j) = u;
+        L.sv_put(R_P + 6 * j, di * Uj);  // pA of body j is consumed: its row now holds U / D
+        L.at(R_UD + j) = u * di;
         if (j > 0) {
           sym_rank1(IA, Uj, di);
           SV pa = pAj + (u * di) * Uj;
-          if (j >= C0) pa = pa + sym_mul(IA, L.sv_at(R_C + 6 * (j - C0)));
-          const Xf X = joint_X(sc, L, j, qj);
+          if (j >= 2) pa = pa + sym_mul(IA, c_at(L, j));
+          const Xf X = joint_X(sc, j, qj);
           const Sym6 Ip = congruence(X, IA);
           const int p = parent_of(j);
           L.sv_put(R_P + 6 * p, L.sv_at(R_P + 6 * p) + x_force_T(X, pa));
@@ -532,9 +561,9 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
       SV a8 = a_prev;
       for (int j = 0; j < NJ; ++j) {
         const float qj = L.at(R_Q + j);
-        const Xf X = joint_X(sc, L, j, qj);
+        const Xf X = joint_X(sc, j, qj);
         const SV ap = x_motion(X, j >= FL ? a8 : a_prev) + c_at(L, j);
-        const float qdd = (L.at(R_UU + j) - dot6(L.sv_at(R_P + 6 * j), ap)) * L.at(R_DI + j);
+        const float qdd = L.at(R_UD + j) - dot6(L.sv_at(R_P + 6 * j), ap);
         const SV aj = ap + s_vec(sc, j, qdd);
         if (j < FL) a_prev = aj;
         if (j == PALM) a8 = aj;
