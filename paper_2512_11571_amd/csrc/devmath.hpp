@@ -17,6 +17,26 @@ __device__ __forceinline__ V3f cross(V3f a, V3f b) {
   return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
+// sin and cos of x (radians), for the bounded angles of the rollout
+// (|x| < 2^12): Cody and Waite's reduction x = k pi/2 + r with pi/2 split into
+// three FP32 parts (the products k * part are exact for such k), then the
+// Taylor polynomials of sin (to r^9) and cos (to r^10) on |r| <= pi/4, whose
+// truncation error is below 2^-28, and the quadrant k mod 4.
+__device__ __forceinline__ void sincos_rad(float x, float *s, float *c) {
+  const float k = rintf(x * 0.636619746685028076f);
+  float r = fmaf(-k, 1.57079637050628662f, x);
+  r = fmaf(-k, -4.37113882867379300e-08f, r);
+  r = fmaf(-k, -1.77635683940025046e-15f, r);
+  const float r2 = r * r;
+  const float ps = fmaf(r * r2, -1.0f / 6.0f + r2 * (1.0f / 120.0f + r2 * (-1.0f / 5040.0f + r2 * (1.0f / 362880.0f))), r);
+  const float pc =
+      fmaf(r2, -0.5f + r2 * (1.0f / 24.0f + r2 * (-1.0f / 720.0f + r2 * (1.0f / 40320.0f + r2 * (-1.0f / 3628800.0f)))),
+           1.0f);
+  const int q = (int)k & 3;
+  *s = q == 0 ? ps : (q == 1 ? pc : (q == 2 ? -ps : -pc));
+  *c = q == 0 ? pc : (q == 1 ? -ps : (q == 2 ? -pc : ps));
+}
+
 // Rotation matrix as three rows.
 struct M3f {
   V3f r0, r1, r2;

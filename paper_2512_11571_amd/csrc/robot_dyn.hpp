@@ -192,7 +192,7 @@ __device__ __forceinline__ void joint_tf_sc(CScene &sc, int j, float q, float s,
 }
 __device__ __forceinline__ void joint_tf(CScene &sc, int j, float q, M3f &R, V3f &r) {
   float s = 0.0f, c = 1.0f;
-  if (sc.j_type[j] == 0) sincosf(q, &s, &c);
+  if (sc.j_type[j] == 0) sincos_rad(q, &s, &c);
   joint_tf_sc(sc, j, q, s, c, R, r);
 }
 __device__ __forceinline__ M3f transpose3(const M3f &R) {

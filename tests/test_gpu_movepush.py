@@ -6,7 +6,7 @@ first 100 control steps on rows the oracle certifies as non-chaotic; over the
 full horizon, tier and cost agree on certified rows (cost to within two
 control steps).  Full size: the configured population (8192) and horizon
 (3000) in one launch, sampled rows checked one by one.  Statistical: median
-best cost of plan_solve over seeds 0-9 within 1e-2 relative at a reduced
+best cost of plan_solve over seeds 0-31 within 1e-2 relative at a reduced
 population.
 """
 import numpy as np
@@ -148,7 +148,11 @@ def test_plan_solve_median_matches_oracle(oracle, mp, Context):
     w = dict(mp, cem=dict(mp["cem"], pop=96, n_elite=12))
     iters = 2
     g, r = [], []
-    for seed in mp["cem"]["seeds"]:
+    # 32 seeds rather than the workload's 10: CE over contact dynamics is
+    # chaotic, so FP32 and FP64 runs that share iteration 0 exactly can pick
+    # different elites later, and a 10-seed median of quantised costs moves
+    # by a whole order statistic when one seed does
+    for seed in range(32):
         with Context(w, seed=seed) as c:
             res = c.plan_solve(iters)
         g.append(res["best_cost"])

@@ -5,7 +5,7 @@ Tolerance: FP32 robot joint angles / object pose within 1e-3 (rad, m) over
 the first 100 control steps on rows the oracle certifies as non-chaotic; over
 the full horizon, tier and cost agree on certified rows (cost to within two
 control steps, since action completion is decided on a threshold per step).
-Statistical: median best cost of plan_solve over seeds 0-9 within 1e-2
+Statistical: median best cost of plan_solve over seeds 0-31 within 1e-2
 relative at a reduced population.  Full size: the configured population and
 horizon, sampled rows checked one by one.
 """
@@ -121,7 +121,11 @@ def test_plan_solve_median_matches_oracle(oracle, pp, Context):
     w = dict(pp, cem=dict(pp["cem"], pop=128, n_elite=16))
     iters = 3
     g, r = [], []
-    for seed in pp["cem"]["seeds"]:
+    # 32 seeds rather than the workload's 10: CE over contact dynamics is
+    # chaotic, so FP32 and FP64 runs that share iteration 0 exactly can pick
+    # different elites later, and a 10-seed median of quantised costs moves
+    # by a whole order statistic when one seed does
+    for seed in range(32):
         with Context(w, seed=seed) as c:
             res = c.plan_solve(iters)
         g.append(res["best_cost"])
