@@ -227,12 +227,27 @@ inline int sphere_box(const V3<T> &c, T r, const V3<T> &p, const M3<T> &R, const
   return 1;
 }
 
-// Broadphase: boxes A and B (half extents ha, hb) can only touch when their
-// bounding spheres (radius = half diagonal) overlap.
-template <class T> inline bool spheres_overlap(const V3<T> &pa, const V3<T> &ha, const V3<T> &pb, const V3<T> &hb) {
-  const V3<T> d = pa - pb;
-  const T r = r_sqrt(dot(ha, ha)) + r_sqrt(dot(hb, hb));
-  return dot(d, d) <= r * r;
+// Broadphase for two boxes (centre p, rotation R box -> world, half extents h):
+// the separating-axis test restricted to the six face normals.  Along the unit
+// axis a, box A covers p_A.a +- sum_k h_A,k |a . R_A e_k|, and likewise B; if
+// the two intervals are disjoint along one of these axes the boxes do not
+// intersect, so no vertex of either lies inside the other.
+template <class T>
+inline bool face_separated(const V3<T> &pA, const M3<T> &RA, const V3<T> &hA, const V3<T> &pB, const M3<T> &RB,
+                           const V3<T> &hB) {
+  const V3<T> d = pB - pA;
+  const T ha[3] = {hA.x, hA.y, hA.z}, hb[3] = {hB.x, hB.y, hB.z};
+  for (int side = 0; side < 2; ++side) {
+    const M3<T> &R1 = side == 0 ? RA : RB, &R2 = side == 0 ? RB : RA;
+    const T *h1 = side == 0 ? ha : hb, *h2 = side == 0 ? hb : ha;
+    for (int k = 0; k < 3; ++k) {
+      const V3<T> a(R1.m[0][k], R1.m[1][k], R1.m[2][k]);
+      T r2 = T(0.0);
+      for (int j = 0; j < 3; ++j) r2 = r2 + h2[j] * r_abs(dot(a, V3<T>(R2.m[0][j], R2.m[1][j], R2.m[2][j])));
+      if (r_abs(dot(a, d)) > h1[k] + r2) return true;
+    }
+  }
+  return false;
 }
 
 // Vertex-face test of box A's vertices against box B (both dynamic or B static):

@@ -179,6 +179,8 @@ template <class T> inline T smooth(T x) {
 template <class T>
 RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z, double *trace, int trace_steps) {
   const Tree tr = tree_of(s);
+  Mat6<T> Ibody[MAXJ];  // body inertias: constants of the tree, built once
+  for (int j = 0; j < tr.n; ++j) Ibody[j] = body_inertia<T>(tr, j);
   const T h = T(s.dt) / T((double)s.substeps);
   const T dt = T(s.dt);
   const T g = T(s.gravity);
@@ -423,7 +425,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       // object against static boxes, both ways
       for (int b = 0; b < s.n_static; ++b) {
         const T mu = T(mu_drawn ? inst.obj_mu : (s.st_ramp[b] ? s.mu_ramp : s.mu_static));
-        if (!spheres_overlap(ob.p, ohe, SP[b], SH[b])) continue;
+        if (face_separated(ob.p, oR, ohe, SP[b], SR[b], SH[b])) continue;
         nc = box_verts_in_box(ob.p, oR, ohe, SP[b], SR[b], SH[b], cs);
         for (int i = 0; i < nc; ++i)
           add_force(W, ob.p, cs[i].x, penalty_force(cs[i], obj_vel(cs[i].x), V3<T>(), k, damp, mu, eps_v));
@@ -438,7 +440,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
         const V3<T> fc = pw[j] + mul(Rw[j], V3<T>(T(s.b_com[j][0]), T(s.b_com[j][1]), T(s.b_com[j][2])));
         const V3<T> fh(T(s.b_half[j][0]), T(s.b_half[j][1]), T(s.b_half[j][2]));
         bool any = false;
-        const bool nearf = spheres_overlap(fc, fh, ob.p, ohe);
+        const bool nearf = !face_separated(fc, Rw[j], fh, ob.p, oR, ohe);
         nc = nearf ? box_verts_in_box(fc, Rw[j], fh, ob.p, oR, ohe, cs) : 0;
         for (int i = 0; i < nc; ++i) {
           const V3<T> F = penalty_force(cs[i], link_vel(j, cs[i].x), obj_vel(cs[i].x), k, damp, T(mu_obj_tool), eps_v);
@@ -461,7 +463,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
         const V3<T> bc = pw[j] + mul(Rw[j], V3<T>(T(s.b_com[j][0]), T(s.b_com[j][1]), T(s.b_com[j][2])));
         const V3<T> bh(T(s.b_half[j][0]), T(s.b_half[j][1]), T(s.b_half[j][2]));
         for (int b = 0; b < s.n_static; ++b) {
-          if (!spheres_overlap(bc, bh, SP[b], SH[b])) continue;
+          if (face_separated(bc, Rw[j], bh, SP[b], SR[b], SH[b])) continue;
           nc = box_verts_in_box(bc, Rw[j], bh, SP[b], SR[b], SH[b], cs);
           for (int i = 0; i < nc; ++i)
             link_force(j, cs[i].x, penalty_force(cs[i], link_vel(j, cs[i].x), V3<T>(), k, damp, T(s.mu_static), eps_v));
@@ -478,7 +480,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
         tau[j] = r_max(-lim, r_min(lim, u));
       }
       T qdd[NJ];
-      aba(tr, q, qd, tau, fext, g, qdd);
+      aba<T>(tr, q, qd, tau, fext, g, qdd, nullptr, Ibody);
       for (int j = 0; j < NJ; ++j) {
         qd[j] = qd[j] + h * qdd[j];
         q[j] = q[j] + h * qd[j];

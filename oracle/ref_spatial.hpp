@@ -175,10 +175,12 @@ template <class T> inline void forward_kinematics(const Tree &tr, const T *q, M3
 // Articulated-body algorithm: qdd = FD(q, qd, tau, fext) with gravity gz
 // (m/s^2 along -z) entering as a fictitious base acceleration +gz z.
 // fext[j] is a spatial force on body j in its own coordinates.
-// vel_out (optional) receives the body spatial velocities.
+// vel_out (optional) receives the body spatial velocities.  Ibody (optional)
+// holds the body inertias body_inertia(tr, i), which depend on the tree only,
+// so a caller stepping the same tree many times builds them once.
 template <class T>
 inline void aba(const Tree &tr, const T *q, const T *qd, const T *tau, const T (*fext)[6], T gz, T *qdd,
-                T (*vel_out)[6] = nullptr) {
+                T (*vel_out)[6] = nullptr, const Mat6<T> *Ibody = nullptr) {
   const int n = tr.n;
   Mat6<T> X[MAXJ], IA[MAXJ];
   T v[MAXJ][6], c[MAXJ][6], pA[MAXJ][6], S[MAXJ][6], U[MAXJ][6], D[MAXJ], u[MAXJ], a[MAXJ][6];
@@ -199,7 +201,7 @@ inline void aba(const Tree &tr, const T *q, const T *qd, const T *tau, const T (
       for (int k = 0; k < 6; ++k) v[i][k] = xv[k] + vJ[k];
       crm(v[i], vJ, c[i]);
     }
-    IA[i] = body_inertia<T>(tr, i);
+    IA[i] = Ibody ? Ibody[i] : body_inertia<T>(tr, i);
     T Iv[6], vIv[6];
     mat6_vec(IA[i], v[i], Iv);
     crf(v[i], Iv, vIv);
