@@ -22,7 +22,10 @@ SOURCES = {
     "api.hip": [],
     "sampler.hip": ["-ffp-contract=off"],
     "select_refit.hip": ["-ffp-contract=off"],
-    "rollout.hip": [],
+    # no sinking of common code out of branches: merging the two in-register
+    # accumulations of the articulated-body pass into one store through a
+    # selected pointer would move those values to scratch memory
+    "rollout.hip": ["-mllvm", "-simplifycfg-sink-common=false"],
     "mlp.hip": [],
 }
 

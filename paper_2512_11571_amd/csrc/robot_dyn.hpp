@@ -21,18 +21,6 @@ __device__ __forceinline__ float dot6(SV x, SV y) { return dot(x.a, y.a) + dot(x
 __device__ __forceinline__ SV crm(SV v, SV m) { return sv(cross(v.a, m.a), cross(v.a, m.b) + cross(v.b, m.a)); }
 __device__ __forceinline__ SV crf(SV v, SV f) { return sv(cross(v.a, f.a) + cross(v.b, f.b), cross(v.a, f.b)); }
 
-// Parent -> child transform: E (rotation parent->child coords) and r (child
-// origin in parent coords).  X m = [E w; E (v - r x w)];  X^T f = [E^T n + r x E^T f; E^T f].
-struct Xf {
-  M3f E;
-  V3f r;
-};
-__device__ __forceinline__ SV x_motion(const Xf &X, SV m) { return sv(mul(X.E, m.a), mul(X.E, m.b - cross(X.r, m.a))); }
-__device__ __forceinline__ SV x_force_T(const Xf &X, SV f) {
-  const V3f n = mulT(X.E, f.a), ff = mulT(X.E, f.b);
-  return sv(n + cross(X.r, ff), ff);
-}
-
 // Symmetric 6x6 [A B; B^T C], A and C symmetric (xx xy xz yy yz zz), B row-major.
 struct Sym6 {
   float A[6], B[9], C[6];
@@ -53,15 +41,19 @@ __device__ __forceinline__ SV sym_mul(const Sym6 &I, SV m) {
   return sv(symv(I.A, m.a) + matv(I.B, m.b), matTv(I.B, m.a) + symv(I.C, m.b));
 }
 // column k (0..5) of I: k < 3 -> [A e_k; B^T e_k] (B^T e_k = row k of B);
-// k >= 3 -> [B e_j; C e_j] (B e_j = column j of B), j = k - 3
+// k >= 3 -> [B e_j; C e_j] (B e_j = column j of B), j = k - 3.  k is the same
+// for the whole wave; each case reads fixed elements, so I stays in registers.
 __device__ __forceinline__ SV sym_col(const Sym6 &I, int k) {
-  if (k < 3) {
-    const int c0 = k == 0 ? 0 : (k == 1 ? 1 : 2), c1 = k == 0 ? 1 : (k == 1 ? 3 : 4), c2 = k == 0 ? 2 : (k == 1 ? 4 : 5);
-    return sv(v3(I.A[c0], I.A[c1], I.A[c2]), v3(I.B[3 * k], I.B[3 * k + 1], I.B[3 * k + 2]));
+  SV o;
+  switch (k) {
+    case 0: o = sv(v3(I.A[0], I.A[1], I.A[2]), v3(I.B[0], I.B[1], I.B[2])); break;
+    case 1: o = sv(v3(I.A[1], I.A[3], I.A[4]), v3(I.B[3], I.B[4], I.B[5])); break;
+    case 2: o = sv(v3(I.A[2], I.A[4], I.A[5]), v3(I.B[6], I.B[7], I.B[8])); break;
+    case 3: o = sv(v3(I.B[0], I.B[3], I.B[6]), v3(I.C[0], I.C[1], I.C[2])); break;
+    case 4: o = sv(v3(I.B[1], I.B[4], I.B[7]), v3(I.C[1], I.C[3], I.C[4])); break;
+    default: o = sv(v3(I.B[2], I.B[5], I.B[8]), v3(I.C[2], I.C[4], I.C[5])); break;
   }
-  const int j = k - 3;
-  const int c0 = j == 0 ? 0 : (j == 1 ? 1 : 2), c1 = j == 0 ? 1 : (j == 1 ? 3 : 4), c2 = j == 0 ? 2 : (j == 1 ? 4 : 5);
-  return sv(v3(I.B[j], I.B[3 + j], I.B[6 + j]), v3(I.C[c0], I.C[c1], I.C[c2]));
+  return o;
 }
 __device__ __forceinline__ void sym_add(Sym6 &I, const Sym6 &J) {
 #pragma unroll
@@ -83,29 +75,10 @@ __device__ __forceinline__ void sym_rank1(Sym6 &I, SV U, float dinv) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) I.B[3 * r + c] -= u[r] * u[3 + c] * dinv;
 }
-// S' = E^T S E for symmetric S (3x3) -- rotation of a block into the parent frame
-__device__ __forceinline__ void rot_sym(const M3f &E, const float *S, float *O) {
-  // columns of E are E e_k; O = E^T S E, O_ij = (E e_i)^T S (E e_j)
-  const V3f e0 = v3(E.r0.x, E.r1.x, E.r2.x), e1 = v3(E.r0.y, E.r1.y, E.r2.y), e2 = v3(E.r0.z, E.r1.z, E.r2.z);
-  const V3f s0 = symv(S, e0), s1 = symv(S, e1), s2 = symv(S, e2);
-  O[0] = dot(e0, s0); O[1] = dot(e0, s1); O[2] = dot(e0, s2);
-  O[3] = dot(e1, s1); O[4] = dot(e1, s2); O[5] = dot(e2, s2);
-}
-__device__ __forceinline__ void rot_gen(const M3f &E, const float *B, float *O) {
-  const V3f e0 = v3(E.r0.x, E.r1.x, E.r2.x), e1 = v3(E.r0.y, E.r1.y, E.r2.y), e2 = v3(E.r0.z, E.r1.z, E.r2.z);
-  const V3f b0 = matv(B, e0), b1 = matv(B, e1), b2 = matv(B, e2);
-  O[0] = dot(e0, b0); O[1] = dot(e0, b1); O[2] = dot(e0, b2);
-  O[3] = dot(e1, b0); O[4] = dot(e1, b1); O[5] = dot(e1, b2);
-  O[6] = dot(e2, b0); O[7] = dot(e2, b1); O[8] = dot(e2, b2);
-}
-// X^T I X: rotate the blocks (A' = E^T A E, B' = E^T B E, C' = E^T C E), then shift by r:
-// A'' = A' + rx B'^T - B' rx - rx C' rx,  B'' = B' + rx C',  C'' = C'
-__device__ __forceinline__ Sym6 congruence(const Xf &X, const Sym6 &I) {
-  Sym6 R;
-  rot_sym(X.E, I.A, R.A);
-  rot_gen(X.E, I.B, R.B);
-  rot_sym(X.E, I.C, R.C);
-  const V3f r = X.r;
+// The translation part of X^T I X for a child -> parent transform X = (R, r)
+// once the blocks are turned (A' = R A R^T, B' = R B R^T, C' = R C R^T):
+// A'' = A' + rx B'^T - B' rx - rx C' rx,  B'' = B' + rx C',  C'' = C'.
+__device__ __forceinline__ Sym6 shift_inertia(const Sym6 &R, V3f r) {
   // rx C' (3x3): row i = r x (column of C')... compute M = rx C' explicitly
   const float *C = R.C;
   const float Cf[9] = {C[0], C[1], C[2], C[1], C[3], C[4], C[2], C[4], C[5]};
@@ -166,50 +139,6 @@ __device__ __forceinline__ Sym6 body_inertia(CScene &sc, int j) {
   return I;
 }
 
-__device__ __forceinline__ V3f unit_axis(int a) {
-  const float s = a < 3 ? 1.0f : -1.0f;
-  const int k = a % 3;
-  return v3(k == 0 ? s : 0.0f, k == 1 ? s : 0.0f, k == 2 ? s : 0.0f);
-}
-
-// Joint j at coordinate q (with s = sin q, c = cos q for a revolute joint):
-// rotation R (child -> parent) and child origin r (parent coords).
-__device__ __forceinline__ void joint_tf_sc(CScene &sc, int j, float q, float s, float c, M3f &R, V3f &r) {
-  const V3f o = v3(sc.j_origin[j][0], sc.j_origin[j][1], sc.j_origin[j][2]);
-  const V3f a = unit_axis(sc.j_axis[j]);
-  if (sc.j_type[j] == 0) {
-    const float t = 1.0f - c;
-    R.r0 = v3(c + a.x * a.x * t, a.x * a.y * t - a.z * s, a.x * a.z * t + a.y * s);
-    R.r1 = v3(a.y * a.x * t + a.z * s, c + a.y * a.y * t, a.y * a.z * t - a.x * s);
-    R.r2 = v3(a.z * a.x * t - a.y * s, a.z * a.y * t + a.x * s, c + a.z * a.z * t);
-    r = o;
-  } else {
-    R.r0 = v3(1.0f, 0.0f, 0.0f);
-    R.r1 = v3(0.0f, 1.0f, 0.0f);
-    R.r2 = v3(0.0f, 0.0f, 1.0f);
-    r = o + q * a;
-  }
-}
-__device__ __forceinline__ void joint_tf(CScene &sc, int j, float q, M3f &R, V3f &r) {
-  float s = 0.0f, c = 1.0f;
-  if (sc.j_type[j] == 0) sincos_rad(q, &s, &c);
-  joint_tf_sc(sc, j, q, s, c, R, r);
-}
-__device__ __forceinline__ M3f transpose3(const M3f &R) {
-  M3f T;
-  T.r0 = v3(R.r0.x, R.r1.x, R.r2.x);
-  T.r1 = v3(R.r0.y, R.r1.y, R.r2.y);
-  T.r2 = v3(R.r0.z, R.r1.z, R.r2.z);
-  return T;
-}
-__device__ __forceinline__ M3f matmul3(const M3f &A, const M3f &B) {
-  const M3f Bt = transpose3(B);
-  M3f C;
-  C.r0 = v3(dot(A.r0, Bt.r0), dot(A.r0, Bt.r1), dot(A.r0, Bt.r2));
-  C.r1 = v3(dot(A.r1, Bt.r0), dot(A.r1, Bt.r1), dot(A.r1, Bt.r2));
-  C.r2 = v3(dot(A.r2, Bt.r0), dot(A.r2, Bt.r1), dot(A.r2, Bt.r2));
-  return C;
-}
 __device__ __forceinline__ int parent_of(int j) { return j <= PALM ? j - 1 : PALM; }
 // motion subspace: index of the nonzero entry (0..5) and its sign
 __device__ __forceinline__ int s_index(CScene &sc, int j) { return (sc.j_type[j] == 0 ? 0 : 3) + sc.j_axis[j] % 3; }
@@ -226,6 +155,138 @@ __device__ __forceinline__ float s_comp(CScene &sc, int j, SV x) {
   return s_sign(sc, j) * c;
 }
 
+// ---- joints about / along a principal axis ----
+// Joint j at q rotates about (revolute) or slides along (prismatic) the
+// principal axis e_k, k = j_axis % 3, with sign sg = +-1.  Its rotation R
+// (child -> parent) turns by sg q about e_k: with (I, J) = (k+1, k+2) mod 3,
+// R e_I = c e_I + s e_J, R e_J = -s e_I + c e_J, R e_k = e_k, where c = cos q
+// and s = sg sin q (c = 1, s = 0 for a prismatic joint).  r is the child
+// origin in parent coordinates.  Every product with R then touches two
+// components only; the axis is the same for the whole wave, so the
+// specialised code is chosen by a uniform branch.
+struct JT {
+  int k;
+  float c, s;
+  V3f r;
+};
+__device__ __forceinline__ JT joint_of(CScene &sc, int j, float q) {
+  JT J;
+  const int ax = sc.j_axis[j];
+  J.k = ax % 3;
+  const float sg = ax < 3 ? 1.0f : -1.0f;
+  V3f r = v3(sc.j_origin[j][0], sc.j_origin[j][1], sc.j_origin[j][2]);
+  if (sc.j_type[j] == 0) {
+    float sn, cs;
+    sincos_rad(q, &sn, &cs);
+    J.c = cs;
+    J.s = sg * sn;
+  } else {
+    J.c = 1.0f;
+    J.s = 0.0f;
+    const float d = sg * q;
+    if (J.k == 0) r.x += d;
+    else if (J.k == 1) r.y += d;
+    else r.z += d;
+  }
+  J.r = r;
+  return J;
+}
+template <int M> __device__ __forceinline__ float cget(const V3f &v) { return M == 0 ? v.x : (M == 1 ? v.y : v.z); }
+template <int M> __device__ __forceinline__ void cset(V3f &v, float x) {
+  if (M == 0) v.x = x;
+  else if (M == 1) v.y = x;
+  else v.z = x;
+}
+// R v for the rotation about e_K by (c, s)
+template <int K> __device__ __forceinline__ V3f rot_k(float c, float s, V3f v) {
+  constexpr int I = (K + 1) % 3, J = (K + 2) % 3;
+  V3f o;
+  cset<I>(o, c * cget<I>(v) - s * cget<J>(v));
+  cset<J>(o, s * cget<I>(v) + c * cget<J>(v));
+  cset<K>(o, cget<K>(v));
+  return o;
+}
+// index of (m, n) in the packed symmetric 3x3 (xx xy xz yy yz zz)
+__host__ __device__ constexpr int sidx(int m, int n) {
+  return m <= n ? (m == 0 ? n : (m == 1 ? 2 + n : 5)) : (n == 0 ? m : (n == 1 ? 2 + m : 5));
+}
+// child -> parent motion transform: X m = [E w; E (v - r x w)] with E = R^T
+template <int K> __device__ __forceinline__ SV x_motion_k(const JT &J, SV m) {
+  return sv(rot_k<K>(J.c, -J.s, m.a), rot_k<K>(J.c, -J.s, m.b - cross(J.r, m.a)));
+}
+// X^T f = [R n + r x R f; R f]
+template <int K> __device__ __forceinline__ SV x_force_T_k(const JT &J, SV f) {
+  const V3f ff = rot_k<K>(J.c, J.s, f.b);
+  return sv(rot_k<K>(J.c, J.s, f.a) + cross(J.r, ff), ff);
+}
+// Rp R (a world rotation times the joint rotation): columns I and J mix
+template <int K> __device__ __forceinline__ V3f row_rot_k(V3f p, float c, float s) {
+  constexpr int I = (K + 1) % 3, J = (K + 2) % 3;
+  V3f o;
+  cset<I>(o, c * cget<I>(p) + s * cget<J>(p));
+  cset<J>(o, c * cget<J>(p) - s * cget<I>(p));
+  cset<K>(o, cget<K>(p));
+  return o;
+}
+template <int K> __device__ __forceinline__ M3f rot_right_k(const M3f &P, float c, float s) {
+  M3f O;
+  O.r0 = row_rot_k<K>(P.r0, c, s);
+  O.r1 = row_rot_k<K>(P.r1, c, s);
+  O.r2 = row_rot_k<K>(P.r2, c, s);
+  return O;
+}
+// X^T I X: the blocks turned by R (R S R^T: only the I, J rows and columns
+// mix), then the shift by r
+// R S R^T for a packed symmetric block S (only the I, J rows and columns mix)
+template <int K>
+__device__ __forceinline__ void rot_sym_k(float c, float s, float cc, float ss, float cs, const float (&X)[6],
+                                          float (&O)[6]) {
+  constexpr int I = (K + 1) % 3, J = (K + 2) % 3;
+  constexpr int II = sidx(I, I), JJ = sidx(J, J), IJ = sidx(I, J), IK = sidx(I, K), JK = sidx(J, K), KK = sidx(K, K);
+  const float sii = X[II], sjj = X[JJ], sij = X[IJ], sik = X[IK], sjk = X[JK];
+  O[II] = cc * sii - 2.0f * cs * sij + ss * sjj;
+  O[JJ] = ss * sii + 2.0f * cs * sij + cc * sjj;
+  O[IJ] = cs * (sii - sjj) + (cc - ss) * sij;
+  O[IK] = c * sik - s * sjk;
+  O[JK] = s * sik + c * sjk;
+  O[KK] = X[KK];
+}
+template <int K> __device__ __forceinline__ Sym6 congruence_k(const JT &Jt, const Sym6 &S) {
+  constexpr int I = (K + 1) % 3, J = (K + 2) % 3;
+  const float c = Jt.c, s = Jt.s, cc = c * c, ss = s * s, cs = c * s;
+  Sym6 R;
+  rot_sym_k<K>(c, s, cc, ss, cs, S.A, R.A);
+  rot_sym_k<K>(c, s, cc, ss, cs, S.C, R.C);
+  // general block: P = R B (rows I, J mix), then P R^T (columns I, J mix)
+  float P[9];
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    P[3 * I + n] = c * S.B[3 * I + n] - s * S.B[3 * J + n];
+    P[3 * J + n] = s * S.B[3 * I + n] + c * S.B[3 * J + n];
+    P[3 * K + n] = S.B[3 * K + n];
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    R.B[3 * m + I] = c * P[3 * m + I] - s * P[3 * m + J];
+    R.B[3 * m + J] = s * P[3 * m + I] + c * P[3 * m + J];
+    R.B[3 * m + K] = P[3 * m + K];
+  }
+  return shift_inertia(R, Jt.r);
+}
+#define CEM_AXIS_CASES(k, CALL)          \
+  switch (k) {                           \
+    case 0: { constexpr int K = 0; CALL; } \
+    case 1: { constexpr int K = 1; CALL; } \
+    default: { constexpr int K = 2; CALL; } \
+  }
+__device__ __forceinline__ SV x_motion(const JT &J, SV m) { CEM_AXIS_CASES(J.k, return x_motion_k<K>(J, m)) }
+__device__ __forceinline__ SV x_force_T(const JT &J, SV f) { CEM_AXIS_CASES(J.k, return x_force_T_k<K>(J, f)) }
+__device__ __forceinline__ M3f rot_right(const M3f &P, const JT &J) { CEM_AXIS_CASES(J.k, return rot_right_k<K>(P, J.c, J.s)) }
+template <int K> struct AxisK {
+  static constexpr int value = K;
+};
+__device__ __forceinline__ V3f col(const M3f &R, int k);
+
 // World poses of bodies 0..PALM (chain) for the arm kinematics.
 __device__ __forceinline__ void chain_fk(CScene &sc, const float *q, M3f *Rw, V3f *pw) {
   M3f Rp;
@@ -233,11 +294,9 @@ __device__ __forceinline__ void chain_fk(CScene &sc, const float *q, M3f *Rw, V3
   V3f pp = v3(0.0f, 0.0f, 0.0f);
 #pragma unroll
   for (int j = 0; j <= PALM; ++j) {
-    M3f R;
-    V3f r;
-    joint_tf(sc, j, q[j], R, r);
-    pp = pp + mul(Rp, r);
-    Rp = matmul3(Rp, R);
+    const JT J = joint_of(sc, j, q[j]);
+    pp = pp + mul(Rp, J.r);
+    Rp = rot_right(Rp, J);
     Rw[j] = Rp;
     pw[j] = pp;
   }
@@ -266,7 +325,9 @@ __device__ __forceinline__ void ik_dls(CScene &sc, float *q, V3f pt, const M3f &
 #pragma unroll
     for (int c = 0; c < NARM; ++c) {
       const int j = ARM0 + c;
-      const V3f z = mul(Rw[j], unit_axis(sc.j_axis[j]));
+      const int ax = sc.j_axis[j], k = ax % 3;
+      const float sg = ax < 3 ? 1.0f : -1.0f;
+      const V3f z = mul(Rw[j], v3(k == 0 ? sg : 0.0f, k == 1 ? sg : 0.0f, k == 2 ? sg : 0.0f));
       const V3f jv = cross(z, pe - pw[j]);
       J[0][c] = jv.x; J[1][c] = jv.y; J[2][c] = jv.z;
       J[3][c] = z.x; J[4][c] = z.y; J[5][c] = z.z;

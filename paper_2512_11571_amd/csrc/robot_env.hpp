@@ -69,15 +69,6 @@ struct Lds {
   }
 };
 
-__device__ __forceinline__ Xf joint_X(CScene &sc, int j, float q) {
-  M3f Rj;
-  V3f rj;
-  joint_tf(sc, j, q, Rj, rj);
-  Xf X;
-  X.E = transpose3(Rj);
-  X.r = rj;
-  return X;
-}
 // Bias acceleration c_j from its stored components (see the row layout).
 __device__ __forceinline__ SV c_at(const Lds &L, int j) {
   const V3f z = v3(0.0f, 0.0f, 0.0f);
@@ -431,17 +422,12 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
       for (int j = 0; j < NJ; ++j) {
         const bool finger = j >= FL;
         const float qj = L.at(R_Q + j);
-        M3f Rj;
-        V3f rj;
-        joint_tf(sc, j, qj, Rj, rj);
-        Xf X;
-        X.E = transpose3(Rj);
-        X.r = rj;
+        const JT X = joint_of(sc, j, qj);
         const M3f Rp = finger ? Rw8 : Rw;
         const V3f pp = finger ? pw8 : pw;
         const SV vp = finger ? v8 : vprev;
-        const M3f Rb = matmul3(Rp, Rj);
-        const V3f pb = pp + mul(Rp, rj);
+        const M3f Rb = rot_right(Rp, X);
+        const V3f pb = pp + mul(Rp, X.r);
         const SV vJ = s_vec(sc, j, L.at(R_QD + j));
         const SV vb = (j == 0 ? sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)) : x_motion(X, vp)) + vJ;
         c_put(L, j, crm(vb, vJ));
@@ -544,15 +530,22 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
           sym_rank1(IA, Uj, di);
           SV pa = pAj + (u * di) * Uj;
           if (j >= 2) pa = pa + sym_mul(IA, c_at(L, j));
-          const Xf X = joint_X(sc, j, qj);
-          const Sym6 Ip = congruence(X, IA);
+          const JT X = joint_of(sc, j, qj);
           const int p = parent_of(j);
-          L.sv_put(R_P + 6 * p, L.sv_at(R_P + 6 * p) + x_force_T(X, pa));
-          if (p == PALM) sym_add(IA8, Ip);
-          else {
-            IAc = inertia_of(sk, p);
-            sym_add(IAc, Ip);
-          }
+          // fold body j into its parent, with the transform specialised to the joint's axis
+          auto fold = [&](auto axis) {
+            constexpr int K = decltype(axis)::value;
+            const Sym6 Ip = congruence_k<K>(X, IA);
+            L.sv_put(R_P + 6 * p, L.sv_at(R_P + 6 * p) + x_force_T_k<K>(X, pa));
+            if (p == PALM) sym_add(IA8, Ip);
+            else {
+              IAc = inertia_of(sk, p);
+              sym_add(IAc, Ip);
+            }
+          };
+          if (X.k == 0) fold(AxisK<0>());
+          else if (X.k == 1) fold(AxisK<1>());
+          else fold(AxisK<2>());
         }
       }
 
@@ -561,7 +554,7 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
       SV a8 = a_prev;
       for (int j = 0; j < NJ; ++j) {
         const float qj = L.at(R_Q + j);
-        const Xf X = joint_X(sc, j, qj);
+        const JT X = joint_of(sc, j, qj);
         const SV ap = x_motion(X, j >= FL ? a8 : a_prev) + c_at(L, j);
         const float qdd = L.at(R_UD + j) - dot6(L.sv_at(R_P + 6 * j), ap);
         const SV aj = ap + s_vec(sc, j, qdd);
