@@ -134,6 +134,104 @@ def bench_batch(a):
     print(json.dumps(out))
 
 
+def _first_reach(curve, target):
+    """First iteration count k (1-based) whose value is within the target band, else None."""
+    for k, v in enumerate(curve, 1):
+        if v <= target:
+            return k
+    return None
+
+
+def bench_surrogate(a):
+    """Surrogate screening against plain CE on the pick-and-place plan: wall time
+    to reach plain CE's final plan cost.  Dataset recording and training are
+    timed and reported on their own (amortised over every later solve)."""
+    import numpy as np
+    import torch
+    from paper_2512_11571_amd import workloads
+    from paper_2512_11571_amd.binding import Batch, Context, Mlp
+
+    spec = workloads.load("surrogate")["surrogate"]
+    base = workloads.load(spec["workload"])
+    ev, tr = spec["eval"], spec["train"]
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)
+
+    insts = workloads.surrogate_dataset_instances(spec)
+    cap = sum(i["workload"]["cem"]["pop"] * i["iters"] for i in insts)
+    X = torch.empty((cap, 16), dtype=torch.float32, device=dev)
+    Y = torch.empty((cap, 8), dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    with Batch(insts) as bt:
+        n = bt.record(spec["dataset"]["iters"], X, Y)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    env_steps_data = sum(i["workload"]["cem"]["pop"] * i["iters"] * i["workload"]["scene"]["horizon"] for i in insts)
+    log("dataset: %d rows in %.1f s" % (n, t_data))
+
+    def solve(seed, screened, m):
+        cem = dict(base["cem"], n_elite=ev["n_elite"], pop=ev["screen_pop"] if screened else ev["n_sim"])
+        w = dict(base, cem=cem)
+        with Context(w, seed=seed) as c:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = m.plan_solve_screened(c, ev["iters"], ev["n_sim"]) if screened else c.plan_solve(ev["iters"])
+            return r, time.perf_counter() - t
+
+    with Mlp(seed=tr["seed"], max_rows=ev["screen_pop"]) as m:
+        t0 = time.perf_counter()
+        m.fit_norm(X, Y, n)
+        losses = m.train(X, Y, n, tr["batch"], tr["epochs"], tr["lr"], seed=tr["seed"])
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        log("training: %d epochs in %.1f s, loss %.4f -> %.4f" % (tr["epochs"], t_train, losses[0], losses[-1]))
+        del X, Y
+        solve(ev["seeds"][0], False, m)          # warm-up of both paths (graph capture, code load)
+        solve(ev["seeds"][0], True, m)
+        curves = {False: [], True: []}
+        times = {False: [], True: []}
+        err = []
+        for seed in ev["seeds"]:
+            for screened in (False, True):
+                r, t = solve(seed, screened, m)
+                curves[screened].append(r["stats"][:, 7])
+                times[screened].append(t)
+                if screened:
+                    err.append(r["surrogate_err"])
+            log("seed %d: plain %.3f, screened %.3f" % (seed, curves[False][-1][-1], curves[True][-1][-1]))
+
+    med = {k: np.median(np.stack(v), axis=0) for k, v in curves.items()}
+    target = float(med[False][-1])
+    band = target * (1.0 + ev["target_tol"])
+    t_iter = {k: float(np.mean(v)) / ev["iters"] for k, v in times.items()}
+    k_plain, k_scr = _first_reach(med[False], band), _first_reach(med[True], band)
+    t_plain = k_plain * t_iter[False]
+    t_scr = k_scr * t_iter[True] if k_scr else None
+    out = {
+        "metric": "wall time to plain CE's final plan cost, screened / plain",
+        "value": (t_scr / t_plain) if t_scr else None,
+        "unit": "x", "n_gpus": 1, "steps": ev["iters"], "warmup": 1,
+        "ms_per_step": t_iter[True] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 rollouts, bf16 MFMA surrogate (f32 accumulate)",
+        "data": "synthetic (seeded pick-and-place instances and Philox samples)",
+        "config": {"workload": "surrogate (pick-and-place)", "n_sim": ev["n_sim"], "screen_pop": ev["screen_pop"],
+                   "n_elite": ev["n_elite"], "iters": ev["iters"], "seeds": ev["seeds"],
+                   "dataset_rows": n, "dataset_env_steps": env_steps_data},
+        "target_cost": target, "target_band": band,
+        "median_best_cost_per_iter": {"plain": [float(x) for x in med[False]],
+                                      "screened": [float(x) for x in med[True]]},
+        "iters_to_target": {"plain": k_plain, "screened": k_scr},
+        "seconds_per_iter": t_iter,
+        "seconds_to_target": {"plain": t_plain, "screened": t_scr},
+        "surrogate_cost_error_mean_per_iter": [float(x) for x in np.mean(np.stack(err), axis=0)],
+        "dataset_seconds": t_data, "train_seconds": t_train,
+        "train_loss_first_last": [float(losses[0]), float(losses[-1])],
+    }
+    print(json.dumps({k: (v if not isinstance(v, dict) or k != "seconds_per_iter" else
+                          {("screened" if kk else "plain"): vv for kk, vv in v.items()}) for k, v in out.items()}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +261,9 @@ def main():
         return
     if a.workload == "batch":
         bench_batch(a)
+        return
+    if a.workload == "surrogate":
+        bench_surrogate(a)
         return
 
     import torch

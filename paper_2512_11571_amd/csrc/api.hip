@@ -1,6 +1,7 @@
 // The C ABI (include/cemtamp.h): context management, argument validation,
 // launches and the replayed CE iteration.  Host code only; every step of the
 // method runs in the kernels of the other translation units.
+#include <atomic>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -223,6 +224,8 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
   c->cov_mode = p->cov_mode;
   c->seed = p->seed;
   c->inst = p->instance;
+  static std::atomic<uint64_t> next_serial{1};
+  c->serial = next_serial.fetch_add(1);
   int rc = CEM_OK;
   do {
     if (hipGetDevice(&c->device) != hipSuccess) { rc = fail(c, CEM_E_HIP, "hipGetDevice"); break; }

@@ -100,5 +100,6 @@ struct cem_ctx {
   uint8_t *tier = nullptr;
   hipStream_t own = nullptr;
   hipGraphExec_t iter_graph = nullptr;
+  uint64_t serial = 0;  // unique per context in the process (host addresses are reused after cem_free)
   std::string err;
 };

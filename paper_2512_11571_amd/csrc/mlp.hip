@@ -431,7 +431,7 @@ struct cem_mlp {
   int step = 0;
   hipStream_t own = nullptr;
   hipGraphExec_t screen_graph = nullptr;
-  cem_ctx *graph_ctx = nullptr;
+  uint64_t graph_serial = 0;  // the context the screened-iteration graph was captured for
   int graph_nsim = 0;
   std::string err_text;
 };
@@ -781,7 +781,9 @@ int plan_solve_screened(cem_ctx *c, cem_mlp *m, int32_t iters, int32_t n_sim, ce
   MHIPCHK(m, hipMemcpyAsync(&it0, &c->st->iter, sizeof it0, hipMemcpyDeviceToHost, s));
   MHIPCHK(m, hipStreamSynchronize(s));
   if (it0 + iters > MAX_STATS_ITERS) return mfail(m, CEM_E_ARG, "iteration counter would exceed 4096");
-  if (!m->screen_graph || m->graph_ctx != c || m->graph_nsim != n_sim) {
+  // the graph holds the context's device buffers: reuse it only for that same
+  // context (its serial, not its address, which a later context can reuse)
+  if (!m->screen_graph || m->graph_serial != c->serial || m->graph_nsim != n_sim) {
     if (m->screen_graph) (void)hipGraphExecDestroy(m->screen_graph);
     m->screen_graph = nullptr;
     hipGraph_t g = nullptr;
@@ -806,7 +808,7 @@ int plan_solve_screened(cem_ctx *c, cem_mlp *m, int32_t iters, int32_t n_sim, ce
       m->screen_graph = nullptr;
       return mfail(m, CEM_E_HIP, "hipGraphInstantiate");
     }
-    m->graph_ctx = c;
+    m->graph_serial = c->serial;
     m->graph_nsim = n_sim;
   }
   for (int j = 0; j < iters; ++j) MHIPCHK(m, hipGraphLaunch(m->screen_graph, s));

@@ -56,3 +56,21 @@ def batch_instances(spec=None, seed=None):
         out.append({"workload": w, "seed": int(spec["seed"] if seed is None else seed), "instance": b,
                     "iters": int(spec["iters"][kind])})
     return out
+
+
+def surrogate_dataset_instances(spec=None):
+    """Task instances whose plain-CE runs make the surrogate's training data:
+    the base workload with the dataset's population and elites, one seed per
+    instance from seed_base on (disjoint from the evaluation seeds)."""
+    import copy
+
+    spec = spec or load("surrogate")["surrogate"]
+    d = spec["dataset"]
+    base = load(spec["workload"])
+    out = []
+    for b in range(d["n_instances"]):
+        w = copy.deepcopy(base)
+        w["cem"]["pop"] = d["pop"]
+        w["cem"]["n_elite"] = d["n_elite"]
+        out.append({"workload": w, "seed": int(d["seed_base"] + b), "instance": b, "iters": int(d["iters"])})
+    return out

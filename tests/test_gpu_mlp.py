@@ -162,3 +162,62 @@ def test_recorded_dataset_is_the_simulated_outcome(oracle, B):
     s = np.where(pose[:, 3:4] < 0, -1.0, 1.0).astype(np.float32)
     assert np.array_equal(Y[:64, 1:4], pose[:, :3]) and np.array_equal(Y[:64, 4:8], s * pose[:, 3:7])
     assert np.all(np.isfinite(Y))
+
+
+def _screening_setup(B, pp, m, rng):
+    norm = np.concatenate([np.asarray(pp["cem"]["mu0"]), np.sqrt(pp["cem"]["cov0_diag"]),
+                           [5.0, 2.0, 0.0, 0.4, 0.5, 0, 0, 0], [2.0, 1.0, 0.5, 0.1, 0.5, 0.5, 0.5, 0.5]])
+    m.set_norm(norm.astype(np.float32))
+    m.set_params(m.get_params() + rng.normal(size=m.n_params).astype(np.float32) * 0.05)
+
+
+def _short_pickplace(pop, n_elite):
+    pp = workloads.load("pickplace")
+    return dict(pp, scene=dict(pp["scene"], horizon=400), cem=dict(pp["cem"], pop=pop, n_elite=n_elite))
+
+
+def test_plan_solve_screened_equals_eager_steps(B):
+    # the captured screened iteration = screen, simulate the kept candidates, refit
+    w = _short_pickplace(2048, 32)
+    n_sim, iters = 256, 2
+    with B.Mlp(seed=3, max_rows=2048) as m:
+        _screening_setup(B, w, m, np.random.default_rng(9))
+        with B.Context(w, seed=4) as c:
+            r = m.plan_solve_screened(c, iters, n_sim)
+            mu_g, S_g = c.get_theta()
+        with B.Context(w, seed=4) as c2:
+            Zs = torch.empty((n_sim, 16), dtype=torch.float32, device="cuda:0")
+            Ps = torch.empty((n_sim, 8), dtype=torch.float32, device="cuda:0")
+            cost = torch.empty(n_sim, dtype=torch.float32, device="cuda:0")
+            tier = torch.empty(n_sim, dtype=torch.uint8, device="cuda:0")
+            for it in range(iters):
+                m.screen(c2, it, n_sim, Zs, Ps)
+                c2.rollout_batch(Zs, cost, tier, None)
+                c2.cem_refit(Zs, cost, tier, None, None)
+            torch.cuda.synchronize()
+            mu_e, S_e = c2.get_theta()
+    assert np.array_equal(mu_g, mu_e) and np.array_equal(S_g, S_e)
+    assert r["iters_done"] == iters and np.isfinite(r["best_cost"])
+    assert np.all(np.isfinite(r["surrogate_err"]))
+
+
+def test_screened_solves_on_successive_contexts(B):
+    # contexts created and freed one after another (a freed context's host
+    # address is reused by the next): each solve uses its own context's buffers
+    w = _short_pickplace(2048, 32)
+    n_sim = 256
+    outs = []
+    with B.Mlp(seed=3, max_rows=2048) as m:
+        _screening_setup(B, w, m, np.random.default_rng(9))
+        P, nrm = m.get_params(), m.get_norm()
+        for seed in (5, 6, 5):
+            with B.Context(w, seed=seed) as c:
+                outs.append(m.plan_solve_screened(c, 1, n_sim))
+    with B.Mlp(seed=3, max_rows=2048) as m2:
+        m2.set_params(P)
+        m2.set_norm(nrm)
+        with B.Context(w, seed=6) as c:
+            fresh = m2.plan_solve_screened(c, 1, n_sim)
+    same = lambda a, b: a["best_cost"] == b["best_cost"] and np.array_equal(a["best_z"], b["best_z"]) and \
+        np.array_equal(a["mu"], b["mu"])
+    assert same(outs[0], outs[2]) and same(outs[1], fresh)
