@@ -270,7 +270,8 @@ int cem_mlp_train_step(cem_mlp *m, const float *X_dev, const float *Y_dev, int32
                        void *stream);
 /* epochs over n rows in shuffled minibatches of `batch` (an affine
  * permutation per epoch, from seed); mean minibatch loss per epoch to
- * epoch_loss_host (nullable).  Synchronous. */
+ * epoch_loss_host (nullable).  Runs on the null stream, after the caller's
+ * earlier work there.  Synchronous. */
 int cem_mlp_train(cem_mlp *m, const float *X_dev, const float *Y_dev, int64_t n, int32_t batch, int32_t epochs,
                   float lr, uint64_t seed, float *epoch_loss_host);
 /* Screening: sample the context's population (iteration iter), predict every

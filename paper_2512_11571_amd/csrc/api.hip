@@ -319,7 +319,7 @@ int cem_refit(cem_ctx *c, const float *Z_dev, const float *cost_dev, const uint8
 int plan_solve(cem_ctx *c, int32_t iters, cem_result *res, float *stats_host, void *stream) {
   if (!c) return CEM_E_ARG;
   if (!res || iters < 0) return fail(c, CEM_E_ARG, "null result or iters < 0");
-  hipStream_t s = stream ? (hipStream_t)stream : c->own;
+  hipStream_t s = (hipStream_t)stream;
   int32_t it0 = 0;
   HIPCHK(c, hipMemcpyAsync(&it0, &c->st->iter, sizeof it0, hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -616,7 +616,7 @@ int cem_batch_autotune(cem_batch *b, int32_t *config_out) {
 
 int cem_batch_step(cem_batch *b, void *stream) {
   if (!b) return CEM_E_ARG;
-  BHIPCHK(b, hipGraphLaunch(b->graph, stream ? (hipStream_t)stream : b->own));
+  BHIPCHK(b, hipGraphLaunch(b->graph, (hipStream_t)stream));
   return CEM_OK;
 }
 
@@ -626,7 +626,7 @@ int cem_batch_record(cem_batch *b, int32_t iters, float *X_dev, float *Y_dev, in
   if (iters < 0 || !X_dev || !Y_dev || !n_out) return bfail(b, CEM_E_ARG, "bad arguments");
   for (cem_ctx *c : b->ctx)
     if (c->D != b->ctx[0]->D) return bfail(b, CEM_E_ARG, "recording needs one parameter dimension");
-  hipStream_t s = stream ? (hipStream_t)stream : b->own;
+  hipStream_t s = (hipStream_t)stream;
   std::vector<int32_t> it(b->ctx.size());
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     BHIPCHK(b, hipMemcpyAsync(&it[i], &b->ctx[i]->st->iter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -655,7 +655,7 @@ int cem_batch_record(cem_batch *b, int32_t iters, float *X_dev, float *Y_dev, in
 int cem_batch_solve(cem_batch *b, int32_t iters, cem_result *results, void *stream) {
   if (!b) return CEM_E_ARG;
   if (iters < 0) return bfail(b, CEM_E_ARG, "iters < 0");
-  hipStream_t s = stream ? (hipStream_t)stream : b->own;
+  hipStream_t s = (hipStream_t)stream;
   for (int j = 0; j < iters; ++j) BHIPCHK(b, hipGraphLaunch(b->graph, s));
   BHIPCHK(b, hipStreamSynchronize(s));
   if (!results) return CEM_OK;

@@ -641,7 +641,7 @@ int cem_mlp_set_norm(cem_mlp *m, const float *host48) {
 
 int cem_mlp_fit_norm(cem_mlp *m, const float *X_dev, const float *Y_dev, int64_t n, void *stream) {
   if (!m || !X_dev || !Y_dev || n < 1) return CEM_E_ARG;
-  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(colstats_kernel, dim3(IN), dim3(256), 0, s, X_dev, (long)n, IN, m->norm, m->norm + IN);
   hipLaunchKernelGGL(colstats_kernel, dim3(OUT), dim3(256), 0, s, Y_dev, (long)n, OUT, m->norm + 2 * IN,
                      m->norm + 2 * IN + OUT);
@@ -654,7 +654,7 @@ int cem_mlp_forward(cem_mlp *m, const float *X_dev, int32_t n, float *Y_dev, voi
   if (n < 0 || n > m->max_rows) return mfail(m, CEM_E_ARG, "n out of range [0, max_rows]");
   if (n == 0) return CEM_OK;
   if (!X_dev || !Y_dev) return mfail(m, CEM_E_ARG, "null buffer");
-  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  hipStream_t s = (hipStream_t)stream;
   MHIPCHK(m, forward_n(m, X_dev, n, false, s));
   hipLaunchKernelGGL(denorm_out_kernel, dim3(blocks((long)n * OUT, 256)), dim3(256), 0, s, m->Yn, n,
                      m->norm + 2 * IN, m->norm + 2 * IN + OUT, Y_dev);
@@ -667,7 +667,7 @@ int cem_mlp_loss_grad(cem_mlp *m, const float *X_dev, const float *Y_dev, int32_
   if (!m) return CEM_E_ARG;
   if (n < 1 || n > m->max_rows) return mfail(m, CEM_E_ARG, "n out of range [1, max_rows]");
   if (!X_dev || !Y_dev) return mfail(m, CEM_E_ARG, "null buffer");
-  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  hipStream_t s = (hipStream_t)stream;
   MHIPCHK(m, loss_grad_n(m, X_dev, Y_dev, n, s));
   if (grad_dev) MHIPCHK(m, hipMemcpyAsync(grad_dev, m->G, sizeof(float) * N_PARAMS, hipMemcpyDeviceToDevice, s));
   if (loss_dev) MHIPCHK(m, hipMemcpyAsync(loss_dev, m->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -678,7 +678,7 @@ int cem_mlp_train_step(cem_mlp *m, const float *X_dev, const float *Y_dev, int32
                        void *stream) {
   int rc = cem_mlp_loss_grad(m, X_dev, Y_dev, n, nullptr, loss_dev, stream);
   if (rc != CEM_OK) return rc;
-  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  hipStream_t s = (hipStream_t)stream;
   m->step += 1;
   const double b1 = 0.9, b2 = 0.999;
   const float c1 = (float)(1.0 - std::pow(b1, m->step)), c2 = (float)(1.0 - std::pow(b2, m->step));
@@ -693,7 +693,7 @@ int cem_mlp_train(cem_mlp *m, const float *X_dev, const float *Y_dev, int64_t n,
   if (!m || !X_dev || !Y_dev) return CEM_E_ARG;
   if (n < 1 || n > (1 << 24) || batch < 1 || batch > m->max_rows || epochs < 0)
     return mfail(m, CEM_E_ARG, "bad sizes");
-  hipStream_t s = m->own;
+  hipStream_t s = nullptr;  // the null stream: ordered after the caller's earlier work on it
   const long steps = (long)(n / batch);
   if (steps < 1) return mfail(m, CEM_E_ARG, "dataset smaller than one batch");
   std::vector<float> losses(steps);
@@ -766,7 +766,7 @@ int cem_screen(cem_ctx *c, cem_mlp *m, int32_t iter, int32_t n_sim, float *Zsim_
   if (c->pop > m->max_rows) return mfail(m, CEM_E_ARG, "population exceeds the network's max_rows");
   if (n_sim < 1 || n_sim > c->pop) return mfail(m, CEM_E_ARG, "n_sim out of range [1, pop]");
   if (!Zsim_dev || iter < 0) return mfail(m, CEM_E_ARG, "null Zsim or iter < 0");
-  return screen_into(c, m, iter, n_sim, Zsim_dev, pred_dev, stream ? (hipStream_t)stream : m->own);
+  return screen_into(c, m, iter, n_sim, Zsim_dev, pred_dev, (hipStream_t)stream);
 }
 
 int plan_solve_screened(cem_ctx *c, cem_mlp *m, int32_t iters, int32_t n_sim, cem_result *res, float *stats_host,
@@ -776,7 +776,7 @@ int plan_solve_screened(cem_ctx *c, cem_mlp *m, int32_t iters, int32_t n_sim, ce
   if (c->pop > m->max_rows) return mfail(m, CEM_E_ARG, "population exceeds the network's max_rows");
   if (n_sim < 1 || n_sim > c->pop || n_sim < c->n_elite) return mfail(m, CEM_E_ARG, "n_sim out of range [n_elite, pop]");
   if (iters < 0) return mfail(m, CEM_E_ARG, "iters < 0");
-  hipStream_t s = stream ? (hipStream_t)stream : m->own;
+  hipStream_t s = (hipStream_t)stream;
   int32_t it0 = 0;
   MHIPCHK(m, hipMemcpyAsync(&it0, &c->st->iter, sizeof it0, hipMemcpyDeviceToHost, s));
   MHIPCHK(m, hipStreamSynchronize(s));
