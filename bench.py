@@ -21,6 +21,8 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks: FP32 vector (packed) 157.3 TFLOP/s, HBM3E 8 TB/s.
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0   # dense BF16 MFMA
+MLP_FLOP_PER_ROW = 2 * (16 * 256 + 256 * 256 + 256 * 256 + 256 * 8)   # one forward pass, multiply-adds x 2
 DEFAULT_WORKLOAD = "pickplace"
 
 # HBM traffic per rollout launch measured with rocprofv3 (FETCH_SIZE + WRITE_SIZE,
@@ -186,6 +188,32 @@ def bench_surrogate(a):
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         log("training: %d epochs in %.1f s, loss %.4f -> %.4f" % (tr["epochs"], t_train, losses[0], losses[-1]))
+        # the network's kernels alone: the screening forward over one population, one training step
+        stream = torch.cuda.current_stream()
+        rows = ev["screen_pop"]
+        Yp = torch.empty((rows, 8), dtype=torch.float32, device=dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        m.forward(X[:rows], Yp, stream)
+        e0.record(stream)
+        for _ in range(20):
+            m.forward(X[:rows], Yp, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fwd_s = e0.elapsed_time(e1) / 20 / 1e3
+        b = tr["batch"]
+        m.train_step(X[:b], Y[:b], 0.0, None, stream)
+        e0.record(stream)
+        for _ in range(20):
+            m.train_step(X[:b], Y[:b], 0.0, None, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        step_s = e0.elapsed_time(e1) / 20 / 1e3
+        mlp = {"forward_rows": rows, "forward_ms": fwd_s * 1e3,
+               "forward_tflops": rows * MLP_FLOP_PER_ROW / fwd_s / 1e12,
+               "forward_frac_of_bf16_peak": rows * MLP_FLOP_PER_ROW / fwd_s / 1e12 / PEAK_BF16_TFLOPS,
+               "train_step_rows": b, "train_step_ms": step_s * 1e3,
+               "train_step_tflops": 3 * b * MLP_FLOP_PER_ROW / step_s / 1e12}
+        log("mlp:", mlp)
         del X, Y
         solve(ev["seeds"][0], False, m)          # warm-up of both paths (graph capture, code load)
         solve(ev["seeds"][0], True, m)
@@ -225,7 +253,7 @@ def bench_surrogate(a):
         "seconds_per_iter": t_iter,
         "seconds_to_target": {"plain": t_plain, "screened": t_scr},
         "surrogate_cost_error_mean_per_iter": [float(x) for x in np.mean(np.stack(err), axis=0)],
-        "dataset_seconds": t_data, "train_seconds": t_train,
+        "dataset_seconds": t_data, "train_seconds": t_train, "mlp": mlp,
         "train_loss_first_last": [float(losses[0]), float(losses[-1])],
     }
     print(json.dumps({k: (v if not isinstance(v, dict) or k != "seconds_per_iter" else

@@ -14,6 +14,8 @@
 // BF16 copy of the weights is refreshed by the Adam kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -77,6 +79,10 @@ struct GemmArgs {
   float *C;           // fp32 out, C[m * ldc + n]
   uint16_t *H;        // bf16 out, H[m * ldc + n]
   int ldc;
+  // split contraction (EPI_STORE only): workgroup z sums k in [z * kc, (z + 1) * kc)
+  // into C + z * c_split (fp32 partial sums, reduced afterwards)
+  int kc;
+  long c_split;
 };
 
 // 64x64 tile of C per workgroup (256 threads = 4 waves, 32x32 each).
@@ -86,22 +92,26 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int kbeg = blockIdx.z * g.kc, kend = min(g.K, kbeg + g.kc);
+  // stage each operand along its contiguous axis, so that neighbouring threads
+  // read neighbouring elements
+  const bool a_kfast = g.a_k == 1, b_nfast = g.b_n == 1;
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
     // stage A (64x16) and B (16x64): 4 elements per thread each, zero outside
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int idx = tid * 4 + e;
-      const int am = idx >> 4, ak = idx & 15;
+      const int am = a_kfast ? idx >> 4 : idx & 63, ak = a_kfast ? idx & 15 : idx >> 6;
       const int m = m0 + am, k = k0 + ak;
-      As[am][ak] = (m < g.M && k < g.K) ? g.A[(long)m * g.a_m + (long)k * g.a_k] : (uint16_t)0;
-      const int bk = idx >> 6, bn = idx & 63;
+      As[am][ak] = (m < g.M && k < kend) ? g.A[(long)m * g.a_m + (long)k * g.a_k] : (uint16_t)0;
+      const int bk = b_nfast ? idx >> 6 : idx & 15, bn = b_nfast ? idx & 63 : idx >> 4;
       const int kk = k0 + bk, n = n0 + bn;
-      Bs[bk][bn] = (kk < g.K && n < g.N) ? g.B[(long)kk * g.b_k + (long)n * g.b_n] : (uint16_t)0;
+      Bs[bk][bn] = (kk < kend && n < g.N) ? g.B[(long)kk * g.b_k + (long)n * g.b_n] : (uint16_t)0;
     }
     __syncthreads();
     const int r = lane & 15, q = lane >> 4;
@@ -133,7 +143,7 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
         const long o = (long)m * g.ldc + n;
         float v = acc[i][j][t];
         if (g.epi == EPI_STORE) {
-          g.C[o] = v;
+          g.C[o + blockIdx.z * g.c_split] = v;
         } else if (g.epi == EPI_BIAS) {
           g.C[o] = v + g.bias[n];
         } else if (g.epi == EPI_BIAS_GELU) {
@@ -148,9 +158,43 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
       }
 }
 
-hipError_t gemm(const GemmArgs &g, hipStream_t s) {
+hipError_t gemm(GemmArgs g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.N + 63) / 64, (g.M + 63) / 64), dim3(256), 0, s, g);
+  g.kc = g.K;
+  g.c_split = 0;
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.N + 63) / 64, (g.M + 63) / 64, 1), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// out[i] = sum over z of part[z * stride + i], z ascending (a fixed order, so
+// the result does not depend on scheduling).
+__global__ void reduce_splits_kernel(const float *__restrict__ part, int splits, long stride, long n,
+                                     float *__restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.0f;
+  for (int z = 0; z < splits; ++z) acc += part[(long)z * stride + i];
+  out[i] = acc;
+}
+
+constexpr int MAX_SPLITS = 32;
+// C (M x N, ldc = N) = A B with a long contraction K: the K range is cut into
+// up to MAX_SPLITS chunks of whole 16-steps so that small outputs (weight
+// gradients) still spread over the chip; partial sums go to `part`
+// (MAX_SPLITS x M x N floats) and are reduced in a fixed order.
+hipError_t gemm_split(GemmArgs g, float *part, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const int tiles = ((g.N + 63) / 64) * ((g.M + 63) / 64);
+  int splits = std::max(1, std::min(MAX_SPLITS, 512 / tiles));
+  g.kc = ((g.K + splits - 1) / splits + 15) / 16 * 16;
+  splits = std::max(1, (g.K + g.kc - 1) / g.kc);
+  float *out = g.C;
+  g.C = part;
+  g.c_split = (long)g.M * g.ldc;
+  g.epi = EPI_STORE;
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.N + 63) / 64, (g.M + 63) / 64, splits), dim3(256), 0, s, g);
+  const long n = (long)g.M * g.ldc;
+  hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, splits, n, n, out);
   return hipGetLastError();
 }
 
@@ -209,13 +253,25 @@ __global__ void __launch_bounds__(1024) sum_kernel(const float *__restrict__ v, 
   if (threadIdx.x == 0) *out = (float)(part[0] / (double)scale);
 }
 
-// Column sums (bias gradients): out[c] = sum_r M[r * cols + c], one thread per column.
-__global__ void colsum_kernel(const float *__restrict__ M, int rows, int cols, float *__restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
-  float s = 0.0f;
-  for (int r = 0; r < rows; ++r) s += M[(long)r * cols + c];
-  out[c] = s;
+// Column sums (bias gradients): out[c] = sum_r M[r * cols + c].  A 32 x 32
+// block covers 32 columns: thread (x, y) sums rows y, y + 32, ... of column x
+// (neighbouring threads read neighbouring columns), then the 32 partial sums of
+// each column are added in row order, so the result is deterministic.
+__global__ void __launch_bounds__(1024) colsum_kernel(const float *__restrict__ M, int rows, int cols,
+                                                      float *__restrict__ out) {
+  __shared__ float part[32][33];
+  const int x = threadIdx.x & 31, y = threadIdx.x >> 5;
+  const int c = blockIdx.x * 32 + x;
+  float acc = 0.0f;
+  if (c < cols)
+    for (int r = y; r < rows; r += 32) acc += M[(long)r * cols + c];
+  part[y][x] = acc;
+  __syncthreads();
+  if (y == 0 && c < cols) {
+    float t = 0.0f;
+    for (int k = 0; k < 32; ++k) t += part[k][x];
+    out[c] = t;
+  }
 }
 
 // Adam (Kingma & Ba) with bias correction; refreshes the BF16 weight copy.
@@ -426,6 +482,7 @@ struct cem_mlp {
   float *Zp[3] = {nullptr, nullptr, nullptr}, *Yn = nullptr, *dY = nullptr, *sq = nullptr, *dZf = nullptr;
   float *Ypred = nullptr, *loss = nullptr, *Xb = nullptr, *Yb = nullptr, *Zs = nullptr, *Ps = nullptr;
   float *err = nullptr;
+  float *part = nullptr;  // split-contraction partial sums (MAX_SPLITS x 256 x 256)
   uint64_t *keys = nullptr;
   int32_t *sel = nullptr;
   int step = 0;
@@ -502,9 +559,10 @@ hipError_t loss_grad_n(cem_mlp *m, const float *X, const float *T, int n, hipStr
   for (int l = NL - 1; l >= 0; --l) {
     const int ni = DIMS[l];
     // dW_l[o][i] = sum_b dZ[b][o] Hin[b][i]
-    e = gemm(gargs(dZ, 1, nz, Hin[l], ni, 1, nz, ni, n, EPI_STORE, nullptr, nullptr, m->G + w_off(l), nullptr, ni), s);
+    e = gemm_split(gargs(dZ, 1, nz, Hin[l], ni, 1, nz, ni, n, EPI_STORE, nullptr, nullptr, m->G + w_off(l), nullptr, ni),
+                   m->part, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(nz, 256)), dim3(256), 0, s, dZf, n, nz, m->G + b_off(l));
+    hipLaunchKernelGGL(colsum_kernel, dim3((nz + 31) / 32), dim3(1024), 0, s, dZf, n, nz, m->G + b_off(l));
     if (l == 0) break;
     // dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1})
     uint16_t *out = m->dZb[(NL - 1 - l) & 1];
@@ -522,7 +580,7 @@ void mlp_release(cem_mlp *m) {
   if (m->own) (void)hipStreamDestroy(m->own);
   void *ptrs[] = {m->P, m->G, m->m, m->v, m->Pb, m->norm, m->Xn, m->H[0], m->H[1], m->H[2], m->dYb, m->dZb[0],
                   m->dZb[1], m->Zp[0], m->Zp[1], m->Zp[2], m->Yn, m->dY, m->sq, m->dZf, m->Ypred, m->loss,
-                  m->Xb, m->Yb, m->Zs, m->Ps, m->err, m->keys, m->sel};
+                  m->Xb, m->Yb, m->Zs, m->Ps, m->err, m->part, m->keys, m->sel};
   for (void *p : ptrs) (void)hipFree(p);
 }
 
@@ -569,6 +627,7 @@ int cem_mlp_init(uint64_t seed, int32_t max_rows, cem_mlp **out) {
   alloc((void **)&m->Zs, sizeof(float) * R * IN);
   alloc((void **)&m->Ps, sizeof(float) * R * OUT);
   alloc((void **)&m->err, sizeof(float) * MAX_STATS_ITERS);
+  alloc((void **)&m->part, sizeof(float) * MAX_SPLITS * HID * HID);
   alloc((void **)&m->keys, sizeof(uint64_t) * R);
   alloc((void **)&m->sel, sizeof(int32_t) * R);
   if (!ok) {
