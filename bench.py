@@ -60,16 +60,18 @@ def cpu_baseline(w, seed, budget_s):
     Z = O.sample(seed, 0, 0, n, mu0, L)
     done, reps = 0, 0
     t0 = time.perf_counter()
+    settle = w["scene"].get("settle_steps", 0)
     while True:
-        O.rollout(w, seed, Z, threads=threads)
-        done += n * H
+        steps = O.rollout(w, seed, Z, threads=threads, with_steps=True)[4]
+        done += int(steps.sum())
         reps += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+    span = ("full horizon %d steps" % H) if not settle else ("horizon %d, early stop after %d settled steps" % (H, settle))
     return {"value": done / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
-            "sample": "%d x %d rollouts of %d iteration-0 samples (full horizon %d steps), %.1f s"
-                      % (reps, n, n, H, dt), "env_steps": done, "seconds": dt}
+            "sample": "%d x %d rollouts of %d iteration-0 samples (%s), %.1f s" % (reps, n, n, span, dt),
+            "env_steps": done, "seconds": dt}
 
 
 def bench_batch(a):
@@ -79,7 +81,9 @@ def bench_batch(a):
     from paper_2512_11571_amd import workloads
     from paper_2512_11571_amd.binding import Batch
 
-    insts = workloads.batch_instances()
+    spec = workloads.load(a.workload)["batch"]
+    kinds = list(spec["kinds"])
+    insts = workloads.batch_instances(spec)
     K = a.steps if a.steps is not None else 3
     cap = min(i["iters"] for i in insts)
     if K > cap:
@@ -103,7 +107,7 @@ def bench_batch(a):
         elapsed = time.perf_counter() - t0
         step_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
     env_steps_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"] for i in insts)
-    fps = {k: workloads.load(k).get("measurement", {}).get("flops_per_env_step") for k in ("push", "pickplace")}
+    fps = {k: workloads.load(k).get("measurement", {}).get("flops_per_env_step") for k in kinds}
     flops_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"]
                      * (fps[i["workload"]["scene"]["kind"]] or 0.0) for i in insts)
     # the replayed step is sampling + the rollout launch + refit; the rollout is > 99.9 % of it,
@@ -117,7 +121,7 @@ def bench_batch(a):
         "ms_per_step": elapsed / K * 1e3, "cem_iters_per_s": K / elapsed,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (FP64 refit and Cholesky)", "data": "synthetic (seeded instances, scenes and Philox samples)",
-        "config": {"workload": "batch", "instances": len(insts), "env_steps_per_iter": env_steps_iter,
+        "config": {"workload": a.workload, "instances": len(insts), "env_steps_per_iter": env_steps_iter,
                    "autotune": tune},
         "step_event_ms": roll_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -126,9 +130,9 @@ def bench_batch(a):
     }
     if not a.no_cpu_baseline:
         per_kind = []
-        for k in ("push", "pickplace"):
+        for k in kinds:
             w = next(i["workload"] for i in insts if i["workload"]["scene"]["kind"] == k)
-            per_kind.append(cpu_baseline(w, a.seed, a.cpu_seconds / 2))
+            per_kind.append(cpu_baseline(w, a.seed, a.cpu_seconds / len(kinds)))
         tot_t = sum(p["seconds"] for p in per_kind)
         steps = sum(p["env_steps"] for p in per_kind)
         out["cpu_baseline"] = {"value": steps / tot_t, "unit": "env-steps/s", "cores": per_kind[0]["cores"],
@@ -269,6 +273,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--settle-steps", type=int, default=0,
+                    help="robot workloads: stop a rollout once its plan has ended and the object has rested this "
+                         "many control steps (0: every rollout runs the full horizon); throughput then counts the "
+                         "steps actually simulated")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the known-size "
                          "reference for the HBM byte counters) and exit")
@@ -287,7 +295,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "launches": 3}))
         return
-    if a.workload == "batch":
+    if a.workload in ("batch", "batch_mixed"):
         bench_batch(a)
         return
     if a.workload == "surrogate":
@@ -299,6 +307,11 @@ def main():
     from paper_2512_11571_amd.binding import Context
 
     w = workloads.load(a.workload)
+    if a.settle_steps:
+        if w["scene"]["kind"] == "push":
+            print("--settle-steps applies to the robot workloads only", file=sys.stderr)
+            sys.exit(2)
+        w["scene"]["settle_steps"] = a.settle_steps
     cem, sc = w["cem"], w["scene"]
     pop, H, D = cem["pop"], sc["horizon"], {"push": 3, "pickplace": 16, "movepush": 12}[sc["kind"]]
     K = a.steps if a.steps is not None else cem["iters"]
@@ -323,23 +336,27 @@ def main():
         torch.cuda.synchronize()
         c.reset()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        counted0 = c.env_steps()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for j in range(K):
             step(j, evs[j])
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        env_steps = c.env_steps() - counted0   # the control steps the rollouts simulated
         roll_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
         mu, S = c.get_theta()
 
-    env_steps = pop * H * K
+    if not sc.get("settle_steps", 0):
+        assert env_steps == pop * H * K, (env_steps, pop * H * K)
     value = env_steps / elapsed
     roll_avg_s = sum(roll_ms) / len(roll_ms) / 1e3
     meas = w.get("measurement", {})
     fps = meas.get("flops_per_env_step")
-    achieved = (fps * pop * H / roll_avg_s / 1e12) if fps else None
+    achieved = (fps * env_steps / K / roll_avg_s / 1e12) if fps else None
     tr = MEASURED_TRAFFIC.get(a.workload)
-    traffic = tr["bytes_per_launch"] if tr and tr.get("src_hash") == _src_hash(a.workload) else None
+    traffic = (tr["bytes_per_launch"] if tr and tr.get("src_hash") == _src_hash(a.workload)
+               and not sc.get("settle_steps", 0) else None)
     out = {
         "metric": "env-steps/s (CE iterations/s alongside)",
         "value": value,
@@ -355,7 +372,10 @@ def main():
         "dtype": "f32 (FP64 refit and Cholesky)",
         "data": "synthetic (seeded scene and Philox samples)",
         "config": {"workload": a.workload, "pop": pop, "horizon": H, "substeps": sc["substeps"], "dim": D,
-                   "n_elite": cem["n_elite"], "dt": sc["dt"], "seed": a.seed},
+                   "n_elite": cem["n_elite"], "dt": sc["dt"], "seed": a.seed,
+                   "settle_steps": sc.get("settle_steps", 0)},
+        "env_steps_simulated": env_steps,
+        "env_steps_full_horizon": pop * H * K,
         "rollout_kernel_ms": roll_avg_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": traffic,

@@ -112,6 +112,15 @@ typedef struct cem_scene {
   float push_vmin, push_vmax, push_dmax, timeout_push;
   float obj_mu_lo, obj_mu_hi;
   float goal_box_center[3], goal_box_half[3];
+  /* Early stop of a robot rollout (0: off, every rollout runs T steps).  When
+   * > 0, a rollout ends after the control step at which, for settle_steps
+   * consecutive steps, every action has ended and the object has moved slower
+   * than rest_speed; psi_g is then read at that step.  The cost is final once
+   * the last action has ended, so only psi_g of an object that would start
+   * moving again afterwards can differ from the full-horizon result.  The
+   * push scene ignores it. */
+  int32_t settle_steps;
+  int32_t reserved_scene;
 } cem_scene;
 
 /* One CE problem (Alg. 1 inputs).  mu0 has D entries, cov0 D x D row-major
@@ -200,6 +209,11 @@ int cem_get_factor(cem_ctx *c, double *L);
  * host draws[3] = (goal x, goal y, object friction coefficient or 0 when the
  * scene does not draw one). Synchronous. */
 int cem_get_instance(cem_ctx *c, double *draws);
+/* Control steps simulated by this context's rollouts since cem_init, summed
+ * over environments: T per rollout, fewer for one that stopped early or
+ * diverged.  Batched runs count into each instance's context.  Waits for all
+ * work on the device first.  Synchronous. */
+int cem_env_steps(cem_ctx *c, uint64_t *steps);
 /* Reset the best-so-far record and the iteration counter. Synchronous. */
 int cem_reset(cem_ctx *c);
 

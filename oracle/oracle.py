@@ -45,6 +45,7 @@ class RefScene(ctypes.Structure):
         ("goal_static", _i), ("joint_speed_max", _d), ("accel_max", _d),
         ("push_vmin", _d), ("push_vmax", _d), ("push_dmax", _d), ("timeout_push", _d),
         ("obj_mu_lo", _d), ("obj_mu_hi", _d), ("goal_box_center", _d * 3), ("goal_box_half", _d * 3),
+        ("settle_steps", _i),
     ]
 
 
@@ -90,7 +91,7 @@ def lib():
         L.ref_sample.argtypes = [u64, u32, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.ref_draw_instance.argtypes = [P(RefScene), u64, u32, vp]
         L.ref_rollout.argtypes = [P(RefScene), u64, u32, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int,
-                                  ctypes.c_int]
+                                  ctypes.c_int, vp]
         L.ref_count_ops.argtypes = [P(RefScene), u64, u32, vp, vp]
         L.ref_select.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp]
         L.ref_cholesky.argtypes = [ctypes.c_int, vp, vp]
@@ -199,6 +200,7 @@ def make_scene(workload):
                 s.goal_box_center[k] = gb["center"][k]
                 s.goal_box_half[k] = gb["half"][k]
     s.obj_mu_lo, s.obj_mu_hi = ob.get("mu", (0.0, 0.0))
+    s.settle_steps = sc.get("settle_steps", 0)
     return s
 
 
@@ -261,8 +263,9 @@ def draw_instance(workload, seed, inst=0):
     return g
 
 
-def rollout(workload, seed, Z, inst=0, trace_steps=0, threads=None):
-    """FP64 rollouts of the rows of Z: returns cost (f64), tier (u8), pose (pop x 7), trace or None."""
+def rollout(workload, seed, Z, inst=0, trace_steps=0, threads=None, with_steps=False):
+    """FP64 rollouts of the rows of Z: returns cost (f64), tier (u8), pose (pop x 7), trace or None
+    (and, with_steps, the control steps each rollout simulated)."""
     s = make_scene(workload)
     Z = np.ascontiguousarray(Z, np.float32)
     pop = Z.shape[0]
@@ -272,10 +275,13 @@ def rollout(workload, seed, Z, inst=0, trace_steps=0, threads=None):
     tw = 13 if workload["scene"]["kind"] == "push" else 35
     trace = np.zeros((pop, trace_steps, tw), np.float64) if trace_steps else None
     threads = threads or default_threads()
+    steps = np.zeros(pop, np.int32)
     rc = lib().ref_rollout(ctypes.byref(s), seed, inst, pop, _ptr(Z), _ptr(cost), _ptr(tier), _ptr(pose),
-                           _ptr(trace) if trace is not None else None, trace_steps, threads)
+                           _ptr(trace) if trace is not None else None, trace_steps, threads, _ptr(steps))
     if rc != 0:
         raise RuntimeError("oracle rollout failed (%d)" % rc)
+    if with_steps:
+        return cost, tier, pose, trace, steps
     return cost, tier, pose, trace
 
 

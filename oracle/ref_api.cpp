@@ -108,7 +108,7 @@ void ref_draw_instance(const RefScene *s, uint64_t seed, uint32_t inst, double o
 
 // Roll out pop parameter rows; trace (optional) gets trace_steps states per env.
 int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const float *Z, double *cost,
-                uint8_t *tier, double *pose, double *trace, int trace_steps, int threads) {
+                uint8_t *tier, double *pose, double *trace, int trace_steps, int threads, int32_t *steps) {
   const int D = param_dim(*s);
   const Instance in = draw_instance(*s, seed, inst);
   if (s->kind != SCENE_PUSH && s->kind != SCENE_PICKPLACE && s->kind != SCENE_MOVEPUSH) return 1;
@@ -120,6 +120,7 @@ int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const 
     tier[i] = (uint8_t)o.tier;
     if (pose)
       for (int c = 0; c < 7; ++c) pose[(long)i * 7 + c] = o.pose[c];
+    if (steps) steps[i] = o.steps;
   });
   return 0;
 }
@@ -365,7 +366,7 @@ int ref_plan_solve(const RefScene *s, uint64_t seed, uint32_t inst, int pop, int
   double bc = INFINITY;
   for (int j = 0; j < iters; ++j) {
     ref_sample(seed, (uint32_t)j, inst, pop, D, mu.data(), L.data(), Z.data());
-    ref_rollout(s, seed, inst, pop, Z.data(), cost.data(), tier.data(), nullptr, nullptr, 0, threads);
+    ref_rollout(s, seed, inst, pop, Z.data(), cost.data(), tier.data(), nullptr, nullptr, 0, threads, nullptr);
     for (int i = 0; i < pop; ++i) costf[i] = (float)cost[i];
     int32_t mode, counts[4];
     const int ne = select_elites(pop, costf.data(), tier.data(), n_elite, elite.data(), &mode, counts);

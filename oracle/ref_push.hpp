@@ -16,6 +16,7 @@ struct RolloutOut {
   double cost;
   int32_t tier;      // 0 ok, 3 diverged (the push plan has no other predicate)
   double pose[7];    // final object pose p (3), q (4)
+  int32_t steps;     // control steps simulated
 };
 
 // Free-body state trace layout per control step: p(3) q(4) v(3) w(3).
@@ -93,6 +94,7 @@ RolloutOut push_rollout(const RefScene &s, const Instance &inst, const float *z,
   const T dist = r_sqrt(dx * dx + dy * dy);
   const T cost = dist + T(s.time_weight) * T(s.dt) * T((double)unsuccessful);
   RolloutOut out;
+  out.steps = s.horizon;
   out.cost = r_val(cost);
   out.pose[0] = r_val(b.p.x); out.pose[1] = r_val(b.p.y); out.pose[2] = r_val(b.p.z);
   out.pose[3] = r_val(b.q.w); out.pose[4] = r_val(b.q.x); out.pose[5] = r_val(b.q.y); out.pose[6] = r_val(b.q.z);

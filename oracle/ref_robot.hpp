@@ -340,6 +340,8 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
 
   start_action(0, 0);
   bool diverged = false;
+  int steps = s.horizon;
+  int calm = 0;  // consecutive control steps with every action ended and the object at rest
   for (int t = 0; t < s.horizon; ++t) {
     // action sequencing
     if (act < n_act) {
@@ -495,7 +497,14 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       o[10] = r_val(ob.w.x); o[11] = r_val(ob.w.y); o[12] = r_val(ob.w.z);
       for (int j = 0; j < NJ; ++j) { o[13 + j] = r_val(q[j]); o[24 + j] = r_val(qd[j]); }
     }
-    if (!r_finite(ob.p.x) || !r_finite(q[0])) { diverged = true; break; }
+    if (!r_finite(ob.p.x) || !r_finite(q[0])) { diverged = true; steps = t + 1; break; }
+    if (s.settle_steps > 0) {
+      // early stop: the plan has ended and the object has stayed at rest; the
+      // cost no longer changes and psi_g is read at this step
+      const bool at_rest = std::sqrt(r_val(dot(ob.v, ob.v))) < s.rest_speed;
+      calm = (act >= n_act && at_rest) ? calm + 1 : 0;
+      if (calm >= s.settle_steps) { steps = t + 1; break; }
+    }
   }
   // goal psi_g at T, the object at rest and either on the goal table's top
   // face (pick-and-place) or with its centre inside the goal box (move-push:
@@ -513,6 +522,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
     goal = std::fabs(px - c[0]) <= hb[0] && std::fabs(py - c[1]) <= hb[1] && std::fabs(pz - c[2]) <= hb[2] && rest;
   }
   RolloutOut out;
+  out.steps = steps;
   const T cost = T(s.time_weight) * dt * T((double)unsuccessful);
   out.cost = r_val(cost);
   out.pose[0] = r_val(ob.p.x); out.pose[1] = r_val(ob.p.y); out.pose[2] = r_val(ob.p.z);

@@ -53,6 +53,9 @@ struct RefScene {
   double obj_mu_lo, obj_mu_hi;
   // goal region used when goal_static < 0: the object's centre inside this box, at rest
   double goal_box_center[3], goal_box_half[3];
+  // early stop of a robot rollout (0 = off): once every action has ended, stop
+  // after this many consecutive control steps with the object at rest
+  int32_t settle_steps;
 };
 
 // Per-instance draws (scene stream 1, sample 0, iteration 0, instance b), one

@@ -58,6 +58,7 @@ class CemScene(ctypes.Structure):
         ("goal_static", _i), ("joint_speed_max", _f), ("accel_max", _f),
         ("push_vmin", _f), ("push_vmax", _f), ("push_dmax", _f), ("timeout_push", _f),
         ("obj_mu_lo", _f), ("obj_mu_hi", _f), ("goal_box_center", _f * 3), ("goal_box_half", _f * 3),
+        ("settle_steps", _i), ("reserved_scene", _i),
     ]
 
 
@@ -79,7 +80,7 @@ class CemResult(ctypes.Structure):
 
 EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem_last_error", "cem_sample", "rollout_batch",
            "rollout_trace", "cem_refit", "plan_solve", "cem_get_theta", "cem_set_theta", "cem_get_factor",
-           "cem_get_instance", "cem_reset", "cem_batch_init", "cem_batch_free", "cem_batch_size",
+           "cem_get_instance", "cem_env_steps", "cem_reset", "cem_batch_init", "cem_batch_free", "cem_batch_size",
            "cem_batch_last_error", "cem_batch_instance", "cem_batch_autotune", "cem_batch_step", "cem_batch_solve",
            "cem_batch_record", "cem_mlp_init", "cem_mlp_free", "cem_mlp_n_params", "cem_mlp_last_error",
            "cem_mlp_get_params", "cem_mlp_set_params", "cem_mlp_get_norm", "cem_mlp_set_norm", "cem_mlp_fit_norm",
@@ -114,6 +115,7 @@ def lib():
         L.cem_set_theta.argtypes = [vp, vp, vp]
         L.cem_get_factor.argtypes = [vp, vp]
         L.cem_get_instance.argtypes = [vp, vp]
+        L.cem_env_steps.argtypes = [vp, P(ctypes.c_uint64)]
         L.cem_reset.argtypes = [vp]
         L.cem_sizeof.argtypes = [ctypes.c_int]
         L.cem_batch_init.argtypes = [vp, vp, _i, P(vp)]
@@ -221,6 +223,7 @@ def make_scene(workload):
                 s.goal_box_center[k] = gb["center"][k]
                 s.goal_box_half[k] = gb["half"][k]
     s.obj_mu_lo, s.obj_mu_hi = ob.get("mu", (0.0, 0.0))
+    s.settle_steps = int(sc.get("settle_steps", 0))
     return s
 
 
@@ -355,6 +358,12 @@ class Context:
         g = np.zeros(3)
         self._check(lib().cem_get_instance(self.h, _np_ptr(g)))
         return g
+
+    def env_steps(self):
+        """Control steps simulated by this context's rollouts so far (summed over environments)."""
+        n = ctypes.c_uint64(0)
+        self._check(lib().cem_env_steps(self.h, ctypes.byref(n)))
+        return int(n.value)
 
     def reset(self):
         self._check(lib().cem_reset(self.h))

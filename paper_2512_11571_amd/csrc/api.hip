@@ -49,6 +49,7 @@ const char *check_scene(const cem_scene &s) {
   if (dim_of(s.kind) == 0) return "unknown scene kind";
   if (s.substeps < 1 || s.substeps > 1000) return "substeps out of range [1, 1000]";
   if (s.horizon < 1 || s.horizon > 100000) return "horizon out of range [1, 100000]";
+  if (s.settle_steps < 0 || s.settle_steps > s.horizon) return "settle_steps out of range [0, horizon]";
   if (!pos(s.dt) || !nonneg(s.gravity) || !nonneg(s.k_contact) || !nonneg(s.c_contact) || !pos(s.eps_v))
     return "invalid physical constants";
   if (!nonneg(s.mu_ground) || !nonneg(s.mu_tool) || !nonneg(s.mu_static) || !nonneg(s.mu_ramp))
@@ -399,6 +400,16 @@ int cem_get_instance(cem_ctx *c, double *draws) {
   HIPCHK(c, hipMemcpyAsync(&mu, &c->st->obj_mu, sizeof(float), hipMemcpyDeviceToHost, c->own));
   HIPCHK(c, hipStreamSynchronize(c->own));
   draws[2] = (double)mu;
+  return CEM_OK;
+}
+
+int cem_env_steps(cem_ctx *c, uint64_t *steps) {
+  if (!c) return CEM_E_ARG;
+  if (!steps) return fail(c, CEM_E_ARG, "null output");
+  HIPCHK(c, hipDeviceSynchronize());
+  unsigned long long n = 0;
+  HIPCHK(c, hipMemcpy(&n, &c->st->env_steps, sizeof n, hipMemcpyDeviceToHost));
+  *steps = (uint64_t)n;
   return CEM_OK;
 }
 

@@ -41,6 +41,10 @@ struct DevState {
   int32_t pop;
   cem_scene scene;             // device copy of the scene (read by the rollout kernels)
   SceneConsts sk;              // derived from scene by launch_scene_consts
+  // Control steps the rollouts of this context have simulated (summed over
+  // environments).  The only field a rollout writes: one atomic add per work
+  // item through a generic pointer, never read by device code.
+  unsigned long long env_steps;
 };
 
 // One task instance as the launches see it: its device state and buffers.

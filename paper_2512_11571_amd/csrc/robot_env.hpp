@@ -97,8 +97,10 @@ __device__ __forceinline__ int qref_row(int j) { return R_QREF + (j < FL ? j : F
 // `lds_mem` is the block's R_ROWS x PP_LANES float array and `lane` this
 // lane's column in it.  The scene, its derived constants and the instance's
 // object friction draw (0: the per-class coefficients) come from `st`.
+// Returns the control steps simulated: T, or fewer after an early stop
+// (scene settle_steps > 0) or a divergence.
 template <bool TRACE>
-__device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict__ Z, long env,
+__device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict__ Z, long env,
                                           float *lds_mem, int lane, float *__restrict__ cost_out,
                                           uint8_t *__restrict__ tier_out, float *__restrict__ pose_out,
                                           float *__restrict__ trace, int trace_steps) {
@@ -264,6 +266,8 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
 
   start_action(0, 0);
   bool diverged = false;
+  int steps = sc.horizon;
+  int calm = 0;  // consecutive control steps with every action ended and the object at rest
   for (int t = 0; t < sc.horizon; ++t) {
     // ---- action sequencing (control rate) ----
     if (act < n_act) {
@@ -576,7 +580,18 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
     }
     if (!isfinite(ob.p.x) || !isfinite(L.at(R_Q + 0))) {
       diverged = true;
+      steps = t + 1;
       break;
+    }
+    if (sc.settle_steps > 0) {
+      // early stop: the cost is final once the last action has ended; after
+      // settle_steps steps of the object at rest psi_g is read at this step
+      const bool at_rest = sqrtf(dot(ob.v, ob.v)) < sc.rest_speed;
+      calm = (act >= n_act && at_rest) ? calm + 1 : 0;
+      if (calm >= sc.settle_steps) {
+        steps = t + 1;
+        break;
+      }
     }
   }
   // goal psi_g: the object at rest, on the goal table's top face or with its centre inside the goal box
@@ -606,6 +621,7 @@ __device__ __forceinline__ void robot_env(CDevState *st, const float *__restrict
   if (pose_out)
 #pragma unroll
     for (int i = 0; i < 7; ++i) pose_out[(long)env * 7 + i] = pose[i];
+  return steps;
 }
 
 }  // namespace

@@ -52,13 +52,22 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
       n = min(64, d.pop - env0);
     }
     CDevState *st = (CDevState *)d.st;
-    const bool active = !(check_iter && st->iter >= d.iters);
+    const bool active = !(check_iter && st->iter >= d.iters);  // wave-uniform
+    int steps = 0;
     if (active && lane < n) {
       const long env = env0 + lane;
-      if (d.kind == CEM_SCENE_PUSH)
+      if (d.kind == CEM_SCENE_PUSH) {
         push_env<TRACE>(st->scene, st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
-      else
-        robot_env<TRACE>(st, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
+        steps = st->scene.horizon;
+      } else {
+        steps = robot_env<TRACE>(st, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
+      }
+    }
+    if (active) {
+      // the item's simulated control steps, one atomic add per wave
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) steps += __shfl_xor(steps, m);
+      if (lane == 0) atomicAdd(&d.st->env_steps, (unsigned long long)steps);
     }
     if (!queue) break;
   }

@@ -62,3 +62,25 @@ def test_extra_steps_past_the_caps_change_nothing(binding):
         r2 = B.solve(2)           # every instance is already at its cap
     for a, b in zip(r1, r2):
         assert _same(a, b)
+
+
+def test_mixed_plans_batched_equal_single_runs(binding):
+    # push, pick-and-place and move-and-push instances (three action sequences) in one launch
+    spec = dict(workloads.load("batch_mixed")["batch"])
+    spec.update(n_instances=6, horizon=[100, 300], pop=[64, 200], iters={"push": 3, "pickplace": 2, "movepush": 2},
+                seed=3)
+    insts = workloads.batch_instances(spec)
+    assert {i["workload"]["scene"]["kind"] for i in insts} == {"push", "pickplace", "movepush"}
+    with binding.Batch(insts) as B:
+        res = B.solve(3)
+        # each instance's context counts the control steps its own rollouts ran
+        counted = [B.instance(k).env_steps() for k in range(len(insts))]
+    for inst, r, n in zip(insts, res, counted):
+        assert r["iters_done"] == inst["iters"]
+        w = inst["workload"]
+        full = inst["iters"] * w["cem"]["pop"] * w["scene"]["horizon"]
+        assert n == full, (inst["instance"], n, full)
+        with binding.Context(w, seed=inst["seed"], instance=inst["instance"]) as c:
+            s = c.plan_solve(inst["iters"])
+            assert c.env_steps() == full
+        assert _same(r, s), inst["instance"]
