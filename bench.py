@@ -314,6 +314,7 @@ def main():
         w["scene"]["settle_steps"] = a.settle_steps
     cem, sc = w["cem"], w["scene"]
     pop, H, D = cem["pop"], sc["horizon"], {"push": 3, "pickplace": 16, "movepush": 12}[sc["kind"]]
+    sched = cem.get("pop_schedule")
     K = a.steps if a.steps is not None else cem["iters"]
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
@@ -323,13 +324,14 @@ def main():
     stream = torch.cuda.current_stream()
     with Context(w, seed=a.seed) as c:
         def step(j, evs=None):
+            n = c.pop_at(j)                    # n_env(j): pop unless the workload has a schedule
             c.cem_sample(j, Z, stream)
             if evs is not None:
                 evs[0].record(stream)
-            c.rollout_batch(Z, cost, tier, None, stream)
+            c.rollout_batch(Z[:n], cost[:n], tier[:n], None, stream)
             if evs is not None:
                 evs[1].record(stream)
-            c.cem_refit(Z, cost, tier, None, None, stream)
+            c.cem_refit(Z[:n], cost[:n], tier[:n], None, None, stream)
 
         for j in range(a.warmup):
             step(j)
@@ -337,6 +339,7 @@ def main():
         c.reset()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
         counted0 = c.env_steps()
+        pops = [c.pop_at(j) for j in range(K)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for j in range(K):
@@ -347,8 +350,8 @@ def main():
         roll_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
         mu, S = c.get_theta()
 
-    if not sc.get("settle_steps", 0):
-        assert env_steps == pop * H * K, (env_steps, pop * H * K)
+    full = sum(pops) * H
+    assert env_steps <= full, (env_steps, full)   # fewer only where rollouts stopped early or diverged
     value = env_steps / elapsed
     roll_avg_s = sum(roll_ms) / len(roll_ms) / 1e3
     meas = w.get("measurement", {})
@@ -373,9 +376,10 @@ def main():
         "data": "synthetic (seeded scene and Philox samples)",
         "config": {"workload": a.workload, "pop": pop, "horizon": H, "substeps": sc["substeps"], "dim": D,
                    "n_elite": cem["n_elite"], "dt": sc["dt"], "seed": a.seed,
-                   "settle_steps": sc.get("settle_steps", 0)},
+                   "settle_steps": sc.get("settle_steps", 0), "pop_schedule": sched,
+                   "init_region": bool(cem.get("init_region"))},
         "env_steps_simulated": env_steps,
-        "env_steps_full_horizon": pop * H * K,
+        "env_steps_full_horizon": full,
         "rollout_kernel_ms": roll_avg_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": traffic,

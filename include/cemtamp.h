@@ -49,6 +49,7 @@ enum { CEM_SCENE_PUSH = 1, CEM_SCENE_PICKPLACE = 2, CEM_SCENE_MOVEPUSH = 3 };
 
 #define CEM_MAX_STATIC 8
 #define CEM_MAX_D 16
+#define CEM_MAX_ANNULI 4
 #define CEM_STATS_COLS 8
 #define CEM_TRACE_FREE 13
 #define CEM_MAX_JOINTS 12
@@ -123,6 +124,26 @@ typedef struct cem_scene {
   int32_t reserved_scene;
 } cem_scene;
 
+/* Initial distribution phi(theta^0) as a region (Sec. III-B: iteration 0
+ * draws uniformly inside each parameter's region h(z) <= 0; Sec. IV-A gives
+ * rings around the tables for the base positions and boxes for the others).
+ * Every dimension d draws z_d ~ U[lo_d, hi_d] except the pairs (d, d+1) named
+ * by ann_dim, which draw a point uniform by area in the ring
+ * ann_radius[k][0] <= |(z_d, z_d+1) - ann_center[k]| <= ann_radius[k][1].
+ * The uniforms are the Philox words of the CE stream at iteration 0 (word
+ * d mod 4 of block d / 4 of the sample), so the draw is bit-reproducible:
+ *   box:  z_d = fma(hi_d - lo_d, u_d, lo_d)
+ *   ring: r = sqrt(fma(r1*r1 - r0*r0, u_d, r0*r0)), (s, c) = sincos(2 pi u_d+1),
+ *         z_d = fma(r, c, cx), z_d+1 = fma(r, s, cy)
+ * with every operation in FP32, correctly rounded. */
+typedef struct cem_init_region {
+  float lo[CEM_MAX_D], hi[CEM_MAX_D];
+  int32_t n_annuli;
+  int32_t ann_dim[CEM_MAX_ANNULI];
+  float ann_center[CEM_MAX_ANNULI][2];
+  float ann_radius[CEM_MAX_ANNULI][2];
+} cem_init_region;
+
 /* One CE problem (Alg. 1 inputs).  mu0 has D entries, cov0 D x D row-major
  * (cov_mode 0 reads its diagonal only).  D is fixed by the scene kind
  * (push 3, pick-place 16, move-push 12).  Pointers are host pointers, copied. */
@@ -135,6 +156,15 @@ typedef struct cem_problem {
   const double *mu0, *cov0;
   uint64_t seed;                /* Philox key                                      */
   uint32_t instance;            /* Philox counter word 3 (task instance id)        */
+  /* n_env(j), the samples of iteration j (an input of Alg. 1; Sec. IV-A
+   * lowers it linearly over the first iterations, then holds it).  0 keeps
+   * n_env = pop; otherwise n_elite <= pop_final <= pop, pop_ramp_iters >= 1 and
+   *   n_env(j) = pop - floor((pop - pop_final) * min(j, pop_ramp_iters) / pop_ramp_iters).
+   * plan_solve follows it (launching each iteration directly rather than
+   * replaying a captured graph); batches reject it. */
+  int32_t pop_final, pop_ramp_iters;
+  /* nullable: iteration 0 draws from N(mu0, cov0) like every other */
+  const cem_init_region *init_region;
 } cem_problem;
 
 /* Output of plan_solve (host memory, filled on return). */
@@ -157,7 +187,8 @@ int cem_init(const cem_problem *p, cem_ctx **out);
 void cem_free(cem_ctx *c);
 
 int cem_dim(const cem_ctx *c);
-/* sizeof of the ABI structs (0 cem_scene, 1 cem_problem, 2 cem_result; else 0),
+/* sizeof of the ABI structs (0 cem_scene, 1 cem_problem, 2 cem_result,
+ * 3 cem_init_region; else 0),
  * for bindings to check their layouts. */
 int cem_sizeof(int which);
 const char *cem_strerror(int code);
@@ -165,7 +196,10 @@ const char *cem_last_error(const cem_ctx *c);
 
 /* Alg. 1, sampling step: Z_dev (pop x D row-major, FP32) = mu + L eps with
  * eps ~ N(0, I) from Philox-4x32-10 counters (tag 0, sample i, iteration
- * iter, instance) and Box-Muller; accumulated in FP64, rounded once. */
+ * iter, instance) and Box-Muller; accumulated in FP64, rounded once.  At
+ * iter 0 of a problem with an init_region, the region's uniform draw instead.
+ * Row i depends only on (seed, instance, iter, i), so the first n rows are
+ * the rows of a population of n. */
 int cem_sample(cem_ctx *c, int32_t iter, float *Z_dev, void *stream);
 
 /* Alg. 1, evaluation step: roll every row of Z_dev (pop x D) out for the
@@ -194,8 +228,10 @@ int cem_refit(cem_ctx *c, const float *Z_dev, const float *cost_dev, const uint8
               int32_t *elite_idx_dev, int32_t *sel_info_dev, void *stream);
 
 /* Alg. 1 end to end: iters iterations of sample -> rollout -> refit on the
- * context's own buffers, replayed from one captured HIP graph per iteration.
- * Continues from the context's current theta and iteration counter.
+ * context's own buffers, replayed from one captured HIP graph per iteration
+ * (launched directly, n_env(j) rows each, when the problem has an n_env
+ * schedule).  Continues from the context's current theta and iteration
+ * counter.
  * Synchronous.  stats_host (nullable) gets iters rows of CEM_STATS_COLS floats:
  * best cost of the iteration, n_tier0..3, n_e, mode, best cost so far. */
 int plan_solve(cem_ctx *c, int32_t iters, cem_result *res, float *stats_host, void *stream);
@@ -205,6 +241,9 @@ int cem_get_theta(cem_ctx *c, double *mu, double *cov);
 int cem_set_theta(cem_ctx *c, const double *mu, const double *cov);
 /* Cholesky factor currently used by cem_sample (host L[D*D]). Synchronous. */
 int cem_get_factor(cem_ctx *c, double *L);
+/* n_env(iter) of the context's schedule (pop when it has none); 0 for a
+ * null context or iter < 0. */
+int cem_pop_at(const cem_ctx *c, int32_t iter);
 /* Per-instance scene draws (Philox scene stream, counter word 3 = instance),
  * host draws[3] = (goal x, goal y, object friction coefficient or 0 when the
  * scene does not draw one). Synchronous. */

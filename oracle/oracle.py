@@ -98,7 +98,10 @@ def lib():
         L.ref_factor_cov.argtypes = [ctypes.c_int, vp, vp]
         L.ref_refit.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int32, vp, vp, vp, vp]
         L.ref_plan_solve.argtypes = [P(RefScene), u64, u32, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                     vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+                                     vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int,
+                                     vp, vp, ctypes.c_int, vp, vp]
+        L.ref_sample_region.argtypes = [u64, u32, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp]
+        L.ref_n_env_at.argtypes = [ctypes.c_int] * 4
         L.ref_tree_aba.argtypes = [P(Tree), vp, vp, vp, vp, ctypes.c_double, vp]
         L.ref_tree_rnea.argtypes = [P(Tree), vp, vp, vp, vp, ctypes.c_double, vp]
         L.ref_tree_crba.argtypes = [P(Tree), vp, vp]
@@ -255,6 +258,33 @@ def sample(seed, it, inst, pop, mu, L):
     return out
 
 
+def _region_arrays(reg, D):
+    """FP32 arrays of an init_region dict: lo, hi (D), ring dims, rings (n x (cx, cy, r0, r1))."""
+    lo = np.ascontiguousarray(reg["lo"][:D], np.float32)
+    hi = np.ascontiguousarray(reg["hi"][:D], np.float32)
+    rings = reg.get("rings", [])
+    dims = np.ascontiguousarray([g["dim"] for g in rings] or [0], np.int32)
+    ring = np.ascontiguousarray([list(g["center"]) + list(g["radius"]) for g in rings] or [[0, 0, 0, 0]],
+                                np.float32)
+    return lo, hi, len(rings), dims, ring
+
+
+def sample_region(workload, seed, inst, pop):
+    """Iteration-0 rows from the workload's init_region (Sec. III-B initial distribution)."""
+    D = param_dim(workload)
+    lo, hi, n, dims, ring = _region_arrays(workload["cem"]["init_region"], D)
+    out = np.zeros((pop, D), np.float32)
+    lib().ref_sample_region(seed, inst, pop, D, _ptr(lo), _ptr(hi), n, _ptr(dims), _ptr(ring), _ptr(out))
+    return out
+
+
+def n_env_at(workload, j):
+    """n_env(j) of the workload's schedule (its pop when it has none)."""
+    cem = workload["cem"]
+    sch = cem.get("pop_schedule") or {"final": 0, "iters": 1}
+    return int(lib().ref_n_env_at(cem["pop"], sch["final"], sch["iters"], j))
+
+
 def draw_instance(workload, seed, inst=0):
     """Per-instance scene draws: (goal x, goal y, object friction or 0)."""
     s = make_scene(workload)
@@ -349,8 +379,18 @@ def plan_solve(workload, seed, inst=0, threads=None, iters=None, pop=None):
     S = np.zeros((D, D), np.float64)
     stats = np.zeros((iters, 8), np.float64)
     threads = threads or default_threads()
+    sch = cem.get("pop_schedule") or {"final": 0, "iters": 1}
+    if sch["final"] > pop:
+        raise ValueError("pop_schedule final exceeds pop")
+    reg = cem.get("init_region")
+    lo = hi = dims = ring = None
+    n_rings = 0
+    if reg:
+        lo, hi, n_rings, dims, ring = _region_arrays(reg, D)
     lib().ref_plan_solve(ctypes.byref(s), seed, inst, pop, cem["n_elite"], iters, cov_mode, _ptr(mu0), _ptr(cov0),
-                         threads, _ptr(best_z), _ptr(best_cost), _ptr(best_tier), _ptr(mu), _ptr(S), _ptr(stats))
+                         threads, _ptr(best_z), _ptr(best_cost), _ptr(best_tier), _ptr(mu), _ptr(S), _ptr(stats),
+                         sch["final"], sch["iters"], _ptr(lo) if reg else None, _ptr(hi) if reg else None, n_rings,
+                         _ptr(dims) if reg else None, _ptr(ring) if reg else None)
     return dict(best_z=best_z, best_cost=float(best_cost[0]), best_tier=int(best_tier[0]), mu=mu, S=S, stats=stats)
 
 

@@ -98,6 +98,15 @@ void ref_sample(uint64_t seed, uint32_t iter, uint32_t inst, int pop, int D, con
   for (int i = 0; i < pop; ++i) cem_sample_row(seed, (uint32_t)i, iter, inst, D, mu, L, Z + (long)i * D, nullptr);
 }
 
+// Iteration-0 rows (pop x D) drawn from a region.
+void ref_sample_region(uint64_t seed, uint32_t inst, int pop, int D, const float *lo, const float *hi, int n_rings,
+                       const int *ring_dim, const float *ring, float *Z) {
+  const RefRegion R{lo, hi, n_rings, ring_dim, ring};
+  for (int i = 0; i < pop; ++i) region_sample_row(seed, (uint32_t)i, inst, D, R, Z + (long)i * D);
+}
+
+int ref_n_env_at(int pop, int pop_final, int ramp, int j) { return n_env_at(pop, pop_final, ramp, j); }
+
 // out = (goal x, goal y, object friction) of instance inst.
 void ref_draw_instance(const RefScene *s, uint64_t seed, uint32_t inst, double out[3]) {
   Instance in = draw_instance(*s, seed, inst);
@@ -345,12 +354,15 @@ int ref_refit(int D, int cov_mode, const float *Z, const int32_t *elite, int ne,
 }
 
 // Alg. 1 end to end: `iters` CE iterations of sample -> rollout -> select ->
-// refit on one instance.  Outputs: best-ever row and its cost/tier, final
-// theta (mu, S), and per-iteration stats rows of 8 doubles:
-// [best cost this iteration, n_tier0, n_tier1, n_tier2, n_tier3, n_elite, mode, best-ever cost].
+// refit on one instance, iteration j with n_env(j) samples (pop_final 0: pop
+// each), iteration 0 from the region when lo is given.  Outputs: best-ever
+// row and its cost/tier, final theta (mu, S), and per-iteration stats rows of
+// 8 doubles: [best cost this iteration, n_tier0, n_tier1, n_tier2, n_tier3,
+// n_elite, mode, best-ever cost].
 int ref_plan_solve(const RefScene *s, uint64_t seed, uint32_t inst, int pop, int n_elite, int iters, int cov_mode,
                    const double *mu0, const double *cov0, int threads, float *best_z, double *best_cost,
-                   int32_t *best_tier, double *mu_out, double *S_out, double *stats) {
+                   int32_t *best_tier, double *mu_out, double *S_out, double *stats, int pop_final, int ramp,
+                   const float *lo, const float *hi, int n_rings, const int *ring_dim, const float *ring) {
   const int D = param_dim(*s);
   std::vector<double> mu(mu0, mu0 + D), S(cov0, cov0 + D * D), L(D * D);
   if (cov_mode == 0)
@@ -364,8 +376,13 @@ int ref_plan_solve(const RefScene *s, uint64_t seed, uint32_t inst, int pop, int
   std::vector<int32_t> elite(n_elite);
   int32_t bt = 4;
   double bc = INFINITY;
+  const int pop_max = pop;
   for (int j = 0; j < iters; ++j) {
-    ref_sample(seed, (uint32_t)j, inst, pop, D, mu.data(), L.data(), Z.data());
+    pop = n_env_at(pop_max, pop_final, ramp, j);
+    if (j == 0 && lo)
+      ref_sample_region(seed, inst, pop, D, lo, hi, n_rings, ring_dim, ring, Z.data());
+    else
+      ref_sample(seed, (uint32_t)j, inst, pop, D, mu.data(), L.data(), Z.data());
     ref_rollout(s, seed, inst, pop, Z.data(), cost.data(), tier.data(), nullptr, nullptr, 0, threads, nullptr);
     for (int i = 0; i < pop; ++i) costf[i] = (float)cost[i];
     int32_t mode, counts[4];

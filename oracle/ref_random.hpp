@@ -175,4 +175,46 @@ inline void cem_sample_row(uint64_t seed, uint32_t i, uint32_t j, uint32_t b, in
   }
 }
 
+// Initial distribution as a region (Sec. III-B: iteration 0 samples uniformly
+// inside each parameter's region h(z) <= 0; Sec. IV-A: rings around the tables
+// for the base positions, boxes for the others).  The uniforms are the words
+// of the same Philox blocks the normals of iteration 0 would use: u_d is word
+// d mod 4 of block d / 4.  A box dimension maps u to lo + (hi - lo) u.  A ring
+// pair (d, d+1) with centre c and radii r0 <= r1 must be uniform by area: the
+// fraction of the ring's area within radius r is (r^2 - r0^2) / (r1^2 - r0^2),
+// so r^2 is uniform on [r0^2, r1^2]; the angle is uniform on [0, 2 pi).
+// Every step is one correctly rounded FP32 operation (fma where written), so
+// the GPU's draw is reproducible bit for bit.
+struct RefRegion {
+  const float *lo, *hi;  // D each
+  int n_rings;
+  const int *ring_dim;   // first dimension of each pair
+  const float *ring;     // n_rings x (cx, cy, r0, r1)
+};
+
+inline void region_sample_row(uint64_t seed, uint32_t i, uint32_t b, int D, const RefRegion &R, float *z_out) {
+  float u[64];
+  for (int d = 0; d < D; ++d) u[d] = u01(philox_draw(seed, STREAM_CEM, (uint32_t)(d / 4), i, 0u, b).w[d % 4]);
+  for (int d = 0; d < D; ++d) z_out[d] = std::fma(R.hi[d] - R.lo[d], u[d], R.lo[d]);
+  for (int k = 0; k < R.n_rings; ++k) {
+    const int d = R.ring_dim[k];
+    const float *g = R.ring + 4 * k;
+    const float rr0 = g[2] * g[2], rr1 = g[3] * g[3];
+    const float r = std::sqrt(std::fma(rr1 - rr0, u[d], rr0));
+    float s, c;
+    ref_sincos2pi(u[d + 1], &s, &c);
+    z_out[d] = std::fma(r, c, g[0]);
+    z_out[d + 1] = std::fma(r, s, g[1]);
+  }
+}
+
+// n_env(j): pop, or with a schedule (pop_final > 0) a linear decrease to
+// pop_final over the first `ramp` iterations, constant afterwards (Sec. IV-A,
+// "Algorithm setting"), rounded down in the decrement.
+inline int n_env_at(int pop, int pop_final, int ramp, int j) {
+  if (pop_final <= 0) return pop;
+  const long k = j < ramp ? j : ramp;
+  return pop - (int)((long)(pop - pop_final) * k / ramp);
+}
+
 }  // namespace ref

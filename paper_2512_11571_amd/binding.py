@@ -20,6 +20,7 @@ SCENE_KIND = {"push": 1, "pickplace": 2, "movepush": 3}
 DIM = {"push": 3, "pickplace": 16, "movepush": 12}
 MAX_STATIC = 8
 MAX_D = 16
+MAX_ANNULI = 4
 MAX_JOINTS = 12
 STATS_COLS = 8
 TRACE_FREE = 13
@@ -62,12 +63,21 @@ class CemScene(ctypes.Structure):
     ]
 
 
+class CemInitRegion(ctypes.Structure):
+    _fields_ = [
+        ("lo", _f * MAX_D), ("hi", _f * MAX_D), ("n_annuli", _i), ("ann_dim", _i * MAX_ANNULI),
+        ("ann_center", (_f * 2) * MAX_ANNULI), ("ann_radius", (_f * 2) * MAX_ANNULI),
+    ]
+
+
 class CemProblem(ctypes.Structure):
     _fields_ = [
         ("scene", ctypes.POINTER(CemScene)),
         ("pop", _i), ("n_elite", _i), ("cov_mode", _i), ("reserved", _i),
         ("mu0", ctypes.POINTER(ctypes.c_double)), ("cov0", ctypes.POINTER(ctypes.c_double)),
         ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
+        ("pop_final", _i), ("pop_ramp_iters", _i),
+        ("init_region", ctypes.POINTER(CemInitRegion)),
     ]
 
 
@@ -80,7 +90,7 @@ class CemResult(ctypes.Structure):
 
 EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem_last_error", "cem_sample", "rollout_batch",
            "rollout_trace", "cem_refit", "plan_solve", "cem_get_theta", "cem_set_theta", "cem_get_factor",
-           "cem_get_instance", "cem_env_steps", "cem_reset", "cem_batch_init", "cem_batch_free", "cem_batch_size",
+           "cem_get_instance", "cem_env_steps", "cem_pop_at", "cem_reset", "cem_batch_init", "cem_batch_free", "cem_batch_size",
            "cem_batch_last_error", "cem_batch_instance", "cem_batch_autotune", "cem_batch_step", "cem_batch_solve",
            "cem_batch_record", "cem_mlp_init", "cem_mlp_free", "cem_mlp_n_params", "cem_mlp_last_error",
            "cem_mlp_get_params", "cem_mlp_set_params", "cem_mlp_get_norm", "cem_mlp_set_norm", "cem_mlp_fit_norm",
@@ -116,6 +126,7 @@ def lib():
         L.cem_get_factor.argtypes = [vp, vp]
         L.cem_get_instance.argtypes = [vp, vp]
         L.cem_env_steps.argtypes = [vp, P(ctypes.c_uint64)]
+        L.cem_pop_at.argtypes = [vp, _i]
         L.cem_reset.argtypes = [vp]
         L.cem_sizeof.argtypes = [ctypes.c_int]
         L.cem_batch_init.argtypes = [vp, vp, _i, P(vp)]
@@ -147,7 +158,7 @@ def lib():
         L.cem_mlp_train.argtypes = [vp, vp, vp, i64, _i, _i, ctypes.c_float, ctypes.c_uint64, vp]
         L.cem_screen.argtypes = [vp, vp, _i, _i, vp, vp, vp]
         L.plan_solve_screened.argtypes = [vp, vp, _i, _i, P(CemResult), vp, vp, vp]
-        for which, st in enumerate((CemScene, CemProblem, CemResult)):
+        for which, st in enumerate((CemScene, CemProblem, CemResult, CemInitRegion)):
             if L.cem_sizeof(which) != ctypes.sizeof(st):
                 raise RuntimeError("ABI struct layout mismatch for %s" % st.__name__)
         _lib = L
@@ -264,7 +275,35 @@ def make_problem(workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None,
     p.mu0 = mu0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.cov0 = cov0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.seed, p.instance = int(seed), int(instance)
-    return p, [scene, mu0, cov0]
+    keep = [scene, mu0, cov0]
+    sch = cem.get("pop_schedule")
+    if sch:
+        if sch["final"] > p.pop:
+            raise ValueError("pop_schedule final %d exceeds pop %d" % (sch["final"], p.pop))
+        p.pop_final, p.pop_ramp_iters = int(sch["final"]), int(sch["iters"])
+    reg = cem.get("init_region")
+    if reg:
+        r = make_region(reg)
+        p.init_region = ctypes.pointer(r)
+        keep.append(r)
+    return p, keep
+
+
+def make_region(reg):
+    """cem_init_region from {"lo": [D], "hi": [D], "rings": [{"dim", "center", "radius"}]}."""
+    r = CemInitRegion()
+    for d, (a, b) in enumerate(zip(reg["lo"], reg["hi"])):
+        r.lo[d], r.hi[d] = a, b
+    rings = reg.get("rings", [])
+    if len(rings) > MAX_ANNULI:
+        raise ValueError("at most %d rings" % MAX_ANNULI)
+    r.n_annuli = len(rings)
+    for k, g in enumerate(rings):
+        r.ann_dim[k] = g["dim"]
+        r.ann_center[k][0], r.ann_center[k][1] = g["center"]
+        r.ann_radius[k][0], r.ann_radius[k][1] = g["radius"]
+    return r
+
 
 
 def _result_dict(res, D):
@@ -358,6 +397,10 @@ class Context:
         g = np.zeros(3)
         self._check(lib().cem_get_instance(self.h, _np_ptr(g)))
         return g
+
+    def pop_at(self, it):
+        """n_env(it) of the problem's schedule (its pop when it has none)."""
+        return int(lib().cem_pop_at(self.h, int(it)))
 
     def env_steps(self):
         """Control steps simulated by this context's rollouts so far (summed over environments)."""

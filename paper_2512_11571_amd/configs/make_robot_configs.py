@@ -1,6 +1,7 @@
-"""Writes the two mobile-manipulator workloads (pickplace.json, movepush.json).
+"""Writes the mobile-manipulator workloads (pickplace.json, movepush.json, and
+the paper-setting variants pickplace_paper.json, pickplace_box.json).
 
-Both use the same synthetic 11-joint robot: a holonomic base (x and y
+All use the same synthetic 11-joint robot: a holonomic base (x and y
 prismatic joints on massless bodies, then yaw), a six-joint arm and two
 prismatic fingers on the palm.  Geometry is stated in metres, masses in kg.
 A "measurement" block already in a file (the FLOP count written by the oracle's
@@ -87,6 +88,49 @@ def pickplace():
     }
 
 
+# Sec. IV-A, "Algorithm setting": iteration 0 uniform inside the parameter
+# regions, then independent normals; n_env 3000 falling linearly to 300 by
+# iteration 10; N_e = 50; a budget of 20 iterations.  The regions follow
+# Sec. IV-A's list, with the rings sized to this robot's reach (an arm of
+# about 1 m from a shoulder 0.2 m ahead of the base centre): Table_1 and
+# Table_2 rings, the grasp quaternion in a box of side 0.3 around the
+# top-down grasp (0, 1, 0, 0), the release point in a 0.2 x 0.4 x 0.6 m box
+# straddling Table 2's near edge and the obstacle, the release yaw within
+# +-0.15 rad of pi; headings anywhere, base speeds in [0.5, 1.5] m/s.
+PP_RING_1 = {"dim": 0, "center": [0.0, 0.0], "radius": [0.7, 1.1]}
+PP_RING_2 = {"dim": 8, "center": [3.0, 0.0], "radius": [0.7, 1.2]}
+
+
+def paper_setting(w, name, description):
+    pi = math.pi
+    w = json.loads(json.dumps(w))
+    w["name"] = name
+    w["description"] = description
+    lo = [0.0, 0.0, -pi, 0.5, -0.15, 0.85, -0.15, -0.15, 0.0, 0.0, -pi, 0.5, 2.5, -0.2, 0.45, pi - 0.15]
+    hi = [0.0, 0.0, pi, 1.5, 0.15, 1.15, 0.15, 0.15, 0.0, 0.0, pi, 1.5, 2.7, 0.2, 1.05, pi + 0.15]
+    w["cem"].update({"pop": 3000, "n_elite": 50, "iters": 20,
+                     "pop_schedule": {"final": 300, "iters": 10},
+                     "init_region": {"lo": lo, "hi": hi, "rings": [PP_RING_1, PP_RING_2]}})
+    return w
+
+
+def pickplace_paper():
+    return paper_setting(pickplace(), "pickplace_paper",
+                         "Pick-and-place over the ramp obstacle with the paper's algorithm setting: iteration 0 "
+                         "uniform in the parameter regions (rings around the tables, grasp and release boxes), "
+                         "n_env 3000 -> 300 linearly by iteration 10, 50 elites, 20 iterations")
+
+
+def pickplace_box():
+    w = paper_setting(pickplace(), "pickplace_box",
+                      "Pick-and-place with the box obstacle (Sec. IV-A setup 2: the obstacle without its slanted "
+                      "side, a rectangular prism on the ramp's footprint and up to its top edge) and the paper's "
+                      "algorithm setting")
+    boxes = w["scene"]["static_boxes"]
+    boxes[2] = {"name": "box", "center": [2.3, 0.0, 0.24], "half": [0.3, 0.5, 0.24]}
+    return w
+
+
 def movepush():
     # shelf 0.6 x 0.6 x 0.5 m at the origin; a 0.1 m, 0.3 kg block near its +x
     # edge; an open container (floor + 4 walls 0.3 m high, 0.4 x 0.4 m inside,
@@ -149,3 +193,5 @@ def write(w):
 if __name__ == "__main__":
     write(pickplace())
     write(movepush())
+    write(pickplace_paper())
+    write(pickplace_box())

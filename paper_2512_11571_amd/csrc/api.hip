@@ -45,6 +45,32 @@ int dim_of(int kind) {
 bool pos(float x) { return std::isfinite(x) && x > 0.0f; }
 bool nonneg(float x) { return std::isfinite(x) && x >= 0.0f; }
 
+// The iteration-0 region of a D-parameter problem: finite box bounds with
+// lo <= hi, rings on disjoint in-range pairs with 0 <= r0 <= r1.
+const char *check_region(const cem_init_region &R, int D) {
+  for (int d = 0; d < D; ++d)
+    if (!std::isfinite(R.lo[d]) || !std::isfinite(R.hi[d]) || !(R.lo[d] <= R.hi[d])) return "region box bound";
+  if (R.n_annuli < 0 || R.n_annuli > CEM_MAX_ANNULI) return "region ring count";
+  unsigned used = 0;
+  for (int k = 0; k < R.n_annuli; ++k) {
+    const int d = R.ann_dim[k];
+    if (d < 0 || d + 1 >= D) return "region ring dimension";
+    if (used & (3u << d)) return "region rings overlap";
+    used |= 3u << d;
+    const float r0 = R.ann_radius[k][0], r1 = R.ann_radius[k][1];
+    if (!std::isfinite(R.ann_center[k][0]) || !std::isfinite(R.ann_center[k][1]) || !std::isfinite(r1) ||
+        !(r0 >= 0.0f) || !(r0 <= r1))
+      return "region ring radii";
+  }
+  return nullptr;
+}
+
+int pop_at(const cem_ctx *c, int j) {
+  if (c->pop_final <= 0) return c->pop;
+  const long k = std::min(j, c->pop_ramp);
+  return c->pop - (int)(((long)(c->pop - c->pop_final) * k) / c->pop_ramp);
+}
+
 const char *check_scene(const cem_scene &s) {
   if (dim_of(s.kind) == 0) return "unknown scene kind";
   if (s.substeps < 1 || s.substeps > 1000) return "substeps out of range [1, 1000]";
@@ -201,6 +227,7 @@ int cem_sizeof(int which) {
     case 0: return (int)sizeof(cem_scene);
     case 1: return (int)sizeof(cem_problem);
     case 2: return (int)sizeof(cem_result);
+    case 3: return (int)sizeof(cem_init_region);
     default: return 0;
   }
 }
@@ -215,6 +242,9 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
   if (p->pop < 1 || p->pop > MAX_POP) return CEM_E_ARG;
   if (p->n_elite < 1 || p->n_elite > p->pop || p->n_elite > MAX_ELITE) return CEM_E_ARG;
   if (p->cov_mode != 0 && p->cov_mode != 1) return CEM_E_ARG;
+  if (p->pop_final != 0 && (p->pop_final < p->n_elite || p->pop_final > p->pop || p->pop_ramp_iters < 1))
+    return CEM_E_ARG;
+  if (p->init_region && check_region(*p->init_region, D)) return CEM_E_ARG;
 
   cem_ctx *c = new (std::nothrow) cem_ctx();
   if (!c) return CEM_E_ALLOC;
@@ -223,6 +253,8 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
   c->pop = p->pop;
   c->n_elite = p->n_elite;
   c->cov_mode = p->cov_mode;
+  c->pop_final = p->pop_final;
+  c->pop_ramp = p->pop_final ? p->pop_ramp_iters : 0;
   c->seed = p->seed;
   c->inst = p->instance;
   static std::atomic<uint64_t> next_serial{1};
@@ -253,6 +285,10 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
     h.inst_id = c->inst;
     h.pop = c->pop;
     h.scene = c->scene;
+    if (p->init_region) {
+      h.region = *p->init_region;
+      h.region_on = 1;
+    }
     if (hipMemcpyAsync(c->st, &h, sizeof h, hipMemcpyHostToDevice, c->own) != hipSuccess) {
       rc = fail(c, CEM_E_HIP, "state upload");
       break;
@@ -325,7 +361,19 @@ int plan_solve(cem_ctx *c, int32_t iters, cem_result *res, float *stats_host, vo
   HIPCHK(c, hipMemcpyAsync(&it0, &c->st->iter, sizeof it0, hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (it0 + iters > MAX_STATS_ITERS) return fail(c, CEM_E_ARG, "iteration counter would exceed 4096");
-  if (!c->iter_graph) {
+  if (c->pop_final > 0) {
+    // n_env schedule: each iteration launched with its own row count (the
+    // sampler reads the iteration from the device counter, which the refit
+    // advances)
+    for (int j = 0; j < iters; ++j) {
+      const int n = pop_at(c, it0 + j);
+      HIPCHK(c, launch_sample(c->seed, c->inst, -1, c->st, n, c->D, c->Z, s));
+      const int r = launch_rollout(c, c->Z, n, c->cost, c->tier, c->pose, nullptr, 0, s);
+      if (r != CEM_OK) return r;
+      HIPCHK(c, launch_select_refit(c->st, c->Z, c->cost, c->tier, n, nullptr, nullptr, c->stats, MAX_STATS_ITERS,
+                                    1, s));
+    }
+  } else if (!c->iter_graph) {
     // one CE iteration: sample (iteration read from the device counter) ->
     // rollout -> select/refit (advances the counter), captured once
     hipGraph_t g = nullptr;
@@ -346,7 +394,8 @@ int plan_solve(cem_ctx *c, int32_t iters, cem_result *res, float *stats_host, vo
       return hip_fail(c, e5, "hipGraphInstantiate");
     }
   }
-  for (int j = 0; j < iters; ++j) HIPCHK(c, hipGraphLaunch(c->iter_graph, s));
+  if (c->pop_final <= 0)
+    for (int j = 0; j < iters; ++j) HIPCHK(c, hipGraphLaunch(c->iter_graph, s));
   DevState h;
   HIPCHK(c, hipMemcpyAsync(&h, c->st, sizeof h, hipMemcpyDeviceToHost, s));
   if (stats_host && iters > 0)
@@ -391,6 +440,8 @@ int cem_get_factor(cem_ctx *c, double *L) {
   HIPCHK(c, hipStreamSynchronize(c->own));
   return CEM_OK;
 }
+
+int cem_pop_at(const cem_ctx *c, int32_t iter) { return (c && iter >= 0) ? pop_at(c, iter) : 0; }
 
 int cem_get_instance(cem_ctx *c, double *draws) {
   if (!c) return CEM_E_ARG;
@@ -526,7 +577,7 @@ int cem_batch_init(const cem_problem *problems, const int32_t *iters, int32_t n,
   *out = nullptr;
   if (!problems || !iters || n < 1 || n > 4096) return CEM_E_ARG;
   for (int i = 0; i < n; ++i)
-    if (iters[i] < 0 || iters[i] > MAX_STATS_ITERS) return CEM_E_ARG;
+    if (iters[i] < 0 || iters[i] > MAX_STATS_ITERS || problems[i].pop_final != 0) return CEM_E_ARG;
   cem_batch *b = new (std::nothrow) cem_batch();
   if (!b) return CEM_E_ALLOC;
   int rc = CEM_OK;

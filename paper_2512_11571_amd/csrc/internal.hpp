@@ -39,6 +39,8 @@ struct DevState {
   uint64_t seed;               // Philox key
   uint32_t inst_id;            // Philox counter word 3
   int32_t pop;
+  cem_init_region region;      // iteration-0 region (used when region_on)
+  int32_t region_on;
   cem_scene scene;             // device copy of the scene (read by the rollout kernels)
   SceneConsts sk;              // derived from scene by launch_scene_consts
   // Control steps the rollouts of this context have simulated (summed over
@@ -104,6 +106,7 @@ struct cem_ctx {
   uint8_t *tier = nullptr;
   hipStream_t own = nullptr;
   hipGraphExec_t iter_graph = nullptr;
+  int pop_final = 0, pop_ramp = 0;  // n_env schedule (pop_final 0: none)
   uint64_t serial = 0;  // unique per context in the process (host addresses are reused after cem_free)
   std::string err;
 };

@@ -92,10 +92,60 @@ __device__ __forceinline__ void sincos_2pi(float u, float &s, float &c) {
   c = q == 0 ? cx : (q == 1 ? -sx : (q == 2 ? -cx : sx));
 }
 
+// Iteration 0 from the region (Sec. III-B: uniform inside each parameter's
+// region): u_d is word d mod 4 of the CE-stream block d / 4; a ring pair
+// (d, d+1) takes its radius uniform in r^2 (uniform by area) from u_d and its
+// angle 2 pi u_{d+1}; every other dimension is uniform on [lo_d, hi_d].
+__device__ __forceinline__ void region_row(uint64_t seed, uint32_t inst, const cem_init_region &R, int D, int i,
+                                           float *__restrict__ Z) {
+  float u[MAX_D];
+#pragma unroll
+  for (int blk = 0; blk < MAX_D / 4; ++blk) {
+    u[blk * 4 + 0] = u[blk * 4 + 1] = u[blk * 4 + 2] = u[blk * 4 + 3] = 0.0f;
+    if (blk * 4 < D) {
+      const U4 w = draw(seed, 0u, (uint32_t)blk, (uint32_t)i, 0u, inst);
+      u[blk * 4 + 0] = unit(w.a);
+      u[blk * 4 + 1] = unit(w.b);
+      u[blk * 4 + 2] = unit(w.c);
+      u[blk * 4 + 3] = unit(w.d);
+    }
+  }
+  float z[MAX_D];
+#pragma unroll
+  for (int d = 0; d < MAX_D; ++d) z[d] = __builtin_fmaf(R.hi[d] - R.lo[d], u[d], R.lo[d]);
+  for (int k = 0; k < R.n_annuli; ++k) {
+    const int d = R.ann_dim[k];
+    const float r0 = R.ann_radius[k][0], r1 = R.ann_radius[k][1];
+    const float a0 = r0 * r0, a1 = r1 * r1;
+    float ud = 0.0f, ue = 0.0f;
+#pragma unroll
+    for (int e = 0; e < MAX_D; ++e) {
+      ud = e == d ? u[e] : ud;
+      ue = e == d + 1 ? u[e] : ue;
+    }
+    const float r = sqrtf(__builtin_fmaf(a1 - a0, ud, a0));
+    float sn, cs;
+    sincos_2pi(ue, sn, cs);
+    const float x = __builtin_fmaf(r, cs, R.ann_center[k][0]);
+    const float y = __builtin_fmaf(r, sn, R.ann_center[k][1]);
+#pragma unroll
+    for (int e = 0; e < MAX_D; ++e) {
+      z[e] = e == d ? x : z[e];
+      z[e] = e == d + 1 ? y : z[e];
+    }
+  }
+  float *row = Z + (long)i * D;
+  for (int d = 0; d < D; ++d) row[d] = z[d];
+}
+
 // One sample row: D normals from ceil(D/4) Philox blocks, then
 // z_d = fl32(mu_d + sum_{e<=d} L_de eps_e) in FP64, ascending e.
 __device__ __forceinline__ void sample_row(uint64_t seed, uint32_t inst, uint32_t iter,
                                            const DevState *__restrict__ st, int D, int i, float *__restrict__ Z) {
+  if (iter == 0 && st->region_on) {
+    region_row(seed, inst, st->region, D, i, Z);
+    return;
+  }
   float eps[MAX_D];
 #pragma unroll
   for (int blk = 0; blk < MAX_D / 4; ++blk) {
