@@ -350,7 +350,8 @@ def main():
         roll_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
         mu, S = c.get_theta()
 
-    full = sum(pops) * H
+    R = max(1, sc.get("domain_randomization", {}).get("scenarios", 1))
+    full = sum(pops) * H * R
     assert env_steps <= full, (env_steps, full)   # fewer only where rollouts stopped early or diverged
     value = env_steps / elapsed
     roll_avg_s = sum(roll_ms) / len(roll_ms) / 1e3
@@ -377,7 +378,7 @@ def main():
         "config": {"workload": a.workload, "pop": pop, "horizon": H, "substeps": sc["substeps"], "dim": D,
                    "n_elite": cem["n_elite"], "dt": sc["dt"], "seed": a.seed,
                    "settle_steps": sc.get("settle_steps", 0), "pop_schedule": sched,
-                   "init_region": bool(cem.get("init_region"))},
+                   "init_region": bool(cem.get("init_region")), "dr_scenarios": R},
         "env_steps_simulated": env_steps,
         "env_steps_full_horizon": full,
         "rollout_kernel_ms": roll_avg_s * 1e3,

@@ -50,6 +50,7 @@ enum { CEM_SCENE_PUSH = 1, CEM_SCENE_PICKPLACE = 2, CEM_SCENE_MOVEPUSH = 3 };
 #define CEM_MAX_STATIC 8
 #define CEM_MAX_D 16
 #define CEM_MAX_ANNULI 4
+#define CEM_MAX_DR 64
 #define CEM_STATS_COLS 8
 #define CEM_TRACE_FREE 13
 #define CEM_MAX_JOINTS 12
@@ -121,7 +122,18 @@ typedef struct cem_scene {
    * moving again afterwards can differ from the full-horizon result.  The
    * push scene ignores it. */
   int32_t settle_steps;
-  int32_t reserved_scene;
+  /* Domain randomisation (Sec. IV-C: plans made robust to bounded uncertainty
+   * in friction or mass).  dr_scenarios R in {0, 1}: off.  R in {2, 4, ..., 64}
+   * (robot scenes): every parameter row is rolled out under R scenarios.
+   * Scenario r draws the object's friction U[dr_mu_lo, dr_mu_hi] (when
+   * dr_mu_hi > 0; else the instance's value) and its mass U[dr_mass_lo,
+   * dr_mass_hi] (when dr_mass_hi > 0; else obj_mass) from the scene stream
+   * (block 1, sample r, iteration 0): the same R scenarios for every row and
+   * iteration of an instance.  A row's tier is the worst over its scenarios,
+   * its cost the mean (dr_reduce 0) or the maximum (1), its pose scenario 0's.
+   * rollout_trace rejects such scenes. */
+  int32_t dr_scenarios, dr_reduce;
+  float dr_mu_lo, dr_mu_hi, dr_mass_lo, dr_mass_hi;
 } cem_scene;
 
 /* Initial distribution phi(theta^0) as a region (Sec. III-B: iteration 0
@@ -248,6 +260,10 @@ int cem_pop_at(const cem_ctx *c, int32_t iter);
  * host draws[3] = (goal x, goal y, object friction coefficient or 0 when the
  * scene does not draw one). Synchronous. */
 int cem_get_instance(cem_ctx *c, double *draws);
+/* The instance's domain-randomisation scenarios (scene dr_*): host
+ * mu[CEM_MAX_DR], mass[CEM_MAX_DR] get each scenario's object friction and
+ * mass as drawn (0 where the scene draws none).  Synchronous. */
+int cem_get_scenarios(cem_ctx *c, float *mu, float *mass);
 /* Control steps simulated by this context's rollouts since cem_init, summed
  * over environments: T per rollout, fewer for one that stopped early or
  * diverged.  Batched runs count into each instance's context.  Waits for all

@@ -29,7 +29,7 @@ def count(name, rows=64):
     mu0 = np.asarray(cem["mu0"], np.float64)
     L, _ = O.factor_cov(np.diag(np.asarray(cem["cov0_diag"], np.float64)))
     n = min(rows, cem["pop"])
-    Z = O.sample(0, 0, 0, n, mu0, L)
+    Z = O.sample_region(w, 0, 0, n) if cem.get("init_region") else O.sample(0, 0, 0, n, mu0, L)
     H = w["scene"]["horizon"]
     tallies = [O.count_ops(w, 0, Z[i]) for i in range(n)]
     per_step = {k: float(np.mean([t[k] for t in tallies])) / H for k in tallies[0]}

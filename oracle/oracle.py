@@ -45,7 +45,8 @@ class RefScene(ctypes.Structure):
         ("goal_static", _i), ("joint_speed_max", _d), ("accel_max", _d),
         ("push_vmin", _d), ("push_vmax", _d), ("push_dmax", _d), ("timeout_push", _d),
         ("obj_mu_lo", _d), ("obj_mu_hi", _d), ("goal_box_center", _d * 3), ("goal_box_half", _d * 3),
-        ("settle_steps", _i),
+        ("settle_steps", _i), ("dr_scenarios", _i), ("dr_reduce", _i),
+        ("dr_mu_lo", _d), ("dr_mu_hi", _d), ("dr_mass_lo", _d), ("dr_mass_hi", _d),
     ]
 
 
@@ -102,6 +103,7 @@ def lib():
                                      vp, vp, ctypes.c_int, vp, vp]
         L.ref_sample_region.argtypes = [u64, u32, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp]
         L.ref_n_env_at.argtypes = [ctypes.c_int] * 4
+        L.ref_scenarios.argtypes = [P(RefScene), u64, u32, ctypes.c_int, vp, vp]
         L.ref_tree_aba.argtypes = [P(Tree), vp, vp, vp, vp, ctypes.c_double, vp]
         L.ref_tree_rnea.argtypes = [P(Tree), vp, vp, vp, vp, ctypes.c_double, vp]
         L.ref_tree_crba.argtypes = [P(Tree), vp, vp]
@@ -204,6 +206,12 @@ def make_scene(workload):
                 s.goal_box_half[k] = gb["half"][k]
     s.obj_mu_lo, s.obj_mu_hi = ob.get("mu", (0.0, 0.0))
     s.settle_steps = sc.get("settle_steps", 0)
+    dr = sc.get("domain_randomization")
+    if dr:
+        s.dr_scenarios = int(dr["scenarios"])
+        s.dr_reduce = {"mean": 0, "max": 1}[dr.get("reduce", "mean")]
+        s.dr_mu_lo, s.dr_mu_hi = dr.get("mu", (0.0, 0.0))
+        s.dr_mass_lo, s.dr_mass_hi = dr.get("mass", (0.0, 0.0))
     return s
 
 
@@ -283,6 +291,15 @@ def n_env_at(workload, j):
     cem = workload["cem"]
     sch = cem.get("pop_schedule") or {"final": 0, "iters": 1}
     return int(lib().ref_n_env_at(cem["pop"], sch["final"], sch["iters"], j))
+
+
+def scenarios(workload, seed, inst=0, n=64):
+    """Domain-randomisation scenarios: (friction[n], mass[n]), 0 where the scene draws none."""
+    s = make_scene(workload)
+    mu = np.zeros(n, np.float64)
+    mass = np.zeros(n, np.float64)
+    lib().ref_scenarios(ctypes.byref(s), seed, inst, n, _ptr(mu), _ptr(mass))
+    return mu, mass
 
 
 def draw_instance(workload, seed, inst=0):

@@ -122,6 +122,31 @@ int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const 
   const Instance in = draw_instance(*s, seed, inst);
   if (s->kind != SCENE_PUSH && s->kind != SCENE_PICKPLACE && s->kind != SCENE_MOVEPUSH) return 1;
   const int tw = s->kind == SCENE_PUSH ? TRACE_FREE : TRACE_ROBOT;
+  const int R = (s->kind != SCENE_PUSH && s->dr_scenarios > 1) ? s->dr_scenarios : 1;
+  if (R > 1) {
+    // domain randomisation: every row under each of the R scenarios; the
+    // worst tier, the mean or maximum cost, scenario 0's pose, the steps summed
+    if (trace) return 1;
+    std::vector<Instance> scen(R);
+    for (int r = 0; r < R; ++r) scen[r] = scenario_of(*s, in, seed, inst, r);
+    parallel_for(pop, threads, [&](int i) {
+      double c_sum = 0.0, c_max = -INFINITY;
+      int t_max = 0, n_steps = 0;
+      for (int r = 0; r < R; ++r) {
+        RolloutOut o = rollout_one(*s, scen[r], Z + (long)i * D, nullptr, 0);
+        c_sum += o.cost;
+        c_max = std::max(c_max, o.cost);
+        t_max = std::max(t_max, o.tier);
+        n_steps += o.steps;
+        if (r == 0 && pose)
+          for (int c = 0; c < 7; ++c) pose[(long)i * 7 + c] = o.pose[c];
+      }
+      cost[i] = s->dr_reduce ? c_max : c_sum / R;
+      tier[i] = (uint8_t)t_max;
+      if (steps) steps[i] = n_steps;
+    });
+    return 0;
+  }
   parallel_for(pop, threads, [&](int i) {
     RolloutOut o = rollout_one(*s, in, Z + (long)i * D, trace ? trace + (long)i * trace_steps * tw : nullptr,
                                trace_steps);
@@ -132,6 +157,17 @@ int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const 
     if (steps) steps[i] = o.steps;
   });
   return 0;
+}
+
+// Domain-randomisation scenarios of instance inst: friction and mass per
+// scenario (0 where the scene draws none).
+void ref_scenarios(const RefScene *s, uint64_t seed, uint32_t inst, int n, double *mu, double *mass) {
+  const Instance in = draw_instance(*s, seed, inst);
+  for (int r = 0; r < n; ++r) {
+    const Instance sc = scenario_of(*s, in, seed, inst, r);
+    mu[r] = s->dr_mu_hi > 0.0 ? sc.obj_mu : 0.0;
+    mass[r] = s->dr_mass_hi > 0.0 ? sc.obj_mass : 0.0;
+  }
 }
 
 // Operation tally of one rollout of parameter row z: add, mul, fma, div, sqrt, trans.

@@ -187,7 +187,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
   const T k = T(s.k_contact), damp = T(s.c_contact), eps_v = T(s.eps_v);
   const T wc = T(s.omega_c), zeta = T(s.zeta);
   const V3<T> ohe(T(s.obj_half[0]), T(s.obj_half[1]), T(s.obj_half[2]));
-  const T om = T(s.obj_mass);
+  const T om = T(inst.obj_mass > 0.0 ? inst.obj_mass : s.obj_mass);
   const V3<T> oIb(om * (ohe.y * ohe.y + ohe.z * ohe.z) / T(3.0), om * (ohe.x * ohe.x + ohe.z * ohe.z) / T(3.0),
                   om * (ohe.x * ohe.x + ohe.y * ohe.y) / T(3.0));
   const V3<T> gv(T(0.0), T(0.0), -g);

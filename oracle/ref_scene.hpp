@@ -56,6 +56,11 @@ struct RefScene {
   // early stop of a robot rollout (0 = off): once every action has ended, stop
   // after this many consecutive control steps with the object at rest
   int32_t settle_steps;
+  // domain randomisation (Sec. IV-C): R scenarios per parameter row (<= 1 off),
+  // each with its own object friction / mass draw; the row's tier is the worst
+  // and its cost the mean (dr_reduce 0) or maximum (1) over scenarios
+  int32_t dr_scenarios, dr_reduce;
+  double dr_mu_lo, dr_mu_hi, dr_mass_lo, dr_mass_hi;
 };
 
 // Per-instance draws (scene stream 1, sample 0, iteration 0, instance b), one
@@ -67,6 +72,7 @@ struct RefScene {
 struct Instance {
   double goal[2];
   double obj_mu;
+  double obj_mass = 0.0;  // 0: the scene's
 };
 
 inline Instance draw_instance(const RefScene &s, uint64_t seed, uint32_t b) {
@@ -79,6 +85,19 @@ inline Instance draw_instance(const RefScene &s, uint64_t seed, uint32_t b) {
   in.goal[0] = s.obj_pos0[0] + rho * std::cos(phi);
   in.goal[1] = s.obj_pos0[1] + rho * std::sin(phi);
   in.obj_mu = s.obj_mu_hi > 0.0 ? s.obj_mu_lo + (s.obj_mu_hi - s.obj_mu_lo) * (double)u01(x.w[2]) : 0.0;
+  return in;
+}
+
+// Domain-randomisation scenario r of instance b (scene stream 1, block 1,
+// sample r, iteration 0, instance b): the object's friction ~ U[dr_mu_lo,
+// dr_mu_hi] from word 0 when dr_mu_hi > 0 (else the instance's draw stands)
+// and its mass ~ U[dr_mass_lo, dr_mass_hi] from word 1 when dr_mass_hi > 0
+// (else the scene's mass).
+inline Instance scenario_of(const RefScene &s, const Instance &base, uint64_t seed, uint32_t b, int r) {
+  Instance in = base;
+  Word4 x = philox_draw(seed, STREAM_SCENE, 1, (uint32_t)r, 0, b);
+  if (s.dr_mu_hi > 0.0) in.obj_mu = s.dr_mu_lo + (s.dr_mu_hi - s.dr_mu_lo) * (double)u01(x.w[0]);
+  if (s.dr_mass_hi > 0.0) in.obj_mass = s.dr_mass_lo + (s.dr_mass_hi - s.dr_mass_lo) * (double)u01(x.w[1]);
   return in;
 }
 

@@ -21,6 +21,7 @@ DIM = {"push": 3, "pickplace": 16, "movepush": 12}
 MAX_STATIC = 8
 MAX_D = 16
 MAX_ANNULI = 4
+MAX_DR = 64
 MAX_JOINTS = 12
 STATS_COLS = 8
 TRACE_FREE = 13
@@ -59,7 +60,8 @@ class CemScene(ctypes.Structure):
         ("goal_static", _i), ("joint_speed_max", _f), ("accel_max", _f),
         ("push_vmin", _f), ("push_vmax", _f), ("push_dmax", _f), ("timeout_push", _f),
         ("obj_mu_lo", _f), ("obj_mu_hi", _f), ("goal_box_center", _f * 3), ("goal_box_half", _f * 3),
-        ("settle_steps", _i), ("reserved_scene", _i),
+        ("settle_steps", _i), ("dr_scenarios", _i), ("dr_reduce", _i),
+        ("dr_mu_lo", _f), ("dr_mu_hi", _f), ("dr_mass_lo", _f), ("dr_mass_hi", _f),
     ]
 
 
@@ -90,7 +92,7 @@ class CemResult(ctypes.Structure):
 
 EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem_last_error", "cem_sample", "rollout_batch",
            "rollout_trace", "cem_refit", "plan_solve", "cem_get_theta", "cem_set_theta", "cem_get_factor",
-           "cem_get_instance", "cem_env_steps", "cem_pop_at", "cem_reset", "cem_batch_init", "cem_batch_free", "cem_batch_size",
+           "cem_get_instance", "cem_get_scenarios", "cem_env_steps", "cem_pop_at", "cem_reset", "cem_batch_init", "cem_batch_free", "cem_batch_size",
            "cem_batch_last_error", "cem_batch_instance", "cem_batch_autotune", "cem_batch_step", "cem_batch_solve",
            "cem_batch_record", "cem_mlp_init", "cem_mlp_free", "cem_mlp_n_params", "cem_mlp_last_error",
            "cem_mlp_get_params", "cem_mlp_set_params", "cem_mlp_get_norm", "cem_mlp_set_norm", "cem_mlp_fit_norm",
@@ -127,6 +129,7 @@ def lib():
         L.cem_get_instance.argtypes = [vp, vp]
         L.cem_env_steps.argtypes = [vp, P(ctypes.c_uint64)]
         L.cem_pop_at.argtypes = [vp, _i]
+        L.cem_get_scenarios.argtypes = [vp, vp, vp]
         L.cem_reset.argtypes = [vp]
         L.cem_sizeof.argtypes = [ctypes.c_int]
         L.cem_batch_init.argtypes = [vp, vp, _i, P(vp)]
@@ -235,6 +238,12 @@ def make_scene(workload):
                 s.goal_box_half[k] = gb["half"][k]
     s.obj_mu_lo, s.obj_mu_hi = ob.get("mu", (0.0, 0.0))
     s.settle_steps = int(sc.get("settle_steps", 0))
+    dr = sc.get("domain_randomization")
+    if dr:
+        s.dr_scenarios = int(dr["scenarios"])
+        s.dr_reduce = {"mean": 0, "max": 1}[dr.get("reduce", "mean")]
+        s.dr_mu_lo, s.dr_mu_hi = dr.get("mu", (0.0, 0.0))
+        s.dr_mass_lo, s.dr_mass_hi = dr.get("mass", (0.0, 0.0))
     return s
 
 
@@ -397,6 +406,13 @@ class Context:
         g = np.zeros(3)
         self._check(lib().cem_get_instance(self.h, _np_ptr(g)))
         return g
+
+    def get_scenarios(self):
+        """Domain-randomisation scenarios: (friction[64], mass[64]) as drawn (0 where none)."""
+        mu = np.zeros(MAX_DR, np.float32)
+        mass = np.zeros(MAX_DR, np.float32)
+        self._check(lib().cem_get_scenarios(self.h, _np_ptr(mu), _np_ptr(mass)))
+        return mu, mass
 
     def pop_at(self, it):
         """n_env(it) of the problem's schedule (its pop when it has none)."""

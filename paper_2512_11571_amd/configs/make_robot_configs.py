@@ -1,5 +1,6 @@
 """Writes the mobile-manipulator workloads (pickplace.json, movepush.json, and
-the paper-setting variants pickplace_paper.json, pickplace_box.json).
+the paper-setting variants pickplace_paper.json, pickplace_box.json, and the
+domain-randomised movepush_dr.json).
 
 All use the same synthetic 11-joint robot: a holonomic base (x and y
 prismatic joints on massless bodies, then yaw), a six-joint arm and two
@@ -178,6 +179,19 @@ def movepush():
     }
 
 
+def movepush_dr():
+    # Sec. IV-C: plans made robust to bounded uncertainty in friction or mass;
+    # every candidate is scored by its mean cost over 8 scenarios whose block
+    # friction and mass are drawn per instance
+    w = movepush()
+    w["name"] = "movepush_dr"
+    w["description"] = ("Move-and-push with domain randomisation: each parameter row rolled out under 8 scenarios "
+                        "(block friction U[0.3, 0.7], mass U[0.2, 0.4] kg), cost the mean, tier the worst; "
+                        "pop 8192 (65,536 rollouts per iteration), 256 elites, 15 iterations")
+    w["scene"]["domain_randomization"] = {"scenarios": 8, "reduce": "mean", "mu": [0.3, 0.7], "mass": [0.2, 0.4]}
+    return w
+
+
 def write(w):
     path = os.path.join(HERE, w["name"] + ".json")
     if os.path.exists(path):
@@ -195,3 +209,4 @@ if __name__ == "__main__":
     write(movepush())
     write(pickplace_paper())
     write(pickplace_box())
+    write(movepush_dr())

@@ -76,6 +76,15 @@ const char *check_scene(const cem_scene &s) {
   if (s.substeps < 1 || s.substeps > 1000) return "substeps out of range [1, 1000]";
   if (s.horizon < 1 || s.horizon > 100000) return "horizon out of range [1, 100000]";
   if (s.settle_steps < 0 || s.settle_steps > s.horizon) return "settle_steps out of range [0, horizon]";
+  if (s.dr_scenarios < 0 || s.dr_scenarios > CEM_MAX_DR || (s.dr_scenarios & (s.dr_scenarios - 1)))
+    return "dr_scenarios must be 0 or a power of two <= 64";
+  if (s.dr_scenarios > 1 && s.kind == CEM_SCENE_PUSH) return "domain randomisation needs a robot scene";
+  if (s.dr_reduce != 0 && s.dr_reduce != 1) return "dr_reduce must be 0 (mean) or 1 (max)";
+  if (!nonneg(s.dr_mu_lo) || !nonneg(s.dr_mu_hi) || (s.dr_mu_hi > 0.0f && !(s.dr_mu_lo <= s.dr_mu_hi)))
+    return "invalid dr friction range";
+  if (!nonneg(s.dr_mass_lo) || !nonneg(s.dr_mass_hi) ||
+      (s.dr_mass_hi > 0.0f && !(s.dr_mass_lo > 0.0f && s.dr_mass_lo <= s.dr_mass_hi)))
+    return "invalid dr mass range";
   if (!pos(s.dt) || !nonneg(s.gravity) || !nonneg(s.k_contact) || !nonneg(s.c_contact) || !pos(s.eps_v))
     return "invalid physical constants";
   if (!nonneg(s.mu_ground) || !nonneg(s.mu_tool) || !nonneg(s.mu_static) || !nonneg(s.mu_ramp))
@@ -138,6 +147,7 @@ InstDesc desc_of(cem_ctx *c, const float *Z, int pop, float *cost, uint8_t *tier
   d.pop = pop;
   d.D = c->D;
   d.iters = 1 << 30;
+  d.scen = scenarios(c->scene);
   return d;
 }
 
@@ -339,6 +349,7 @@ int rollout_trace(cem_ctx *c, const float *Z_dev, int32_t pop, int32_t n_steps, 
   if (!Z_dev || !trace_dev) return fail(c, CEM_E_ARG, "null buffer");
   if (pop < 0 || pop > MAX_POP) return fail(c, CEM_E_ARG, "pop out of range [0, 65536]");
   if (n_steps < 1 || n_steps > c->scene.horizon) return fail(c, CEM_E_ARG, "n_steps out of range [1, horizon]");
+  if (scenarios(c->scene) > 1) return fail(c, CEM_E_ARG, "traces are per environment: no domain randomisation");
   if (pop == 0) return CEM_OK;
   return launch_rollout(c, Z_dev, pop, nullptr, nullptr, nullptr, trace_dev, n_steps, (hipStream_t)stream);
 }
@@ -454,6 +465,15 @@ int cem_get_instance(cem_ctx *c, double *draws) {
   return CEM_OK;
 }
 
+int cem_get_scenarios(cem_ctx *c, float *mu, float *mass) {
+  if (!c) return CEM_E_ARG;
+  if (!mu || !mass) return fail(c, CEM_E_ARG, "null output");
+  HIPCHK(c, hipMemcpyAsync(mu, c->st->dr_mu, sizeof(float) * CEM_MAX_DR, hipMemcpyDeviceToHost, c->own));
+  HIPCHK(c, hipMemcpyAsync(mass, c->st->dr_mass, sizeof(float) * CEM_MAX_DR, hipMemcpyDeviceToHost, c->own));
+  HIPCHK(c, hipStreamSynchronize(c->own));
+  return CEM_OK;
+}
+
 int cem_env_steps(cem_ctx *c, uint64_t *steps) {
   if (!c) return CEM_E_ARG;
   if (!steps) return fail(c, CEM_E_ARG, "null output");
@@ -512,11 +532,13 @@ int build_items(cem_batch *b, int envs) {
     const cem_ctx *c = b->ctx[i];
     const double weight = c->scene.kind == CEM_SCENE_PUSH ? 1.0 : 28.0;
     const double per_env = (double)c->scene.horizon * c->scene.substeps * weight;
-    for (int e0 = 0; e0 < c->pop; e0 += envs) {
+    // a row's scenarios (a power of two <= 64) never straddle two items
+    const int R = scenarios(c->scene), step = std::max(envs, R), n_env = c->pop * R;
+    for (int e0 = 0; e0 < n_env; e0 += step) {
       Key k;
       k.w.inst = i;
       k.w.env0 = e0;
-      k.w.n = std::min(envs, c->pop - e0);
+      k.w.n = std::min(step, n_env - e0);
       k.w.pad = 0;
       k.cost = per_env;
       keys.push_back(k);

@@ -29,6 +29,8 @@ struct DevState {
   double cov0[MAX_D * MAX_D];  // initial covariance (its diagonal feeds the single-elite noise)
   double goal[2];              // per-instance draw: the push goal
   float obj_mu;                // per-instance draw: the object's friction (0: per-class values)
+  float dr_mu[CEM_MAX_DR];     // domain-randomisation scenarios: object friction and mass
+  float dr_mass[CEM_MAX_DR];
   int32_t iter;                // CE iteration counter for the replayed iteration
   int32_t D, cov_mode, n_elite;
   float best_z[MAX_D];
@@ -58,11 +60,15 @@ struct InstDesc {
   float *pose;      // pop x 7, nullable
   float *stats;     // iteration stats rows (batched refit), nullable
   int32_t kind, pop, D, iters;  // iters: iteration cap in batched runs
+  int32_t scen, pad;            // scenarios per row (1: no domain randomisation); pop * scen environments
 };
 // Up to 64 environments [env0, env0 + n) of instance `inst`.
 struct WorkItem {
   int32_t inst, env0, n, pad;
 };
+
+// Domain-randomisation scenarios per parameter row (1: none).
+inline int scenarios(const cem_scene &s) { return s.dr_scenarios > 1 ? s.dr_scenarios : 1; }
 
 // Read-only views for the device code.  The scene, its derived constants and
 // the rest of a context's state do not change while a rollout runs; reading

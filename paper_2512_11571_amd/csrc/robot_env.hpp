@@ -92,21 +92,26 @@ __device__ __forceinline__ void c_put(const Lds &L, int j, SV c) {
 // Joint reference row (both fingers share one).
 __device__ __forceinline__ int qref_row(int j) { return R_QREF + (j < FL ? j : FL); }
 
+// Outcome of one rollout: Problem 2's cost and tier, the object's final pose
+// (p, q) and the control steps simulated (T, or fewer after an early stop or
+// a divergence).
+struct EnvOut {
+  float cost;
+  int tier, steps;
+  float pose[7];
+};
+
 // Rolls out row `env` of Z (16 parameters for pick-and-place, 12 for
-// move-push) and writes its cost, tier, pose and (TRACE) per-step trace.
+// move-push) with the object's friction `mu_obj` (0: the per-class
+// coefficients) and mass `om`, and (TRACE) writes its per-step trace.
 // `lds_mem` is the block's R_ROWS x PP_LANES float array and `lane` this
-// lane's column in it.  The scene, its derived constants and the instance's
-// object friction draw (0: the per-class coefficients) come from `st`.
-// Returns the control steps simulated: T, or fewer after an early stop
-// (scene settle_steps > 0) or a divergence.
+// lane's column in it.  The scene and its derived constants come from `st`.
 template <bool TRACE>
-__device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict__ Z, long env,
-                                          float *lds_mem, int lane, float *__restrict__ cost_out,
-                                          uint8_t *__restrict__ tier_out, float *__restrict__ pose_out,
-                                          float *__restrict__ trace, int trace_steps) {
+__device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restrict__ Z, long env, float mu_obj,
+                                             float om, float *lds_mem, int lane, float *__restrict__ trace,
+                                             int trace_steps) {
   CScene &sc = st->scene;
   CConsts &sk = st->sk;
-  const float mu_obj = st->obj_mu;
   const Lds L{lds_mem, lane};
   const bool pnp = sc.kind == CEM_SCENE_PICKPLACE;
   const int n_act = pnp ? 4 : 2, n_par = pnp ? 16 : 12;
@@ -118,7 +123,7 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
   const float kc = sc.k_contact, damp = sc.c_contact, eps2 = sc.eps_v * sc.eps_v;
   const float wc = sc.omega_c, zeta = sc.zeta;
   const V3f ohe = v3(sc.obj_half[0], sc.obj_half[1], sc.obj_half[2]);
-  const float om = sc.obj_mass, inv_om = 1.0f / om;
+  const float inv_om = 1.0f / om;
   const V3f oIb = v3(om * (ohe.y * ohe.y + ohe.z * ohe.z) / 3.0f, om * (ohe.x * ohe.x + ohe.z * ohe.z) / 3.0f,
                      om * (ohe.x * ohe.x + ohe.y * ohe.y) / 3.0f);
   const V3f gv = v3(0.0f, 0.0f, -g);
@@ -615,13 +620,13 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
   fin = fin && fabsf(ob.p.x) < 1e3f && fabsf(ob.p.y) < 1e3f && fabsf(ob.p.z) < 1e3f;
   const bool all_ok = ok_bits == (1u << n_act) - 1u;
   const int tier = !fin ? 3 : (all_ok ? (goal ? 0 : 1) : 2);
-  const float cost = fin ? sc.time_weight * dt * (float)unsuccessful : __int_as_float(0x7F800000);
-  if (cost_out) cost_out[env] = cost;
-  if (tier_out) tier_out[env] = (uint8_t)tier;
-  if (pose_out)
+  EnvOut out;
+  out.cost = fin ? sc.time_weight * dt * (float)unsuccessful : __int_as_float(0x7F800000);
+  out.tier = tier;
+  out.steps = steps;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) pose_out[(long)env * 7 + i] = pose[i];
-  return steps;
+  for (int i = 0; i < 7; ++i) out.pose[i] = pose[i];
+  return out;
 }
 
 }  // namespace

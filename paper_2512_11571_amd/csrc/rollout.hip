@@ -44,23 +44,53 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
       d.kind = di.kind;
       d.pop = di.pop;
       d.iters = di.iters;
+      d.scen = di.scen;
       env0 = w.env0;
       n = w.n;
     } else {
       d = single;
       env0 = it * 64;
-      n = min(64, d.pop - env0);
+      n = min(64, d.pop * d.scen - env0);
     }
     CDevState *st = (CDevState *)d.st;
     const bool active = !(check_iter && st->iter >= d.iters);  // wave-uniform
+    const bool robot = d.kind != CEM_SCENE_PUSH;                // wave-uniform
+    const int R = d.scen;  // scenarios per row: a power of two <= 64, aligned to the item (wave-uniform)
     int steps = 0;
+    EnvOut o{0.0f, 0, 0, {0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f}};
+    const long env = env0 + lane, row = env / R;
     if (active && lane < n) {
-      const long env = env0 + lane;
-      if (d.kind == CEM_SCENE_PUSH) {
+      if (!robot) {
         push_env<TRACE>(st->scene, st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
         steps = st->scene.horizon;
       } else {
-        steps = robot_env<TRACE>(st, d.Z, env, lds, lane, d.cost, d.tier, d.pose, trace, trace_steps);
+        float mu = st->obj_mu, m = st->scene.obj_mass;
+        if (R > 1) {
+          const int r = (int)(env & (R - 1));
+          if (st->scene.dr_mu_hi > 0.0f) mu = st->dr_mu[r];
+          if (st->scene.dr_mass_hi > 0.0f) m = st->dr_mass[r];
+        }
+        o = robot_env<TRACE>(st, d.Z, row, mu, m, lds, lane, trace, trace_steps);
+        steps = o.steps;
+      }
+    }
+    if (active && robot) {
+      // a row's scenarios sit in R adjacent lanes: the worst tier, and the
+      // mean or the largest cost, by a fixed butterfly over the group
+      const bool use_max = st->scene.dr_reduce != 0;
+      for (int m = 1; m < R; m <<= 1) {
+        const float oc = __shfl_xor(o.cost, m);
+        const int ot = __shfl_xor(o.tier, m);
+        o.cost = use_max ? fmaxf(o.cost, oc) : o.cost + oc;
+        o.tier = max(o.tier, ot);
+      }
+      if (R > 1 && !use_max) o.cost = o.cost * (1.0f / (float)R);
+      if (lane < n && (env & (R - 1)) == 0) {
+        if (d.cost) d.cost[row] = o.cost;
+        if (d.tier) d.tier[row] = (uint8_t)o.tier;
+        if (d.pose)
+#pragma unroll
+          for (int i = 0; i < 7; ++i) d.pose[row * 7 + i] = o.pose[i];
       }
     }
     if (active) {
@@ -135,7 +165,8 @@ __global__ void pack_dataset_kernel(const float *__restrict__ Z, const float *__
 }  // namespace
 
 hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s) {
-  const int n_items = (d.pop + 63) / 64;
+  if (d.scen < 1 || d.scen > 64 || (d.scen & (d.scen - 1))) return hipErrorInvalidValue;
+  const int n_items = (d.pop * d.scen + 63) / 64;
   if (n_items == 0) return hipSuccess;
   if (trace)
     hipLaunchKernelGGL(rollout_items_kernel<true>, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items,

@@ -223,7 +223,20 @@ __global__ void __launch_bounds__(256) mlp_init_kernel(uint64_t seed, InitLayers
 // (words 0, 1), and the object's friction coefficient U[obj_mu_lo, obj_mu_hi]
 // when obj_mu_hi > 0 (word 2).
 __global__ void instance_draw_kernel(cem_scene sc, uint64_t seed, uint32_t inst, DevState *st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int t = threadIdx.x;
+  if (blockIdx.x != 0) return;
+  if (t < CEM_MAX_DR) {
+    // domain-randomisation scenario t: object friction (word 0) and mass (word 1)
+    const U4 v = draw(seed, 1u, 1u, (uint32_t)t, 0u, inst);
+    st->dr_mu[t] = sc.dr_mu_hi > 0.0f
+                       ? (float)((double)sc.dr_mu_lo + ((double)sc.dr_mu_hi - (double)sc.dr_mu_lo) * (double)unit(v.a))
+                       : 0.0f;
+    st->dr_mass[t] =
+        sc.dr_mass_hi > 0.0f
+            ? (float)((double)sc.dr_mass_lo + ((double)sc.dr_mass_hi - (double)sc.dr_mass_lo) * (double)unit(v.b))
+            : 0.0f;
+  }
+  if (t != 0) return;
   const U4 w = draw(seed, 1u, 0u, 0u, 0u, inst);
   const double u0 = (double)unit(w.a), u1 = (double)unit(w.b);
   const double rho = (double)sc.goal_rho_lo + ((double)sc.goal_rho_hi - (double)sc.goal_rho_lo) * u0;

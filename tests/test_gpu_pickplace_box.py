@@ -1,0 +1,104 @@
+"""GPU parity of pick-and-place with the box obstacle (Sec. IV-A setup 2) and
+the paper's algorithm setting, against the FP64 oracle through the C ABI.
+
+Tolerances as for the ramp scene: FP32 joint angles / object position within
+1e-3 over the first 100 control steps on rows the oracle certifies as
+non-chaotic; over the full horizon, tier and cost on certified rows (cost to
+within two control steps).  The rows: iteration-0 rows of the region and
+Gaussian rows around the ramp plan and around a plan that passes the obstacle
+on its +y side, so that all of psi_g's outcomes occur.  Statistical: the
+median best cost of plan_solve with the region and a reduced schedule over 32
+seeds within 1e-2 relative.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from paper_2512_11571_amd import workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+AROUND = [0.06, 0.93, -2.03, 0.9, 0.11, 0.88, -0.04, 0.03, 2.99, 0.8, -2.18, 1.5, 2.59, 0.19, 0.52, 3.4]
+
+
+@pytest.fixture(scope="module")
+def box():
+    return workloads.load("pickplace_box")
+
+
+@pytest.fixture(scope="module")
+def Context():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_2512_11571_amd.binding import Context
+    return Context
+
+
+def _rows(oracle, w, seed, n):
+    """n/4 region rows, then Gaussian rows around the ramp plan and the +y plan."""
+    cem = w["cem"]
+    reg = oracle.sample_region(w, seed, 0, n // 4)
+    L, _ = oracle.factor_cov(np.diag(cem["cov0_diag"]) * 0.05)
+    m = (n - n // 4) // 2
+    a = oracle.sample(seed, 1, 0, m, np.asarray(workloads.load("pickplace")["cem"]["mu0"], np.float64), L)
+    b = oracle.sample(seed, 2, 0, n - n // 4 - m, np.asarray(AROUND, np.float64), L)
+    return np.concatenate([reg, a, b])
+
+
+def _gpu_rollout(Context, w, Z, trace_steps=0):
+    n = Z.shape[0]
+    w = copy.deepcopy(w)
+    w["cem"].pop("pop_schedule")
+    with Context(w, pop=max(n, 64), n_elite=1) as c:
+        Zd = torch.from_numpy(np.ascontiguousarray(Z)).to("cuda:0")
+        if trace_steps:
+            tr = torch.empty((n, trace_steps, 35), dtype=torch.float32, device="cuda:0")
+            c.rollout_trace(Zd, trace_steps, tr)
+            torch.cuda.synchronize()
+            return tr.cpu().numpy().astype(np.float64)
+        cost = torch.empty(n, dtype=torch.float32, device="cuda:0")
+        tier = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        c.rollout_batch(Zd, cost, tier)
+        torch.cuda.synchronize()
+        return cost.cpu().numpy().astype(np.float64), tier.cpu().numpy()
+
+
+def test_trace_parity_first_100_steps(oracle, box, Context):
+    Z = _rows(oracle, box, 0, 64)
+    _, _, _, t0 = oracle.rollout(box, 0, Z, trace_steps=100)
+    _, _, _, t1 = oracle.rollout(box, 0, np.nextafter(Z, np.float32(np.inf)).astype(np.float32), trace_steps=100)
+    ok = np.max(np.abs(t0 - t1)[:, :, list(range(7)) + list(range(13, 24))], axis=(1, 2)) < 1e-4
+    assert ok.sum() >= 32
+    tg = _gpu_rollout(Context, box, Z[ok], trace_steps=100)
+    ref = t0[ok]
+    assert np.max(np.abs(tg[:, :, 13:24] - ref[:, :, 13:24])) < 1e-3
+    assert np.max(np.abs(tg[:, :, 0:3] - ref[:, :, 0:3])) < 1e-3
+
+
+def test_full_horizon_cost_and_tier_parity(oracle, box, Context):
+    Z = _rows(oracle, box, 1, 128)
+    c0, t0, _, _ = oracle.rollout(box, 1, Z)
+    c1, t1, _, _ = oracle.rollout(box, 1, np.nextafter(Z, np.float32(np.inf)).astype(np.float32))
+    c2, t2, _, _ = oracle.rollout(box, 1, np.nextafter(Z, np.float32(-np.inf)).astype(np.float32))
+    ok = (t0 == t1) & (t0 == t2) & (np.abs(c1 - c0) < 1e-9) & (np.abs(c2 - c0) < 1e-9)
+    assert ok.sum() >= 48
+    assert {0, 1, 2} <= set(np.unique(t0[ok]))
+    cg, tg = _gpu_rollout(Context, box, Z)
+    assert np.mean(tg[ok] == t0[ok]) >= 0.95
+    same = ok & (tg == t0) & (t0 < 3)
+    assert np.max(np.abs(cg[same] - c0[same])) <= 2 * box["scene"]["dt"] + 1e-6
+
+
+def test_plan_solve_median_matches_oracle(oracle, box, Context):
+    w = copy.deepcopy(box)
+    w["cem"].update(pop=256, n_elite=16, pop_schedule={"final": 64, "iters": 2})
+    iters = 3
+    g, r = [], []
+    for seed in range(32):
+        with Context(w, seed=seed) as c:
+            res = c.plan_solve(iters)
+        g.append(res["best_cost"])
+        r.append(oracle.plan_solve(w, seed, iters=iters)["best_cost"])
+    assert abs(np.median(g) - np.median(r)) <= 1e-2 * np.median(r)
