@@ -36,6 +36,7 @@ def test_struct_layouts_match():
     assert L.cem_sizeof(0) == ctypes.sizeof(binding.CemScene)
     assert L.cem_sizeof(1) == ctypes.sizeof(binding.CemProblem)
     assert L.cem_sizeof(2) == ctypes.sizeof(binding.CemResult)
+    assert L.cem_sizeof(3) == ctypes.sizeof(binding.CemInitRegion)
     assert L.cem_sizeof(7) == 0
 
 
@@ -78,3 +79,46 @@ def test_batch_workload_recipe():
         assert x["iters"] == spec["iters"][w["scene"]["kind"]]
     pops = [x["workload"]["cem"]["pop"] * x["workload"]["scene"]["horizon"] for x in a]
     assert 1e8 < sum(pops) < 6e8
+
+
+def _rejects(binding, w, code, **kw):
+    with pytest.raises(binding.CemError) as e:
+        binding.Context(w, **kw)
+    assert e.value.code == code
+
+
+def test_options_are_validated_before_touching_the_device():
+    import copy
+    from paper_2512_11571_amd import binding, workloads
+    pp = workloads.load("pickplace_paper")
+    # iteration-0 region: box bounds, ring dimensions, overlap, radii
+    for change in (lambda r: r["lo"].__setitem__(2, 4.0),
+                   lambda r: r["lo"].__setitem__(3, float("nan")),
+                   lambda r: r["rings"][0].__setitem__("dim", 15),
+                   lambda r: r["rings"][1].__setitem__("dim", 1),
+                   lambda r: r["rings"][0].__setitem__("radius", [1.2, 1.1]),
+                   lambda r: r["rings"][0].__setitem__("radius", [-0.1, 1.1])):
+        w = copy.deepcopy(pp)
+        change(w["cem"]["init_region"])
+        _rejects(binding, w, 1)
+    # n_env schedule: final below N_e, no ramp
+    w = copy.deepcopy(pp)
+    w["cem"]["pop_schedule"] = {"final": 10, "iters": 10}
+    _rejects(binding, w, 1)
+    w["cem"]["pop_schedule"] = {"final": 300, "iters": 0}
+    _rejects(binding, w, 1)
+    with pytest.raises(ValueError):
+        binding.Context(pp, pop=200)             # final 300 exceeds the population
+    # early stop window, domain-randomisation scenarios, reduction and ranges
+    mp = workloads.load("movepush")
+    for scene in ({"settle_steps": -1}, {"settle_steps": 3001},
+                  {"domain_randomization": {"scenarios": 3, "mu": [0.3, 0.7]}},
+                  {"domain_randomization": {"scenarios": 128, "mu": [0.3, 0.7]}},
+                  {"domain_randomization": {"scenarios": 4, "reduce": "max", "mu": [0.7, 0.3]}},
+                  {"domain_randomization": {"scenarios": 4, "mass": [0.0, 0.4]}}):
+        w = copy.deepcopy(mp)
+        w["scene"].update(scene)
+        _rejects(binding, w, 2)
+    w = copy.deepcopy(workloads.load("push"))
+    w["scene"]["domain_randomization"] = {"scenarios": 4, "mu": [0.3, 0.7]}
+    _rejects(binding, w, 2)                      # robot scenes only
