@@ -225,7 +225,9 @@ int rollout_batch(cem_ctx *c, const float *Z_dev, int32_t pop, float *cost_dev, 
 /* Same dynamics, recording the state after each of the first n_steps control
  * steps: trace_dev[pop][n_steps][W] with W = CEM_TRACE_FREE (13: the free
  * object's p q v w) for the push scene and W = CEM_TRACE_ROBOT (35: object
- * p q v w, then robot q[11] and qd[11]) for the robot scenes. */
+ * p q v w, then robot q[11] and qd[11]) for the robot scenes.  Steps after a
+ * rollout stopped (early stop, divergence) are left unwritten.  Scenes with
+ * domain-randomisation scenarios are rejected (CEM_E_ARG). */
 int rollout_trace(cem_ctx *c, const float *Z_dev, int32_t pop, int32_t n_steps, float *trace_dev, void *stream);
 
 /* Alg. 1, update step: order the samples by (tier, cost, index), NaN cost as

@@ -4,7 +4,7 @@
 // Not part of the paper's method; its limitation paragraph (full rollouts are
 // expensive) motivates it: CE samples a 16x larger population, the network
 // ranks it, and only the most promising candidates are simulated in full -
-// the simulation stays the judge of every cost that enters the refit.
+// full simulation decides every cost that enters the refit.
 //
 // All matrix products run on the MFMA units: BF16 operands, FP32
 // accumulation (v_mfma_f32_16x16x16_bf16), 64x64 output tiles per workgroup

@@ -420,14 +420,14 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
         });
       }
 
-      // ---- ABA pass 1 (root to leaves): poses, velocities, bias terms, link contacts ----
+      // ---- ABA pass 1 (root to leaves): poses, velocities, bias terms ----
       M3f Rw;  // world pose and velocity of the latest chain body
       V3f pw = v3(0.0f, 0.0f, 0.0f);
       SV vprev = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));
       Rw.r0 = v3(1.0f, 0.0f, 0.0f); Rw.r1 = v3(0.0f, 1.0f, 0.0f); Rw.r2 = v3(0.0f, 0.0f, 1.0f);
-      M3f Rw8 = Rw;
-      V3f pw8 = pw;
-      SV v8 = vprev;
+      M3f Rw8 = Rw, Rw2 = Rw;  // the palm's and the base link's pose and velocity
+      V3f pw8 = pw, pw2 = pw;
+      SV v8 = vprev, v2 = vprev;
       for (int j = 0; j < NJ; ++j) {
         const bool finger = j >= FL;
         const float qj = L.at(R_Q + j);
@@ -440,63 +440,12 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
         const SV vJ = s_vec(sc, j, L.at(R_QD + j));
         const SV vb = (j == 0 ? sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)) : x_motion(X, vp)) + vJ;
         c_put(L, j, crm(vb, vJ));
-        SV pAj = crf(vb, sym_mul(inertia_of(sk, j), vb));
-        if (j == BASEB || finger) {
-          // contacts on this link: world forces -> body spatial force, subtracted from pA
-          Box LB;
-          LB.p = pb + mul(Rb, v3(sc.b_com[j][0], sc.b_com[j][1], sc.b_com[j][2]));
-          LB.R = Rb;
-          LB.h = v3(sc.b_half[j][0], sc.b_half[j][1], sc.b_half[j][2]);
-          SV fe = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));
-          auto link_v = [&](V3f x) {
-            const V3f xb = mulT(Rb, x - pb);
-            return mul(Rb, vb.b + cross(vb.a, xb));
-          };
-          auto link_f = [&](V3f x, V3f F) {
-            const V3f Fb = mulT(Rb, F), xb = mulT(Rb, x - pb);
-            fe = fe + sv(cross(xb, Fb), Fb);
-          };
-          if (j == BASEB) {
-            for (int b = 0; b < sc.n_static; ++b) {
-              const Box SB = static_box(sc, sk, b);
-              const Rel r = rel_of(LB, SB);
-              if (face_separated(r, LB.h, SB.h)) continue;
-              verts_in_box(r, LB.h, SB, [&](V3f x, V3f n, float d) {
-                link_f(x, contact_force(true, n, d, link_v(x), kc, damp, sc.mu_static, eps2));
-              });
-              verts_in_box(rel_swap(r), SB.h, LB, [&](V3f x, V3f n, float d) {
-                link_f(x, -contact_force(true, n, d, v3(0.0f, 0.0f, 0.0f) - link_v(x), kc, damp, sc.mu_static, eps2));
-              });
-            }
-          } else {
-            const Rel r = rel_of(LB, OB);
-            bool any = false;
-            if (!face_separated(r, LB.h, ohe)) {
-              // finger vertices in the object (A = finger, B = object)
-              verts_in_box(r, LB.h, OB, [&](V3f x, V3f n, float d) {
-                const V3f ro = x - ob.p;
-                const V3f F = contact_force(true, n, d, link_v(x) - (ob.v + cross(ob.w, ro)), kc, damp, mu_o_tool, eps2);
-                link_f(x, F);
-                apply(W, ro, -F);
-                any = true;
-              });
-              // object vertices in the finger (A = object, B = finger)
-              verts_in_box(rel_swap(r), ohe, LB, [&](V3f x, V3f n, float d) {
-                const V3f ro = x - ob.p;
-                const V3f F = contact_force(true, n, d, (ob.v + cross(ob.w, ro)) - link_v(x), kc, damp, mu_o_tool, eps2);
-                apply(W, ro, F);
-                link_f(x, -F);
-                any = true;
-              });
-            }
-            if (last) {
-              if (j == FL) touchL = any;
-              else touchR = any;
-            }
-          }
-          pAj = pAj - fe;
+        L.sv_put(R_P + 6 * j, crf(vb, sym_mul(inertia_of(sk, j), vb)));
+        if (j == BASEB) {
+          Rw2 = Rb;
+          pw2 = pb;
+          v2 = vb;
         }
-        L.sv_put(R_P + 6 * j, pAj);
         if (!finger) {
           Rw = Rb;
           pw = pb;
@@ -506,6 +455,83 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
           Rw8 = Rb;
           pw8 = pb;
           v8 = vb;
+        }
+      }
+
+      // ---- contacts on the base link and the fingers: world forces become body
+      // spatial forces, taken off those bodies' bias forces ----
+      {
+        auto link_box = [&](int j, const M3f &Rb, V3f pb) {
+          Box LB;
+          LB.p = pb + mul(Rb, v3(sc.b_com[j][0], sc.b_com[j][1], sc.b_com[j][2]));
+          LB.R = Rb;
+          LB.h = v3(sc.b_half[j][0], sc.b_half[j][1], sc.b_half[j][2]);
+          return LB;
+        };
+        // the base link against the static boxes
+        {
+          const Box LB = link_box(BASEB, Rw2, pw2);
+          // velocity of a point and the force sum in the world frame, the
+          // moment about the body origin; one rotation into the body at the end
+          const V3f wa = mul(Rw2, v2.a), wb = mul(Rw2, v2.b);
+          V3f fm = v3(0.0f, 0.0f, 0.0f), ff = v3(0.0f, 0.0f, 0.0f);
+          auto link_v = [&](V3f x) { return wb + cross(wa, x - pw2); };
+          auto link_f = [&](V3f x, V3f F) {
+            fm = fm + cross(x - pw2, F);
+            ff = ff + F;
+          };
+          for (int b = 0; b < sc.n_static; ++b) {
+            const Box SB = static_box(sc, sk, b);
+            const Rel r = rel_of(LB, SB);
+            if (face_separated(r, LB.h, SB.h)) continue;
+            verts_in_box(r, LB.h, SB, [&](V3f x, V3f n, float d) {
+              link_f(x, contact_force(true, n, d, link_v(x), kc, damp, sc.mu_static, eps2));
+            });
+            verts_in_box(rel_swap(r), SB.h, LB, [&](V3f x, V3f n, float d) {
+              link_f(x, -contact_force(true, n, d, v3(0.0f, 0.0f, 0.0f) - link_v(x), kc, damp, sc.mu_static, eps2));
+            });
+          }
+          L.sv_put(R_P + 6 * BASEB, L.sv_at(R_P + 6 * BASEB) - sv(mulT(Rw2, fm), mulT(Rw2, ff)));
+        }
+        // the fingers against the object (their pose again from the palm's)
+        for (int j = FL; j <= FR; ++j) {
+          const JT X = joint_of(sc, j, L.at(R_Q + j));
+          const M3f Rb = rot_right(Rw8, X);
+          const V3f pb = pw8 + mul(Rw8, X.r);
+          const SV vb = x_motion(X, v8) + s_vec(sc, j, L.at(R_QD + j));
+          const Box LB = link_box(j, Rb, pb);
+          const V3f wa = mul(Rb, vb.a), wb = mul(Rb, vb.b);
+          V3f fm = v3(0.0f, 0.0f, 0.0f), ff = v3(0.0f, 0.0f, 0.0f);
+          auto link_v = [&](V3f x) { return wb + cross(wa, x - pb); };
+          auto link_f = [&](V3f x, V3f F) {
+            fm = fm + cross(x - pb, F);
+            ff = ff + F;
+          };
+          const Rel r = rel_of(LB, OB);
+          bool any = false;
+          if (!face_separated(r, LB.h, ohe)) {
+            // finger vertices in the object (A = finger, B = object)
+            verts_in_box(r, LB.h, OB, [&](V3f x, V3f n, float d) {
+              const V3f ro = x - ob.p;
+              const V3f F = contact_force(true, n, d, link_v(x) - (ob.v + cross(ob.w, ro)), kc, damp, mu_o_tool, eps2);
+              link_f(x, F);
+              apply(W, ro, -F);
+              any = true;
+            });
+            // object vertices in the finger (A = object, B = finger)
+            verts_in_box(rel_swap(r), ohe, LB, [&](V3f x, V3f n, float d) {
+              const V3f ro = x - ob.p;
+              const V3f F = contact_force(true, n, d, (ob.v + cross(ob.w, ro)) - link_v(x), kc, damp, mu_o_tool, eps2);
+              apply(W, ro, F);
+              link_f(x, -F);
+              any = true;
+            });
+          }
+          if (last) {
+            if (j == FL) touchL = any;
+            else touchR = any;
+          }
+          L.sv_put(R_P + 6 * j, L.sv_at(R_P + 6 * j) - sv(mulT(Rb, fm), mulT(Rb, ff)));
         }
       }
 

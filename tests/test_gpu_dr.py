@@ -142,3 +142,18 @@ def test_plan_solve_median_matches_oracle(oracle, B):
             g.append(c.plan_solve(iters)["best_cost"])
         r.append(oracle.plan_solve(w, seed, iters=iters)["best_cost"])
     assert abs(np.median(g) - np.median(r)) <= 1e-2 * np.median(r)
+
+
+@pytest.mark.parametrize("name,R", [("pickplace", 1), ("movepush", 64)])
+def test_rows_do_not_depend_on_the_population(oracle, B, name, R):
+    # a row's outcome is the same whether it runs alone (pop 1 or 3; with 64
+    # scenarios one row fills a wave) or among 100 rows
+    base = workloads.load(name)
+    w = _dr(base, R, H=300) if R > 1 else dict(base, scene=dict(base["scene"], horizon=300))
+    Z = _rows(oracle, base, 3, 100)
+    full = _run(B, w, Z, 3)
+    for n in (1, 3):
+        part = _run(B, w, Z[:n], 3)
+        for a, b in zip(part[:3], full[:3]):
+            assert np.array_equal(a, b[:n])
+        assert part[3] >= 0.99 * n * R * 300
