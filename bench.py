@@ -81,6 +81,12 @@ def cpu_baseline(w, seed, budget_s):
             "env_steps": done, "seconds": dt}
 
 
+def _valu_ceiling():
+    """The device's measured unpacked FP32 FMA rate (TFLOP/s): the ceiling of the rollout's arithmetic."""
+    from paper_2512_11571_amd.binding import valu_fma_rate
+    return valu_fma_rate() / 1e12
+
+
 def bench_batch(a):
     """The batched workload: all instances, one CE iteration per step (graph replay)."""
     import numpy as np
@@ -121,6 +127,7 @@ def bench_batch(a):
     # so the step's event time bounds the rollout kernel's duration from above
     roll_s = sum(step_ms) / len(step_ms) / 1e3
     achieved = flops_iter / roll_s / 1e12 if roll_s > 0 else None
+    ceiling = _valu_ceiling()
     out = {
         "metric": "env-steps/s (CE iterations/s alongside)",
         "value": env_steps_iter * K / elapsed,
@@ -133,7 +140,8 @@ def bench_batch(a):
         "step_event_ms": roll_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": None,
-                     "flops_per_env_step": fps},
+                     "flops_per_env_step": fps, "unpacked_fma_measured": ceiling,
+                     "frac_of_measured": achieved / ceiling if achieved and ceiling else None},
     }
     if not a.no_cpu_baseline:
         per_kind = []
@@ -429,6 +437,7 @@ def main():
     meas = w.get("measurement", {})
     fps = meas.get("flops_per_env_step")
     achieved = (fps * env_steps / K / roll_avg_s / 1e12) if fps else None
+    ceiling = _valu_ceiling()
     tr = MEASURED_TRAFFIC.get(a.workload)
     traffic = (tr["bytes_per_launch"] if tr and tr.get("src_hash") == _src_hash(a.workload)
                and not sc.get("settle_steps", 0) else None)
@@ -455,7 +464,9 @@ def main():
         "rollout_kernel_ms": roll_avg_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": traffic,
-                     "flops_per_env_step": fps},
+                     "flops_per_env_step": fps,
+                     "unpacked_fma_measured": ceiling,
+                     "frac_of_measured": (achieved / ceiling) if achieved and ceiling else None},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.seed, a.cpu_seconds)

@@ -199,6 +199,13 @@ int cem_init(const cem_problem *p, cem_ctx **out);
 void cem_free(cem_ctx *c);
 
 int cem_dim(const cem_ctx *c);
+/* Measurement aid, not part of the method: the device's FP32 vector FMA rate
+ * (FLOP/s, an FMA counting 2) on the current device, from a kernel of
+ * independent unpacked FMA chains at eight waves per SIMD, best of three timed
+ * launches on `stream` (NULL: the null stream).  The ceiling of unpacked FP32
+ * arithmetic, beside the published packed peak.  Synchronous; allocates and
+ * frees an 8 MiB output buffer. */
+int cem_valu_fma_rate(double *flops_per_s, void *stream);
 /* sizeof of the ABI structs (0 cem_scene, 1 cem_problem, 2 cem_result,
  * 3 cem_init_region; else 0),
  * for bindings to check their layouts. */

@@ -92,7 +92,8 @@ class CemResult(ctypes.Structure):
 
 EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem_last_error", "cem_sample", "rollout_batch",
            "rollout_trace", "cem_refit", "plan_solve", "cem_get_theta", "cem_set_theta", "cem_get_factor",
-           "cem_get_instance", "cem_get_scenarios", "cem_env_steps", "cem_pop_at", "cem_reset", "cem_batch_init", "cem_batch_free", "cem_batch_size",
+           "cem_get_instance", "cem_get_scenarios", "cem_env_steps", "cem_pop_at", "cem_reset",
+           "cem_valu_fma_rate", "cem_batch_init", "cem_batch_free", "cem_batch_size",
            "cem_batch_last_error", "cem_batch_instance", "cem_batch_autotune", "cem_batch_step", "cem_batch_solve",
            "cem_batch_record", "cem_mlp_init", "cem_mlp_free", "cem_mlp_n_params", "cem_mlp_last_error",
            "cem_mlp_get_params", "cem_mlp_set_params", "cem_mlp_get_norm", "cem_mlp_set_norm", "cem_mlp_fit_norm",
@@ -130,6 +131,7 @@ def lib():
         L.cem_env_steps.argtypes = [vp, P(ctypes.c_uint64)]
         L.cem_pop_at.argtypes = [vp, _i]
         L.cem_get_scenarios.argtypes = [vp, vp, vp]
+        L.cem_valu_fma_rate.argtypes = [P(ctypes.c_double), vp]
         L.cem_reset.argtypes = [vp]
         L.cem_sizeof.argtypes = [ctypes.c_int]
         L.cem_batch_init.argtypes = [vp, vp, _i, P(vp)]
@@ -166,6 +168,15 @@ def lib():
                 raise RuntimeError("ABI struct layout mismatch for %s" % st.__name__)
         _lib = L
     return _lib
+
+
+def valu_fma_rate(stream=None):
+    """Measured FP32 vector FMA rate of the current device, FLOP/s (a measurement aid)."""
+    r = ctypes.c_double(0.0)
+    rc = lib().cem_valu_fma_rate(ctypes.byref(r), _stream(stream) if stream is not None else None)
+    if rc != CEM_OK:
+        raise CemError(rc, lib().cem_strerror(rc).decode())
+    return r.value
 
 
 class CemError(RuntimeError):

@@ -27,6 +27,7 @@ SOURCES = {
     # selected pointer would move those values to scratch memory
     "rollout.hip": ["-mllvm", "-simplifycfg-sink-common=false"],
     "mlp.hip": [],
+    "peak.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
