@@ -5,8 +5,8 @@
 //    f_n = max(0, k d - c v_n), f_t = -mu f_n v_t / sqrt(|v_t|^2 + eps_v^2)
 //  - semi-implicit Euler: v, w first (gyroscopic term explicit, world-frame w),
 //    then p and the quaternion (first order, renormalised).
-// Contact loops test every candidate and form forces only where a lane has a
-// contact (the branch is skipped by the whole wave when no lane does).
+// Contact loops test every candidate, then form forces in one pass per
+// contact of a lane (a wave runs as many passes as its busiest lane).
 #pragma once
 #include "devmath.hpp"
 
@@ -39,20 +39,26 @@ __device__ __forceinline__ void apply(Wrench &W, V3f r, V3f F) {
 
 // Box corners against the plane z = 0 (A = box, B = ground at rest).  The
 // corner heights come from the third row of R alone; the lever arm and the
-// force are formed only where a lane has the corner below the plane.
+// force are formed once per corner below the plane of a lane, in ascending
+// corner order, so lanes whose corners below the plane differ share passes.
 __device__ __forceinline__ void box_ground(const FreeBody &b, const M3f &R, V3f he, float k, float damp, float mu,
                                            float eps2, Wrench &W) {
   const float zx = he.x * R.r2.x, zy = he.y * R.r2.y, zz = he.z * R.r2.z;
+  unsigned below = 0u;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const float rz = ((i & 4) ? zz : -zz) + ((i & 2) ? zy : -zy) + ((i & 1) ? zx : -zx);
+    if (-(b.p.z + rz) > 0.0f) below |= 1u << i;
+  }
+  while (below != 0u) {  // at most eight passes
+    const int i = __builtin_ctz(below);
+    below &= below - 1u;
+    const float rz = ((i & 4) ? zz : -zz) + ((i & 2) ? zy : -zy) + ((i & 1) ? zx : -zx);
     const float d = -(b.p.z + rz);
-    if (d > 0.0f) {  // skipped by the whole wave when no lane has this corner below the plane
-      const V3f loc = v3((i & 1) ? he.x : -he.x, (i & 2) ? he.y : -he.y, (i & 4) ? he.z : -he.z);
-      const V3f r = mul(R, loc);
-      const V3f vA = b.v + cross(b.w, r);
-      apply(W, r, contact_force(true, v3(0.0f, 0.0f, 1.0f), d, vA, k, damp, mu, eps2));
-    }
+    const V3f loc = v3((i & 1) ? he.x : -he.x, (i & 2) ? he.y : -he.y, (i & 4) ? he.z : -he.z);
+    const V3f r = mul(R, loc);
+    const V3f vA = b.v + cross(b.w, r);
+    apply(W, r, contact_force(true, v3(0.0f, 0.0f, 1.0f), d, vA, k, damp, mu, eps2));
   }
 }
 

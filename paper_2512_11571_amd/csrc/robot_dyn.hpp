@@ -285,6 +285,9 @@ __device__ __forceinline__ M3f rot_right(const M3f &P, const JT &J) { CEM_AXIS_C
 template <int K> struct AxisK {
   static constexpr int value = K;
 };
+template <bool B> struct BoolK {
+  static constexpr bool value = B;
+};
 __device__ __forceinline__ V3f col(const M3f &R, int k);
 
 // World poses of bodies 0..PALM (chain) for the arm kinematics.
@@ -452,19 +455,27 @@ __device__ __forceinline__ bool face_separated(const Rel &r, V3f hA, V3f hB) {
 }
 // Vertex-face: the vertices of box A strictly inside box B (r = rel_of(A, B));
 // for each, depth = distance to B's nearest face, n = that face's outward
-// normal (world), x = the vertex (world), calling f(x, n, d).  Faces +x -x +y
-// -y +z -z, first on ties.  Vertices are built in B's frame from the scaled
-// axes of A; the face search and the world-frame quantities are computed only
-// where a lane has the vertex inside.
+// normal (world), x = the vertex (world), calling f(x, n, d) in ascending
+// vertex order.  Faces +x -x +y -y +z -z, first on ties.  Vertices are built
+// in B's frame from the scaled axes of A.  The inside test runs for all eight;
+// the face search and the contact then run once per inside vertex of a lane,
+// so lanes whose inside vertices differ share passes (the wave runs as many
+// passes as its lane with the most vertices inside, not one per vertex index).
 template <class F>
 __device__ __forceinline__ void verts_in_box(const Rel &r, V3f hA, const Box &B, F &&f) {
   const V3f c0 = hA.x * col(r.M, 0), c1 = hA.y * col(r.M, 1), c2 = hA.z * col(r.M, 2);
   const V3f hb = B.h;
+  unsigned inside = 0u;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const V3f xb = (r.t + ((i & 4) ? c2 : -c2) + ((i & 2) ? c1 : -c1)) + ((i & 1) ? c0 : -c0);
-    const bool in = fabsf(xb.x) < hb.x && fabsf(xb.y) < hb.y && fabsf(xb.z) < hb.z;
-    if (in) {  // skipped by the whole wave when no lane has this vertex inside
+    if (fabsf(xb.x) < hb.x && fabsf(xb.y) < hb.y && fabsf(xb.z) < hb.z) inside |= 1u << i;
+  }
+  while (inside != 0u) {  // at most eight passes
+    const int i = __builtin_ctz(inside);
+    inside &= inside - 1u;
+    {
+      const V3f xb = (r.t + ((i & 4) ? c2 : -c2) + ((i & 2) ? c1 : -c1)) + ((i & 1) ? c0 : -c0);
       const float ds[6] = {hb.x - xb.x, hb.x + xb.x, hb.y - xb.y, hb.y + xb.y, hb.z - xb.z, hb.z + xb.z};
       int fb = 0;
       float dmin = ds[0];

@@ -536,22 +536,14 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       }
 
       // ---- ABA pass 2 (leaves to root): articulated inertias, U, D, u ----
+      // Body j's articulated inertia IA arrives from its children; the
+      // fingers start from their own inertia, fold into the palm's (IA8), the
+      // palm and the chain bodies fold into their parent's (IAc).  Three loops
+      // with the source and destination fixed, so no per-body selects.
       Sym6 IA8 = inertia_of(sk, PALM);
       Sym6 IAc = IA8;
-      for (int j = NJ - 1; j >= 0; --j) {
-        Sym6 IA;
-        {
-          // element-wise select (a struct-level select would be lowered through memory)
-          const Sym6 Ib = inertia_of(sk, j);
-          const bool leaf = j >= FL, palm = j == PALM;
-#pragma unroll
-          for (int i = 0; i < 6; ++i) {
-            IA.A[i] = leaf ? Ib.A[i] : (palm ? IA8.A[i] : IAc.A[i]);
-            IA.C[i] = leaf ? Ib.C[i] : (palm ? IA8.C[i] : IAc.C[i]);
-          }
-#pragma unroll
-          for (int i = 0; i < 9; ++i) IA.B[i] = leaf ? Ib.B[i] : (palm ? IA8.B[i] : IAc.B[i]);
-        }
+      auto pass2 = [&](int j, Sym6 &IA, auto into_palm) {
+        constexpr bool TO_PALM = decltype(into_palm)::value;
         const SV pAj = L.sv_at(R_P + 6 * j);
         const float qj = L.at(R_Q + j), qdj = L.at(R_QD + j);
         const float lim = sc.j_inom[j] * sc.accel_max;
@@ -572,8 +564,9 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
             constexpr int K = decltype(axis)::value;
             const Sym6 Ip = congruence_k<K>(X, IA);
             L.sv_put(R_P + 6 * p, L.sv_at(R_P + 6 * p) + x_force_T_k<K>(X, pa));
-            if (p == PALM) sym_add(IA8, Ip);
-            else {
+            if constexpr (TO_PALM) {
+              sym_add(IA8, Ip);
+            } else {
               IAc = inertia_of(sk, p);
               sym_add(IAc, Ip);
             }
@@ -582,7 +575,13 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
           else if (X.k == 1) fold(AxisK<1>());
           else fold(AxisK<2>());
         }
+      };
+      for (int j = FR; j >= FL; --j) {
+        Sym6 IA = inertia_of(sk, j);
+        pass2(j, IA, BoolK<true>());
       }
+      pass2(PALM, IA8, BoolK<false>());
+      for (int j = PALM - 1; j >= 0; --j) pass2(j, IAc, BoolK<false>());
 
       // ---- ABA pass 3 (root to leaves): accelerations and the joint update ----
       SV a_prev = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, g));  // world: -gravity
