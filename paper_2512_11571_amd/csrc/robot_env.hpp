@@ -421,41 +421,48 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       }
 
       // ---- ABA pass 1 (root to leaves): poses, velocities, bias terms ----
-      M3f Rw;  // world pose and velocity of the latest chain body
+      // The chain (bodies 0..PALM), then the fingers, children of the palm:
+      // separate loops, so the parent's pose needs no per-body select.
+      auto pass1 = [&](int j, const M3f &Rp, V3f pp, const SV &vp, M3f &Rb, V3f &pb, SV &vb) {
+        const float qj = L.at(R_Q + j);
+        const JT X = joint_of(sc, j, qj);
+        Rb = rot_right(Rp, X);
+        pb = pp + mul(Rp, X.r);
+        const SV vJ = s_vec(sc, j, L.at(R_QD + j));
+        vb = (j == 0 ? sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)) : x_motion(X, vp)) + vJ;
+        c_put(L, j, crm(vb, vJ));
+        L.sv_put(R_P + 6 * j, crf(vb, sym_mul(inertia_of(sk, j), vb)));
+      };
+      M3f Rw;  // world pose and velocity of the latest chain body (the palm's after the chain)
       V3f pw = v3(0.0f, 0.0f, 0.0f);
       SV vprev = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));
       Rw.r0 = v3(1.0f, 0.0f, 0.0f); Rw.r1 = v3(0.0f, 1.0f, 0.0f); Rw.r2 = v3(0.0f, 0.0f, 1.0f);
-      M3f Rw8 = Rw, Rw2 = Rw;  // the palm's and the base link's pose and velocity
-      V3f pw8 = pw, pw2 = pw;
-      SV v8 = vprev, v2 = vprev;
-      for (int j = 0; j < NJ; ++j) {
-        const bool finger = j >= FL;
-        const float qj = L.at(R_Q + j);
-        const JT X = joint_of(sc, j, qj);
-        const M3f Rp = finger ? Rw8 : Rw;
-        const V3f pp = finger ? pw8 : pw;
-        const SV vp = finger ? v8 : vprev;
-        const M3f Rb = rot_right(Rp, X);
-        const V3f pb = pp + mul(Rp, X.r);
-        const SV vJ = s_vec(sc, j, L.at(R_QD + j));
-        const SV vb = (j == 0 ? sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)) : x_motion(X, vp)) + vJ;
-        c_put(L, j, crm(vb, vJ));
-        L.sv_put(R_P + 6 * j, crf(vb, sym_mul(inertia_of(sk, j), vb)));
-        if (j == BASEB) {
-          Rw2 = Rb;
-          pw2 = pb;
-          v2 = vb;
-        }
-        if (!finger) {
-          Rw = Rb;
-          pw = pb;
-          vprev = vb;
-        }
-        if (j == PALM) {
-          Rw8 = Rb;
-          pw8 = pb;
-          v8 = vb;
-        }
+      for (int j = 0; j <= BASEB; ++j) {
+        M3f Rb;
+        V3f pb;
+        SV vb;
+        pass1(j, Rw, pw, vprev, Rb, pb, vb);
+        Rw = Rb;
+        pw = pb;
+        vprev = vb;
+      }
+      const M3f Rw2 = Rw;  // the base link's pose and velocity, for its contacts
+      const V3f pw2 = pw;
+      const SV v2 = vprev;
+      for (int j = BASEB + 1; j <= PALM; ++j) {
+        M3f Rb;
+        V3f pb;
+        SV vb;
+        pass1(j, Rw, pw, vprev, Rb, pb, vb);
+        Rw = Rb;
+        pw = pb;
+        vprev = vb;
+      }
+      for (int j = FL; j <= FR; ++j) {
+        M3f Rb;
+        V3f pb;
+        SV vb;
+        pass1(j, Rw, pw, vprev, Rb, pb, vb);
       }
 
       // ---- contacts on the base link and the fingers: world forces become body
@@ -496,9 +503,9 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
         // the fingers against the object (their pose again from the palm's)
         for (int j = FL; j <= FR; ++j) {
           const JT X = joint_of(sc, j, L.at(R_Q + j));
-          const M3f Rb = rot_right(Rw8, X);
-          const V3f pb = pw8 + mul(Rw8, X.r);
-          const SV vb = x_motion(X, v8) + s_vec(sc, j, L.at(R_QD + j));
+          const M3f Rb = rot_right(Rw, X);
+          const V3f pb = pw + mul(Rw, X.r);
+          const SV vb = x_motion(X, vprev) + s_vec(sc, j, L.at(R_QD + j));
           const Box LB = link_box(j, Rb, pb);
           const V3f wa = mul(Rb, vb.a), wb = mul(Rb, vb.b);
           V3f fm = v3(0.0f, 0.0f, 0.0f), ff = v3(0.0f, 0.0f, 0.0f);
@@ -584,20 +591,19 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       for (int j = PALM - 1; j >= 0; --j) pass2(j, IAc, BoolK<false>());
 
       // ---- ABA pass 3 (root to leaves): accelerations and the joint update ----
-      SV a_prev = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, g));  // world: -gravity
-      SV a8 = a_prev;
-      for (int j = 0; j < NJ; ++j) {
+      auto pass3 = [&](int j, const SV &a_parent) {
         const float qj = L.at(R_Q + j);
         const JT X = joint_of(sc, j, qj);
-        const SV ap = x_motion(X, j >= FL ? a8 : a_prev) + c_at(L, j);
+        const SV ap = x_motion(X, a_parent) + c_at(L, j);
         const float qdd = L.at(R_UD + j) - dot6(L.sv_at(R_P + 6 * j), ap);
-        const SV aj = ap + s_vec(sc, j, qdd);
-        if (j < FL) a_prev = aj;
-        if (j == PALM) a8 = aj;
         const float qdn = L.at(R_QD + j) + h * qdd;
         L.at(R_QD + j) = qdn;
         L.at(R_Q + j) = qj + h * qdn;
-      }
+        return ap + s_vec(sc, j, qdd);
+      };
+      SV a_prev = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, g));  // world: -gravity
+      for (int j = 0; j <= PALM; ++j) a_prev = pass3(j, a_prev);
+      for (int j = FL; j <= FR; ++j) pass3(j, a_prev);          // the fingers, from the palm's acceleration
       integrate(ob, W, inv_om, oIb, gv, h);
     }
     if (TRACE && t < trace_steps) {
