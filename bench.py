@@ -110,6 +110,7 @@ def bench_batch(a):
     with Batch(insts) as B:
         tune = B.autotune()           # untimed
         torch.cuda.synchronize()
+        counted0 = sum(B.instance(k).env_steps() for k in range(len(insts)))
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
         t0 = time.perf_counter()
         for j in range(K):            # one CE iteration of every instance per replay
@@ -119,7 +120,9 @@ def bench_batch(a):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         step_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+        counted = sum(B.instance(k).env_steps() for k in range(len(insts))) - counted0
     env_steps_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"] for i in insts)
+    assert counted <= env_steps_iter * K, (counted, env_steps_iter * K)   # fewer only where rollouts diverged
     fps = {k: workloads.load(k).get("measurement", {}).get("flops_per_env_step") for k in kinds}
     flops_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"]
                      * (fps[i["workload"]["scene"]["kind"]] or 0.0) for i in insts)
@@ -130,13 +133,14 @@ def bench_batch(a):
     ceiling = _valu_ceiling()
     out = {
         "metric": "env-steps/s (CE iterations/s alongside)",
-        "value": env_steps_iter * K / elapsed,
+        "value": counted / elapsed,
         "unit": "env-steps/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
         "ms_per_step": elapsed / K * 1e3, "cem_iters_per_s": K / elapsed,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (FP64 refit and Cholesky)", "data": "synthetic (seeded instances, scenes and Philox samples)",
         "config": {"workload": a.workload, "instances": len(insts), "env_steps_per_iter": env_steps_iter,
                    "autotune": tune},
+        "env_steps_simulated": counted, "env_steps_full_horizon": env_steps_iter * K,
         "step_event_ms": roll_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": None,
