@@ -7,7 +7,9 @@ full-horizon run of the same rows: identical cost wherever both are finite (the
 stop waits for the last action to end), psi_g agrees on nearly every row, and
 fewer steps are simulated.  Against the FP64 oracle with the same option:
 tier and cost on certified rows as for the full horizon, and the total of
-simulated steps within 5 %.
+simulated steps within 5 %.  With domain-randomisation scenarios the costs
+still equal the full-horizon ones, and batched instances that stop early give
+the bits and step counts of their single runs.
 """
 import copy
 
@@ -109,3 +111,35 @@ def test_early_stop_parity_with_the_oracle(oracle, Context):
     same = ok & (tg == tr) & (tr < 3)
     assert np.max(np.abs(cg[same] - cr[same])) <= 2 * w["scene"]["dt"] + 1e-6
     assert abs(sg - int(sr.sum())) <= 0.05 * sr.sum()
+
+
+def test_early_stop_with_scenarios_and_in_a_batch(oracle, Context):
+    # early stop composes with domain randomisation (each scenario stops on its
+    # own; the cost is still the full-horizon one) and with batching (a batched
+    # instance that stops early gives the bits of its single run)
+    from paper_2512_11571_amd import binding
+    w = copy.deepcopy(workloads.load("movepush"))
+    w["scene"]["horizon"] = 1500
+    w["scene"]["domain_randomization"] = {"scenarios": 4, "mu": [0.3, 0.7], "mass": [0.2, 0.4]}
+    Z = _rows(oracle, w, 2, 96)
+    cf, tf, sf = _gpu(Context, w, Z, 2)
+    ce, te, se = _gpu(Context, _early(w), Z, 2)
+    both = np.isfinite(cf) & np.isfinite(ce)
+    assert both.mean() >= 0.99 and np.array_equal(cf[both], ce[both])
+    assert np.mean(tf == te) >= 0.95
+    assert se < sf
+    we = _early(w)
+    we["cem"].update(pop=128, n_elite=8)
+    pp = copy.deepcopy(workloads.load("pickplace"))
+    pp["scene"]["horizon"] = 600
+    pp["cem"].update(pop=100, n_elite=8)
+    insts = [{"workload": we, "seed": 0, "instance": 0, "iters": 2},
+             {"workload": _early(pp), "seed": 1, "instance": 1, "iters": 2}]
+    with binding.Batch(insts) as bt:
+        res = bt.solve(2)
+        counted = [bt.instance(k).env_steps() for k in range(2)]
+    for inst, r, n in zip(insts, res, counted):
+        with Context(inst["workload"], seed=inst["seed"], instance=inst["instance"]) as c:
+            s = c.plan_solve(inst["iters"])
+            assert c.env_steps() == n
+        assert r["best_cost"] == s["best_cost"] and np.array_equal(r["mu"], s["mu"])
