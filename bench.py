@@ -38,7 +38,7 @@ DEFAULT_WORKLOAD = "pickplace"
 MEASURED_TRAFFIC = {
     # rollout of 1024 pick-and-place plans over 2000 steps: FETCH_SIZE 856.75 KiB x 2.0
     # + WRITE_SIZE 5.5 KiB x 1.0 (a 256 MiB copy reads as 131083.5 / 262144 KiB)
-    "pickplace": {"bytes_per_launch": int((856.75 * 2.0 + 5.5 * 1.0) * 1024), "src_hash": "9fd10c3d4e718685"},
+    "pickplace": {"bytes_per_launch": int((856.75 * 2.0 + 5.5 * 1.0) * 1024), "src_hash": "0125f9437e43f2c3"},
 }
 
 _KERNEL_FILES = ["rollout.hip", "push_env.hpp", "robot_env.hpp", "robot_dyn.hpp", "rigid.hpp", "devmath.hpp",

@@ -23,18 +23,21 @@
 //
 // Dynamics per substep: Featherstone's articulated-body algorithm in three
 // passes over the fixed 11-body tree (base x, base y, base yaw, six arm
-// joints, two fingers on the last arm body), with the contact forces on the
-// base and finger links folded into the bias forces during the first pass and
-// the semi-implicit Euler update folded into the last; the object is a free
-// box against the ground, the static boxes and the fingers (vertex-face both
-// ways).
+// joints, two fingers on the last arm body).  Each pass runs one loop per
+// segment of the tree (the chain, then the fingers off the palm), so no body
+// selects its parent's data.  The contact forces on the base and finger links
+// are taken off their bias forces between the first and second passes, and
+// the semi-implicit Euler update is folded into the last; the object is a
+// free box against the ground, the static boxes and the fingers (vertex-face
+// both ways, one pass per contact of a lane).
 //
 // One environment per lane.  The per-body quantities the three passes hand to
 // each other (joint state, bias accelerations, bias forces / U columns, D^-1,
 // u) and the push's third joint-space anchor live in LDS, one lane-contiguous
 // row per quantity, so the passes loop over bodies without unrolling and
-// without scratch; the rest of the state stays in VGPRs.  HBM is touched only for z in and (cost, tier, pose) out;
-// the scene is read through wave-uniform scalar loads.
+// without scratch; the rest of the state stays in VGPRs.  HBM is touched only
+// for z in and (cost, tier, pose) out; the scene is read through wave-uniform
+// scalar loads.
 #pragma once
 #include "robot_dyn.hpp"
 
