@@ -85,49 +85,82 @@ struct GemmArgs {
   long c_split;
 };
 
-// 64x64 tile of C per workgroup (256 threads = 4 waves, 32x32 each).
+// Eight elements of an operand, p[e * stride] for e = 0..7, into LDS: one
+// 16-byte load where they are contiguous (stride 1), in range and aligned,
+// element by element (zero outside the operand) otherwise.  `ok(e)` says
+// whether element e is in range; `dst(e)` is its LDS slot.
+template <class InRange, class Dst>
+__device__ __forceinline__ void stage8(const uint16_t *__restrict__ p, long stride, bool all_in, InRange ok, Dst dst) {
+  if (stride == 1 && all_in && (((uintptr_t)p & 15u) == 0u)) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dst(e) = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dst(e) = ok(e) ? p[e * stride] : (uint16_t)0;
+  }
+}
+
+// 64x64 tile of C per workgroup (256 threads = 4 waves, 32x32 each), 32 of the
+// contraction per step (two MFMA 16-steps in ascending k, as a plain loop over
+// 16-steps would take them).  Each operand is staged along its contiguous axis
+// with 16-byte loads and kept in LDS with the contraction contiguous ([m][k]
+// and [n][k]), so a lane reads each 4-element MFMA fragment as one 8-byte word.
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
-  __shared__ uint16_t As[64][16 + 4];
-  __shared__ uint16_t Bs[16][64 + 4];
+  constexpr int KS = 32, LDK = KS + 8;  // 80-byte LDS rows: 16-byte aligned, banks staggered
+  __shared__ __align__(16) uint16_t As[64][LDK];
+  __shared__ __align__(16) uint16_t Bs[64][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int kbeg = blockIdx.z * g.kc, kend = min(g.K, kbeg + g.kc);
-  // stage each operand along its contiguous axis, so that neighbouring threads
-  // read neighbouring elements
-  const bool a_kfast = g.a_k == 1, b_nfast = g.b_n == 1;
+  const bool a_kfast = g.a_k == 1, b_kfast = g.b_k == 1 && g.b_n != 1;
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    // stage A (64x16) and B (16x64): 4 elements per thread each, zero outside
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid * 4 + e;
-      const int am = a_kfast ? idx >> 4 : idx & 63, ak = a_kfast ? idx & 15 : idx >> 6;
-      const int m = m0 + am, k = k0 + ak;
-      As[am][ak] = (m < g.M && k < kend) ? g.A[(long)m * g.a_m + (long)k * g.a_k] : (uint16_t)0;
-      const int bk = b_nfast ? idx >> 6 : idx & 15, bn = b_nfast ? idx & 63 : idx >> 4;
-      const int kk = k0 + bk, n = n0 + bn;
-      Bs[bk][bn] = (kk < kend && n < g.N) ? g.B[(long)kk * g.b_k + (long)n * g.b_n] : (uint16_t)0;
+  for (int k0 = kbeg; k0 < kend; k0 += KS) {
+    // A (64 x 32): 64 rows x 4 chunks of k, or 32 k x 8 chunks of m
+    if (a_kfast) {
+      const int am = tid >> 2, ak = (tid & 3) * 8, m = m0 + am, k = k0 + ak;
+      const uint16_t *p = g.A + (long)m * g.a_m + k;
+      stage8(p, 1, m < g.M && k + 7 < kend, [&](int e) { return m < g.M && k + e < kend; },
+             [&](int e) -> uint16_t & { return As[am][ak + e]; });
+    } else {
+      const int ak = tid >> 3, am = (tid & 7) * 8, m = m0 + am, k = k0 + ak;
+      const uint16_t *p = g.A + (long)m * g.a_m + (long)k * g.a_k;
+      stage8(p, g.a_m, k < kend && m + 7 < g.M, [&](int e) { return k < kend && m + e < g.M; },
+             [&](int e) -> uint16_t & { return As[am + e][ak]; });
+    }
+    // B (32 x 64): 64 columns x 4 chunks of k, or 32 k x 8 chunks of n
+    if (b_kfast) {
+      const int bn = tid >> 2, bk = (tid & 3) * 8, n = n0 + bn, k = k0 + bk;
+      const uint16_t *p = g.B + (long)k + (long)n * g.b_n;
+      stage8(p, 1, n < g.N && k + 7 < kend, [&](int e) { return n < g.N && k + e < kend; },
+             [&](int e) -> uint16_t & { return Bs[bn][bk + e]; });
+    } else {
+      const int bk = tid >> 3, bn = (tid & 7) * 8, n = n0 + bn, k = k0 + bk;
+      const uint16_t *p = g.B + (long)k * g.b_k + (long)n * g.b_n;
+      stage8(p, g.b_n, k < kend && n + 7 < g.N, [&](int e) { return k < kend && n + e < g.N; },
+             [&](int e) -> uint16_t & { return Bs[bn + e][bk]; });
     }
     __syncthreads();
     const int r = lane & 15, q = lane >> 4;
-    bf16x4 af[2], bfr[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int kk = 0; kk < KS; kk += 16) {
+      bf16x4 af[2], bfr[2];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) af[i][t] = (short)As[wm + 16 * i + r][4 * q + t];
+      for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x4 *>(&As[wm + 16 * i + r][kk + 4 * q]);
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x4 *>(&Bs[wn + 16 * j + r][kk + 4 * q]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) bfr[j][t] = (short)Bs[4 * q + t][wn + 16 * j + r];
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
     __syncthreads();
   }
   // lane holds D[4q + t][r] of each 16x16 tile
