@@ -549,12 +549,15 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       // Body j's articulated inertia IA arrives from its children; the
       // fingers start from their own inertia, fold into the palm's (IA8), the
       // palm and the chain bodies fold into their parent's (IAc).  Three loops
-      // with the source and destination fixed, so no per-body selects.
+      // with the source and destination fixed, so no per-body selects.  The
+      // parent's bias force receives its child's share in registers (pA8 for
+      // the palm, pAc along the chain) instead of a round trip through LDS.
       Sym6 IA8 = inertia_of(sk, PALM);
       Sym6 IAc = IA8;
-      auto pass2 = [&](int j, Sym6 &IA, auto into_palm) {
+      SV pA8 = L.sv_at(R_P + 6 * PALM), pAc;
+      auto pass2 = [&](int j, Sym6 &IA, const SV &pA_in, auto into_palm) {
         constexpr bool TO_PALM = decltype(into_palm)::value;
-        const SV pAj = L.sv_at(R_P + 6 * j);
+        const SV pAj = pA_in;
         const float qj = L.at(R_Q + j), qdj = L.at(R_QD + j);
         const float lim = sc.j_inom[j] * sc.accel_max;
         const float tq = fmaxf(-lim, fminf(lim, sc.j_inom[j] * (wc * wc * (L.at(qref_row(j)) - qj) - 2.0f * zeta * wc * qdj)));
@@ -573,10 +576,11 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
           auto fold = [&](auto axis) {
             constexpr int K = decltype(axis)::value;
             const Sym6 Ip = congruence_k<K>(X, IA);
-            L.sv_put(R_P + 6 * p, L.sv_at(R_P + 6 * p) + x_force_T_k<K>(X, pa));
             if constexpr (TO_PALM) {
+              pA8 = pA8 + x_force_T_k<K>(X, pa);
               sym_add(IA8, Ip);
             } else {
+              pAc = L.sv_at(R_P + 6 * p) + x_force_T_k<K>(X, pa);
               IAc = inertia_of(sk, p);
               sym_add(IAc, Ip);
             }
@@ -588,10 +592,10 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       };
       for (int j = FR; j >= FL; --j) {
         Sym6 IA = inertia_of(sk, j);
-        pass2(j, IA, BoolK<true>());
+        pass2(j, IA, L.sv_at(R_P + 6 * j), BoolK<true>());
       }
-      pass2(PALM, IA8, BoolK<false>());
-      for (int j = PALM - 1; j >= 0; --j) pass2(j, IAc, BoolK<false>());
+      pass2(PALM, IA8, pA8, BoolK<false>());
+      for (int j = PALM - 1; j >= 0; --j) pass2(j, IAc, pAc, BoolK<false>());
 
       // ---- ABA pass 3 (root to leaves): accelerations and the joint update ----
       auto pass3 = [&](int j, const SV &a_parent) {
