@@ -36,9 +36,9 @@ DEFAULT_WORKLOAD = "pickplace"
 # scaled by the copy-kernel calibration), keyed by workload; valid only while
 # the rollout sources hash to the recorded value.
 MEASURED_TRAFFIC = {
-    # rollout of 1024 pick-and-place plans over 2000 steps: FETCH_SIZE 856.75 KiB x 2.0
+    # rollout of 1024 pick-and-place plans over 2000 steps: FETCH_SIZE 851.75 KiB x 2.0
     # + WRITE_SIZE 5.5 KiB x 1.0 (a 256 MiB copy reads as 131083.5 / 262144 KiB)
-    "pickplace": {"bytes_per_launch": int((856.75 * 2.0 + 5.5 * 1.0) * 1024), "src_hash": "0125f9437e43f2c3"},
+    "pickplace": {"bytes_per_launch": int((851.75 * 2.0 + 5.5 * 1.0) * 1024), "src_hash": "8ed86696b9e08ccd"},
 }
 
 _KERNEL_FILES = ["rollout.hip", "push_env.hpp", "robot_env.hpp", "robot_dyn.hpp", "rigid.hpp", "devmath.hpp",
