@@ -7,7 +7,7 @@ line with env-steps/s (one env-step = one control step dt of one environment,
 with all its physics substeps), CE iterations/s, the roofline of the rollout
 kernel and the CPU oracle's throughput on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--settle-steps N]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--settle-steps N] [--lanes auto|1|2|4|8]
 
 Workloads: pickplace (the default: 1024 plans x 2000 steps), push, movepush,
 pickplace_paper and pickplace_box (iteration-0 regions, n_env schedule),
@@ -85,6 +85,22 @@ def _valu_ceiling():
     """The device's measured unpacked FP32 FMA rate (TFLOP/s): the ceiling of the rollout's arithmetic."""
     from paper_2512_11571_amd.binding import valu_fma_rate
     return valu_fma_rate() / 1e12
+
+
+def auto_lanes(scene, pop, scenarios):
+    """Lanes per environment for a single robot instance: the most (8, 4, 2 or
+    1) whose waves still fit one per SIMD (64 lanes a wave, 4 SIMDs a CU), and
+    no more than the object's world tests (ground and static boxes; at least
+    the four finger-object tests) give work to."""
+    import torch
+    if scene["kind"] == "push":
+        return 1
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    cap = 8 if len(scene.get("static_boxes", [])) + 1 > 4 else 4
+    for G in (8, 4, 2):
+        if G <= cap and scenarios * G <= 64 and -(-pop * scenarios * G // 64) <= simds:
+            return G
+    return 1
 
 
 def bench_batch(a):
@@ -357,6 +373,9 @@ def main():
                     help="robot workloads: stop a rollout once its plan has ended and the object has rested this "
                          "many control steps (0: every rollout runs the full horizon); throughput then counts the "
                          "steps actually simulated")
+    ap.add_argument("--lanes", default="auto",
+                    help="lanes per environment of a single robot instance (1, 2, 4, 8; auto: the most whose "
+                         "waves fit one per SIMD)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the known-size "
                          "reference for the HBM byte counters) and exit")
@@ -405,7 +424,9 @@ def main():
     cost = torch.empty(pop, dtype=torch.float32, device=dev)
     tier = torch.empty(pop, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
-    with Context(w, seed=a.seed) as c:
+    R = max(1, sc.get("domain_randomization", {}).get("scenarios", 1))
+    lanes = auto_lanes(sc, pop, R) if a.lanes == "auto" else int(a.lanes)
+    with Context(w, seed=a.seed, lanes=lanes) as c:
         def step(j, evs=None):
             n = c.pop_at(j)                    # n_env(j): pop unless the workload has a schedule
             c.cem_sample(j, Z, stream)
@@ -433,7 +454,6 @@ def main():
         roll_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
         mu, S = c.get_theta()
 
-    R = max(1, sc.get("domain_randomization", {}).get("scenarios", 1))
     full = sum(pops) * H * R
     assert env_steps <= full, (env_steps, full)   # fewer only where rollouts stopped early or diverged
     value = env_steps / elapsed
@@ -444,7 +464,7 @@ def main():
     ceiling = _valu_ceiling()
     tr = MEASURED_TRAFFIC.get(a.workload)
     traffic = (tr["bytes_per_launch"] if tr and tr.get("src_hash") == _src_hash(a.workload)
-               and not sc.get("settle_steps", 0) else None)
+               and tr.get("lanes", 1) == lanes and not sc.get("settle_steps", 0) else None)
     out = {
         "metric": "env-steps/s (CE iterations/s alongside)",
         "value": value,
@@ -462,7 +482,7 @@ def main():
         "config": {"workload": a.workload, "pop": pop, "horizon": H, "substeps": sc["substeps"], "dim": D,
                    "n_elite": cem["n_elite"], "dt": sc["dt"], "seed": a.seed,
                    "settle_steps": sc.get("settle_steps", 0), "pop_schedule": sched,
-                   "init_region": bool(cem.get("init_region")), "dr_scenarios": R},
+                   "init_region": bool(cem.get("init_region")), "dr_scenarios": R, "lanes_per_env": lanes},
         "env_steps_simulated": env_steps,
         "env_steps_full_horizon": full,
         "rollout_kernel_ms": roll_avg_s * 1e3,

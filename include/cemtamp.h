@@ -164,7 +164,13 @@ typedef struct cem_problem {
   int32_t pop;                  /* n_env: samples per iteration, 1..65536          */
   int32_t n_elite;              /* N_e, 1..min(pop, 256)                           */
   int32_t cov_mode;             /* 0 diagonal, 1 full                              */
-  int32_t reserved;
+  /* Lanes of a wave that share one environment of a robot scene (0 or 1: one
+   * lane each; 2, 4 or 8: the lanes split the environment's contact tests and
+   * sum their forces).  An implementation choice, not part of Alg. 1: it
+   * fills more of the device when pop is small, and moves the FP32 rounding
+   * of the contact sums.  Push scenes and batches take 0 or 1 only;
+   * lanes_per_env * dr_scenarios <= 64.  Else CEM_E_ARG. */
+  int32_t lanes_per_env;
   const double *mu0, *cov0;
   uint64_t seed;                /* Philox key                                      */
   uint32_t instance;            /* Philox counter word 3 (task instance id)        */

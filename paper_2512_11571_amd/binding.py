@@ -75,7 +75,7 @@ class CemInitRegion(ctypes.Structure):
 class CemProblem(ctypes.Structure):
     _fields_ = [
         ("scene", ctypes.POINTER(CemScene)),
-        ("pop", _i), ("n_elite", _i), ("cov_mode", _i), ("reserved", _i),
+        ("pop", _i), ("n_elite", _i), ("cov_mode", _i), ("lanes_per_env", _i),
         ("mu0", ctypes.POINTER(ctypes.c_double)), ("cov0", ctypes.POINTER(ctypes.c_double)),
         ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
         ("pop_final", _i), ("pop_ramp_iters", _i),
@@ -279,8 +279,9 @@ def _np_ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def make_problem(workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None, cov0=None):
-    """(cem_problem, keep-alive list) for a workload dict."""
+def make_problem(workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None, cov0=None, lanes=None):
+    """(cem_problem, keep-alive list) for a workload dict.  `lanes` (else the
+    workload's cem.lanes_per_env, else 1) is the lanes per environment."""
     cem = workload["cem"]
     scene = make_scene(workload)
     mu0 = np.ascontiguousarray(mu0 if mu0 is not None else cem["mu0"], np.float64)
@@ -295,6 +296,7 @@ def make_problem(workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None,
     p.mu0 = mu0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.cov0 = cov0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.seed, p.instance = int(seed), int(instance)
+    p.lanes_per_env = int(lanes if lanes is not None else cem.get("lanes_per_env", 0))
     keep = [scene, mu0, cov0]
     sch = cem.get("pop_schedule")
     if sch:
@@ -335,14 +337,15 @@ def _result_dict(res, D):
 class Context:
     """One CE problem on the current device (wraps cem_ctx*)."""
 
-    def __init__(self, workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None, cov0=None, handle=None):
+    def __init__(self, workload, seed=0, instance=0, pop=None, n_elite=None, mu0=None, cov0=None, handle=None,
+                 lanes=None):
         self.workload = workload
         self.kind = workload["scene"]["kind"]
         self.D = DIM[self.kind]
         if handle is not None:          # borrowed from a batch, which owns it
             self.h, self._owned = handle, False
             return
-        p, self._keep = make_problem(workload, seed, instance, pop, n_elite, mu0, cov0)
+        p, self._keep = make_problem(workload, seed, instance, pop, n_elite, mu0, cov0, lanes)
         self.pop, self.n_elite = p.pop, p.n_elite
         h = ctypes.c_void_p()
         rc = lib().cem_init(ctypes.byref(p), ctypes.byref(h))

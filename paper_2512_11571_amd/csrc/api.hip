@@ -148,6 +148,7 @@ InstDesc desc_of(cem_ctx *c, const float *Z, int pop, float *cost, uint8_t *tier
   d.D = c->D;
   d.iters = 1 << 30;
   d.scen = scenarios(c->scene);
+  d.lanes = c->lanes;
   return d;
 }
 
@@ -255,6 +256,10 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
   if (p->pop_final != 0 && (p->pop_final < p->n_elite || p->pop_final > p->pop || p->pop_ramp_iters < 1))
     return CEM_E_ARG;
   if (p->init_region && check_region(*p->init_region, D)) return CEM_E_ARG;
+  const int lanes = p->lanes_per_env <= 1 ? 1 : p->lanes_per_env;
+  if (p->lanes_per_env < 0 || (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) ||
+      (lanes > 1 && p->scene->kind == CEM_SCENE_PUSH) || lanes * scenarios(*p->scene) > 64)
+    return CEM_E_ARG;
 
   cem_ctx *c = new (std::nothrow) cem_ctx();
   if (!c) return CEM_E_ALLOC;
@@ -265,6 +270,7 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
   c->cov_mode = p->cov_mode;
   c->pop_final = p->pop_final;
   c->pop_ramp = p->pop_final ? p->pop_ramp_iters : 0;
+  c->lanes = lanes;
   c->seed = p->seed;
   c->inst = p->instance;
   static std::atomic<uint64_t> next_serial{1};
@@ -599,7 +605,8 @@ int cem_batch_init(const cem_problem *problems, const int32_t *iters, int32_t n,
   *out = nullptr;
   if (!problems || !iters || n < 1 || n > 4096) return CEM_E_ARG;
   for (int i = 0; i < n; ++i)
-    if (iters[i] < 0 || iters[i] > MAX_STATS_ITERS || problems[i].pop_final != 0) return CEM_E_ARG;
+    if (iters[i] < 0 || iters[i] > MAX_STATS_ITERS || problems[i].pop_final != 0 || problems[i].lanes_per_env > 1)
+      return CEM_E_ARG;
   cem_batch *b = new (std::nothrow) cem_batch();
   if (!b) return CEM_E_ALLOC;
   int rc = CEM_OK;

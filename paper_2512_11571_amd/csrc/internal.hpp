@@ -60,7 +60,8 @@ struct InstDesc {
   float *pose;      // pop x 7, nullable
   float *stats;     // iteration stats rows (batched refit), nullable
   int32_t kind, pop, D, iters;  // iters: iteration cap in batched runs
-  int32_t scen, pad;            // scenarios per row (1: no domain randomisation); pop * scen environments
+  int32_t scen;                 // scenarios per row (1: no domain randomisation); pop * scen environments
+  int32_t lanes;                // lanes per environment (1, 2, 4); pop * scen * lanes lanes
 };
 // Up to 64 environments [env0, env0 + n) of instance `inst`.
 struct WorkItem {
@@ -113,6 +114,7 @@ struct cem_ctx {
   hipStream_t own = nullptr;
   hipGraphExec_t iter_graph = nullptr;
   int pop_final = 0, pop_ramp = 0;  // n_env schedule (pop_final 0: none)
+  int lanes = 1;                    // lanes per environment
   uint64_t serial = 0;  // unique per context in the process (host addresses are reused after cem_free)
   std::string err;
 };

@@ -92,6 +92,22 @@ __device__ __forceinline__ void c_put(const Lds &L, int j, SV c) {
     L.at(r) = c.b.x; L.at(r + 1) = c.b.y; L.at(r + 2) = c.b.z;
   }
 }
+// Sum over the G (1, 2, 4 or 8) adjacent lanes that share an environment, by
+// a butterfly: quad permutations for lane distances 1 and 2, a swizzle (xor 4
+// within 32 lanes) for 4.  Each level adds the same two operands on both
+// lanes of a pair, so every lane of the group ends with the same bits and the
+// group's lanes keep identical state.  The group's lanes are all active or
+// all inactive.
+__device__ __forceinline__ float group_sum(float v, int G) {
+  if (G >= 2) v = v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+  if (G >= 4) v = v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+  if (G >= 8) v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
+  return v;
+}
+__device__ __forceinline__ V3f group_sum(V3f v, int G) {
+  return v3(group_sum(v.x, G), group_sum(v.y, G), group_sum(v.z, G));
+}
+
 // Joint reference row (both fingers share one).
 __device__ __forceinline__ int qref_row(int j) { return R_QREF + (j < FL ? j : FL); }
 
@@ -109,10 +125,16 @@ struct EnvOut {
 // coefficients) and mass `om`, and (TRACE) writes its per-step trace.
 // `lds_mem` is the block's R_ROWS x PP_LANES float array and `lane` this
 // lane's column in it.  The scene and its derived constants come from `st`.
+// G adjacent lanes (1, 2, 4 or 8; gi this lane's place among them) run the
+// same environment: each keeps the whole state, takes every G-th contact test
+// of the object and the base against the world, and a share of the
+// finger-object tests (G 2: one finger; G 4, 8: one finger, one direction);
+// the forces are then summed over the group.  With G = 1 the sums run in the
+// original order.
 template <bool TRACE>
 __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restrict__ Z, long env, float mu_obj,
-                                             float om, float *lds_mem, int lane, float *__restrict__ trace,
-                                             int trace_steps) {
+                                             float om, float *lds_mem, int lane, int gi, int G,
+                                             float *__restrict__ trace, int trace_steps) {
   CScene &sc = st->scene;
   CConsts &sk = st->sk;
   const Lds L{lds_mem, lane};
@@ -405,8 +427,13 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       OB.R = rot_of(ob.q);
       OB.h = ohe;
       Wrench W{v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)};
-      box_ground(ob, OB.R, ohe, kc, damp, mu_o_ground, eps2, W);
-      for (int b = 0; b < sc.n_static; ++b) {
+      // test u: 0 the ground, 1 + b static box b; this lane takes every G-th
+      for (int u = gi; u <= sc.n_static; u += G) {
+        if (u == 0) {
+          box_ground(ob, OB.R, ohe, kc, damp, mu_o_ground, eps2, W);
+          continue;
+        }
+        const int b = u - 1;
         const Box SB = static_box(sc, sk, b);
         const float mu = mu_drawn ? mu_obj : (sc.st_ramp[b] ? sc.mu_ramp : sc.mu_static);
         const Rel r = rel_of(OB, SB);
@@ -490,7 +517,7 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
             fm = fm + cross(x - pw2, F);
             ff = ff + F;
           };
-          for (int b = 0; b < sc.n_static; ++b) {
+          for (int b = gi; b < sc.n_static; b += G) {
             const Box SB = static_box(sc, sk, b);
             const Rel r = rel_of(LB, SB);
             if (face_separated(r, LB.h, SB.h)) continue;
@@ -501,10 +528,21 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
               link_f(x, -contact_force(true, n, d, v3(0.0f, 0.0f, 0.0f) - link_v(x), kc, damp, sc.mu_static, eps2));
             });
           }
+          if (G > 1) {
+            fm = group_sum(fm, G);
+            ff = group_sum(ff, G);
+          }
           L.sv_put(R_P + 6 * BASEB, L.sv_at(R_P + 6 * BASEB) - sv(mulT(Rw2, fm), mulT(Rw2, ff)));
         }
-        // the fingers against the object (their pose again from the palm's)
-        for (int j = FL; j <= FR; ++j) {
+        // the fingers against the object (their pose again from the palm's);
+        // G 1 takes both fingers, G 2 finger FL + gi, G 4 and 8 finger
+        // FL + gi / 2 in one direction (bit 0 of dirs: finger vertices in the
+        // object, bit 1: object vertices in the finger) on lanes gi < 4
+        const int jf0 = G == 1 ? FL : FL + (G == 2 ? gi : (gi >> 1) & 1), jf1 = G == 1 ? FR : jf0;
+        const int dirs = G <= 2 ? 3 : gi < 4 ? 1 << (gi & 1) : 0;
+        SV part = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));  // G > 1: this lane's body-frame share
+        bool part_any = false;
+        for (int j = jf0; j <= jf1; ++j) {
           const JT X = joint_of(sc, j, L.at(R_Q + j));
           const M3f Rb = rot_right(Rw, X);
           const V3f pb = pw + mul(Rw, X.r);
@@ -521,7 +559,7 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
           bool any = false;
           if (!face_separated(r, LB.h, ohe)) {
             // finger vertices in the object (A = finger, B = object)
-            verts_in_box(r, LB.h, OB, [&](V3f x, V3f n, float d) {
+            if (dirs & 1) verts_in_box(r, LB.h, OB, [&](V3f x, V3f n, float d) {
               const V3f ro = x - ob.p;
               const V3f F = contact_force(true, n, d, link_v(x) - (ob.v + cross(ob.w, ro)), kc, damp, mu_o_tool, eps2);
               link_f(x, F);
@@ -529,7 +567,7 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
               any = true;
             });
             // object vertices in the finger (A = object, B = finger)
-            verts_in_box(rel_swap(r), ohe, LB, [&](V3f x, V3f n, float d) {
+            if (dirs & 2) verts_in_box(rel_swap(r), ohe, LB, [&](V3f x, V3f n, float d) {
               const V3f ro = x - ob.p;
               const V3f F = contact_force(true, n, d, (ob.v + cross(ob.w, ro)) - link_v(x), kc, damp, mu_o_tool, eps2);
               apply(W, ro, F);
@@ -537,11 +575,34 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
               any = true;
             });
           }
-          if (last) {
-            if (j == FL) touchL = any;
-            else touchR = any;
+          if (G == 1) {
+            if (last) {
+              if (j == FL) touchL = any;
+              else touchR = any;
+            }
+            L.sv_put(R_P + 6 * j, L.sv_at(R_P + 6 * j) - sv(mulT(Rb, fm), mulT(Rb, ff)));
+          } else {
+            part = sv(mulT(Rb, fm), mulT(Rb, ff));
+            part_any = any;
           }
-          L.sv_put(R_P + 6 * j, L.sv_at(R_P + 6 * j) - sv(mulT(Rb, fm), mulT(Rb, ff)));
+        }
+        if (G > 1) {
+          // each finger's force from the lanes that tested it (the others add
+          // exact zeros), the object's wrench from the whole group
+          const V3f z = v3(0.0f, 0.0f, 0.0f);
+          const bool left = jf0 == FL;
+          const SV pL = sv(group_sum(left ? part.a : z, G), group_sum(left ? part.b : z, G));
+          const SV pR = sv(group_sum(left ? z : part.a, G), group_sum(left ? z : part.b, G));
+          const float aL = group_sum(left && part_any ? 1.0f : 0.0f, G);
+          const float aR = group_sum(!left && part_any ? 1.0f : 0.0f, G);
+          if (last) {
+            touchL = aL > 0.0f;
+            touchR = aR > 0.0f;
+          }
+          L.sv_put(R_P + 6 * FL, L.sv_at(R_P + 6 * FL) - pL);
+          L.sv_put(R_P + 6 * FR, L.sv_at(R_P + 6 * FR) - pR);
+          W.f = group_sum(W.f, G);
+          W.t = group_sum(W.t, G);
         }
       }
 
@@ -613,7 +674,7 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       for (int j = FL; j <= FR; ++j) pass3(j, a_prev);          // the fingers, from the palm's acceleration
       integrate(ob, W, inv_om, oIb, gv, h);
     }
-    if (TRACE && t < trace_steps) {
+    if (TRACE && t < trace_steps && gi == 0) {
       float *o = trace + ((long)env * trace_steps + t) * CEM_TRACE_ROBOT;
       o[0] = ob.p.x; o[1] = ob.p.y; o[2] = ob.p.z;
       o[3] = ob.q.w; o[4] = ob.q.x; o[5] = ob.q.y; o[6] = ob.q.z;

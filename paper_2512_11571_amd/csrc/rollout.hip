@@ -1,7 +1,8 @@
 // The rollout launch (evaluation step of Alg. 1) for one or many task instances.
 //
 // Work is cut into items of up to 64 environments of one instance (one wave,
-// one environment per lane).  A single instance runs one workgroup per item.
+// one environment per lane; a single robot instance may give each environment
+// 2, 4 or 8 adjacent lanes, which split its contact tests).  A single instance runs one workgroup per item.
 // A batch of instances (independent CE problems with their own scene kind,
 // population and horizon) runs as one persistent launch: each workgroup pulls
 // the next item from an atomic queue until the list is exhausted, so the items
@@ -45,20 +46,25 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
       d.pop = di.pop;
       d.iters = di.iters;
       d.scen = di.scen;
+      d.lanes = 1;
       env0 = w.env0;
       n = w.n;
     } else {
       d = single;
       env0 = it * 64;
-      n = min(64, d.pop * d.scen - env0);
+      n = min(64, d.pop * d.scen * d.lanes - env0);
     }
     CDevState *st = (CDevState *)d.st;
     const bool active = !(check_iter && st->iter >= d.iters);  // wave-uniform
     const bool robot = d.kind != CEM_SCENE_PUSH;                // wave-uniform
     const int R = d.scen;  // scenarios per row: a power of two <= 64, aligned to the item (wave-uniform)
+    const int G = d.lanes;  // lanes per environment: 1, 2, 4 or 8, with R * G <= 64 (wave-uniform)
     int steps = 0;
     EnvOut o{0.0f, 0, 0, {0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f}};
-    const long env = env0 + lane, row = env / R;
+    // lane layout: ((row * R) + scenario) * G + g, g the lane's place in its environment's group
+    const int lg = G == 8 ? 3 : G == 4 ? 2 : G == 2 ? 1 : 0;
+    const long vl = env0 + lane, env = vl >> lg, row = env / R;
+    const int g = (int)(vl & (G - 1));
     if (active && lane < n) {
       if (!robot) {
         push_env<TRACE>(st->scene, st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
@@ -70,22 +76,22 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
           if (st->scene.dr_mu_hi > 0.0f) mu = st->dr_mu[r];
           if (st->scene.dr_mass_hi > 0.0f) m = st->dr_mass[r];
         }
-        o = robot_env<TRACE>(st, d.Z, row, mu, m, lds, lane, trace, trace_steps);
-        steps = o.steps;
+        o = robot_env<TRACE>(st, d.Z, row, mu, m, lds, lane, g, G, trace, trace_steps);
+        steps = g == 0 ? o.steps : 0;
       }
     }
     if (active && robot) {
       // a row's scenarios sit in R adjacent lanes: the worst tier, and the
       // mean or the largest cost, by a fixed butterfly over the group
       const bool use_max = st->scene.dr_reduce != 0;
-      for (int m = 1; m < R; m <<= 1) {
+      for (int m = G; m < R * G; m <<= 1) {
         const float oc = __shfl_xor(o.cost, m);
         const int ot = __shfl_xor(o.tier, m);
         o.cost = use_max ? fmaxf(o.cost, oc) : o.cost + oc;
         o.tier = max(o.tier, ot);
       }
       if (R > 1 && !use_max) o.cost = o.cost * (1.0f / (float)R);
-      if (lane < n && (env & (R - 1)) == 0) {
+      if (lane < n && (env & (R - 1)) == 0 && g == 0) {
         if (d.cost) d.cost[row] = o.cost;
         if (d.tier) d.tier[row] = (uint8_t)o.tier;
         if (d.pose)
@@ -166,7 +172,10 @@ __global__ void pack_dataset_kernel(const float *__restrict__ Z, const float *__
 
 hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s) {
   if (d.scen < 1 || d.scen > 64 || (d.scen & (d.scen - 1))) return hipErrorInvalidValue;
-  const int n_items = (d.pop * d.scen + 63) / 64;
+  if ((d.lanes != 1 && d.lanes != 2 && d.lanes != 4 && d.lanes != 8) || d.scen * d.lanes > 64 ||
+      (d.lanes > 1 && d.kind == CEM_SCENE_PUSH))
+    return hipErrorInvalidValue;
+  const int n_items = (d.pop * d.scen * d.lanes + 63) / 64;
   if (n_items == 0) return hipSuccess;
   if (trace)
     hipLaunchKernelGGL(rollout_items_kernel<true>, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items,

@@ -122,3 +122,20 @@ def test_options_are_validated_before_touching_the_device():
     w = copy.deepcopy(workloads.load("push"))
     w["scene"]["domain_randomization"] = {"scenarios": 4, "mu": [0.3, 0.7]}
     _rejects(binding, w, 2)                      # robot scenes only
+
+
+def test_lanes_per_env_is_validated_before_touching_the_device():
+    import copy
+    from paper_2512_11571_amd import binding, workloads
+    pp = workloads.load("pickplace")
+    for lanes in (-1, 3, 16, 64):
+        _rejects(binding, pp, 1, lanes=lanes)
+    _rejects(binding, workloads.load("push"), 1, lanes=2)    # robot scenes only
+    w = copy.deepcopy(workloads.load("movepush"))
+    w["scene"]["domain_randomization"] = {"scenarios": 32, "mu": [0.3, 0.7]}
+    _rejects(binding, w, 1, lanes=4)                        # lanes x scenarios <= 64
+    insts = [{"workload": copy.deepcopy(pp), "seed": 0, "instance": 0, "iters": 1}]
+    insts[0]["workload"]["cem"]["lanes_per_env"] = 2
+    with pytest.raises(binding.CemError) as e:
+        binding.Batch(insts)                                 # batches run one lane per environment
+    assert e.value.code == 1
