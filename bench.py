@@ -36,9 +36,10 @@ DEFAULT_WORKLOAD = "pickplace"
 # scaled by the copy-kernel calibration), keyed by workload; valid only while
 # the rollout sources hash to the recorded value.
 MEASURED_TRAFFIC = {
-    # rollout of 1024 pick-and-place plans over 2000 steps: FETCH_SIZE 851.75 KiB x 2.0
-    # + WRITE_SIZE 5.5 KiB x 1.0 (a 256 MiB copy reads as 131083.5 / 262144 KiB)
-    "pickplace": {"bytes_per_launch": int((851.75 * 2.0 + 5.5 * 1.0) * 1024), "src_hash": "8ed86696b9e08ccd"},
+    # rollout of 1024 pick-and-place plans over 2000 steps, 4 lanes per plan: FETCH_SIZE
+    # 849.25 KiB x 2.0 + WRITE_SIZE 8.0 KiB x 1.0 (a 256 MiB copy reads as 131083.5 / 262144 KiB)
+    "pickplace": {"bytes_per_launch": int((849.25 * 2.0 + 8.0 * 1.0) * 1024), "lanes": 4,
+                  "src_hash": "617cfaa0d78f3588"},
 }
 
 _KERNEL_FILES = ["rollout.hip", "push_env.hpp", "robot_env.hpp", "robot_dyn.hpp", "rigid.hpp", "devmath.hpp",
@@ -210,8 +211,9 @@ def bench_modes(a):
         t2 = w["scene"]["static_boxes"][1]                 # table 2: its near edge ends the obstacle
         far_x = t2["center"][0] - t2["half"][0]
         costs, tiers, modes, times, curves = [], [], {}, [], []
+        lanes = auto_lanes(w["scene"], w["cem"]["pop"], 1) if a.lanes == "auto" else int(a.lanes)
         for seed in w["cem"]["seeds"]:
-            with Context(w, seed=seed) as c:
+            with Context(w, seed=seed, lanes=lanes) as c:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 r = c.plan_solve(iters)
@@ -229,7 +231,7 @@ def bench_modes(a):
         out_scenes[name] = {
             "iterations": iters, "seeds": len(costs), "feasible_seeds": len(feas),
             "median_best_cost_s": float(np.median(feas)) if feas else None,
-            "modes": modes, "seconds_per_solve": float(np.median(times)),
+            "modes": modes, "seconds_per_solve": float(np.median(times)), "lanes_per_env": lanes,
             "median_best_so_far_by_iteration": [float(v) for v in np.median(np.array(curves), axis=0)],
         }
     ramp = out_scenes["pickplace_paper"]
@@ -272,10 +274,13 @@ def bench_surrogate(a):
     env_steps_data = sum(i["workload"]["cem"]["pop"] * i["iters"] * i["workload"]["scene"]["horizon"] for i in insts)
     log("dataset: %d rows in %.1f s" % (n, t_data))
 
+    # both arms simulate n_sim plans per iteration, with the same lanes per environment
+    lanes = auto_lanes(base["scene"], ev["n_sim"], 1) if a.lanes == "auto" else int(a.lanes)
+
     def solve(seed, screened, m):
         cem = dict(base["cem"], n_elite=ev["n_elite"], pop=ev["screen_pop"] if screened else ev["n_sim"])
         w = dict(base, cem=cem)
-        with Context(w, seed=seed) as c:
+        with Context(w, seed=seed, lanes=lanes) as c:
             torch.cuda.synchronize()
             t = time.perf_counter()
             r = m.plan_solve_screened(c, ev["iters"], ev["n_sim"]) if screened else c.plan_solve(ev["iters"])
@@ -344,7 +349,7 @@ def bench_surrogate(a):
         "dtype": "f32 rollouts, bf16 MFMA surrogate (f32 accumulate)",
         "data": "synthetic (seeded pick-and-place instances and Philox samples)",
         "config": {"workload": "surrogate (pick-and-place)", "n_sim": ev["n_sim"], "screen_pop": ev["screen_pop"],
-                   "n_elite": ev["n_elite"], "iters": ev["iters"], "seeds": ev["seeds"],
+                   "n_elite": ev["n_elite"], "iters": ev["iters"], "seeds": ev["seeds"], "lanes_per_env": lanes,
                    "dataset_rows": n, "dataset_env_steps": env_steps_data},
         "target_cost": target, "target_band": band,
         "median_best_cost_per_iter": {"plain": [float(x) for x in med[False]],
