@@ -130,11 +130,13 @@ struct EnvOut {
 // of the object and the base against the world, and a share of the
 // finger-object tests (G 2: one finger; G 4, 8: one finger, one direction);
 // the forces are then summed over the group.  With G = 1 the sums run in the
-// original order.
-template <bool TRACE>
+// original order; the MULTI = false instance compiles G = 1 in.
+template <bool TRACE, bool MULTI>
 __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restrict__ Z, long env, float mu_obj,
-                                             float om, float *lds_mem, int lane, int gi, int G,
+                                             float om, float *lds_mem, int lane, int gi_in, int G_in,
                                              float *__restrict__ trace, int trace_steps) {
+  // !MULTI: one lane per environment, known at compile time
+  const int G = MULTI ? G_in : 1, gi = MULTI ? gi_in : 0;
   CScene &sc = st->scene;
   CConsts &sk = st->sk;
   const Lds L{lds_mem, lane};

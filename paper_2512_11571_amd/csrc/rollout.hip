@@ -17,7 +17,7 @@
 namespace cem {
 namespace {
 
-template <bool TRACE>
+template <bool TRACE, bool MULTI>
 __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, const InstDesc *__restrict__ insts,
                                                            const WorkItem *__restrict__ items, int n_items,
                                                            int *__restrict__ queue, int check_iter,
@@ -58,7 +58,8 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
     const bool active = !(check_iter && st->iter >= d.iters);  // wave-uniform
     const bool robot = d.kind != CEM_SCENE_PUSH;                // wave-uniform
     const int R = d.scen;  // scenarios per row: a power of two <= 64, aligned to the item (wave-uniform)
-    const int G = d.lanes;  // lanes per environment: 1, 2, 4 or 8, with R * G <= 64 (wave-uniform)
+    // lanes per environment: 1, 2, 4 or 8, with R * G <= 64 (wave-uniform; 1 unless MULTI)
+    const int G = MULTI ? d.lanes : 1;
     int steps = 0;
     EnvOut o{0.0f, 0, 0, {0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f}};
     // lane layout: ((row * R) + scenario) * G + g, g the lane's place in its environment's group
@@ -76,7 +77,7 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
           if (st->scene.dr_mu_hi > 0.0f) mu = st->dr_mu[r];
           if (st->scene.dr_mass_hi > 0.0f) m = st->dr_mass[r];
         }
-        o = robot_env<TRACE>(st, d.Z, row, mu, m, lds, lane, g, G, trace, trace_steps);
+        o = robot_env<TRACE, MULTI>(st, d.Z, row, mu, m, lds, lane, g, G, trace, trace_steps);
         steps = g == 0 ? o.steps : 0;
       }
     }
@@ -108,6 +109,8 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
     if (!queue) break;
   }
 }
+
+using RolloutKernel = void (*)(InstDesc, const InstDesc *, const WorkItem *, int, int *, int, float *, int);
 
 // Scene constants used every substep, derived once per context: the static
 // boxes' rotations Rz(yaw) Ry(pitch) and each body's spatial inertia about its
@@ -177,12 +180,11 @@ hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_step
     return hipErrorInvalidValue;
   const int n_items = (d.pop * d.scen * d.lanes + 63) / 64;
   if (n_items == 0) return hipSuccess;
-  if (trace)
-    hipLaunchKernelGGL(rollout_items_kernel<true>, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items,
-                       nullptr, 0, trace, trace_steps);
-  else
-    hipLaunchKernelGGL(rollout_items_kernel<false>, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items,
-                       nullptr, 0, nullptr, 0);
+  const bool multi = d.lanes > 1;
+  const RolloutKernel k = trace ? (multi ? rollout_items_kernel<true, true> : rollout_items_kernel<true, false>)
+                                : (multi ? rollout_items_kernel<false, true> : rollout_items_kernel<false, false>);
+  hipLaunchKernelGGL(k, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items, nullptr, 0, trace,
+                     trace ? trace_steps : 0);
   return hipGetLastError();
 }
 
@@ -202,8 +204,8 @@ hipError_t launch_rollout_batch(const InstDesc *insts, const WorkItem *items, in
                                 hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, queue);
   InstDesc none{};
-  hipLaunchKernelGGL(rollout_items_kernel<false>, dim3(grid), dim3(64), 0, s, none, insts, items, n_items, queue,
-                     1, nullptr, 0);
+  const RolloutKernel k = rollout_items_kernel<false, false>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, s, none, insts, items, n_items, queue, 1, nullptr, 0);
   return hipGetLastError();
 }
 
