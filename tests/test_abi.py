@@ -139,3 +139,18 @@ def test_lanes_per_env_is_validated_before_touching_the_device():
     with pytest.raises(binding.CemError) as e:
         binding.Batch(insts)                                 # batches run one lane per environment
     assert e.value.code == 1
+
+
+def test_bench_lane_choice():
+    # the most lanes whose waves still fit one per SIMD (1024 SIMDs on MI355X)
+    import bench
+    from paper_2512_11571_amd import workloads
+    pick = lambda name, pop=None, R=1: bench.auto_lanes(workloads.load(name)["scene"],
+                                                        pop or workloads.load(name)["cem"]["pop"], R, simds=1024)
+    assert pick("pickplace") == 4                 # 1024 plans: 64 waves; four object-world tests
+    assert pick("pickplace_paper") == 4           # 3000 plans: 188 waves
+    assert pick("movepush") == 8                  # 8192 plans: 1024 waves; seven object-world tests
+    assert pick("movepush", 8192, 8) == 1         # 65,536 rollouts already fill the chip
+    assert pick("movepush", 16384) == 4
+    assert pick("push") == 1
+    assert pick("pickplace", 65536) == 1

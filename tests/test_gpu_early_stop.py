@@ -9,7 +9,9 @@ fewer steps are simulated.  Against the FP64 oracle with the same option:
 tier and cost on certified rows as for the full horizon, and the total of
 simulated steps within 5 %.  With domain-randomisation scenarios the costs
 still equal the full-horizon ones, and batched instances that stop early give
-the bits and step counts of their single runs.
+the bits and step counts of their single runs.  The cost-and-goal test also
+runs at the lanes per plan the benchmarks use (8 for move-push, 4 for
+pick-and-place).
 """
 import copy
 
@@ -44,10 +46,10 @@ def _early(w):
     return we
 
 
-def _gpu(Context, w, Z, seed):
+def _gpu(Context, w, Z, seed, lanes=1):
     """cost, tier and the control steps the rollouts simulated."""
     n = Z.shape[0]
-    with Context(w, seed=seed, pop=max(n, 64), n_elite=1) as c:
+    with Context(w, seed=seed, pop=max(n, 64), n_elite=1, lanes=lanes) as c:
         assert c.env_steps() == 0
         Zd = torch.from_numpy(np.ascontiguousarray(Z)).to("cuda:0")
         cost = torch.empty(n, dtype=torch.float32, device="cuda:0")
@@ -70,14 +72,14 @@ def test_full_horizon_counts_T_steps_per_rollout(oracle, Context, name):
         assert c.env_steps() == 2 * n * w["scene"]["horizon"]
 
 
-@pytest.mark.parametrize("name", ["movepush", "pickplace"])
-def test_early_stop_keeps_cost_and_goal(oracle, Context, name):
+@pytest.mark.parametrize("name,lanes", [("movepush", 1), ("pickplace", 1), ("movepush", 8), ("pickplace", 4)])
+def test_early_stop_keeps_cost_and_goal(oracle, Context, name, lanes):
     w = workloads.load(name)
     H = w["scene"]["horizon"]
     n = 256
     Z = _rows(oracle, w, 1, n)
-    cf, tf, sf = _gpu(Context, w, Z, 1)
-    ce, te, se = _gpu(Context, _early(w), Z, 1)
+    cf, tf, sf = _gpu(Context, w, Z, 1, lanes)
+    ce, te, se = _gpu(Context, _early(w), Z, 1, lanes)
     assert sf == n * H
     both = np.isfinite(cf) & np.isfinite(ce)
     assert both.mean() >= 0.99
