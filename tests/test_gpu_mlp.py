@@ -176,16 +176,18 @@ def _short_pickplace(pop, n_elite):
     return dict(pp, scene=dict(pp["scene"], horizon=400), cem=dict(pp["cem"], pop=pop, n_elite=n_elite))
 
 
-def test_plan_solve_screened_equals_eager_steps(B):
-    # the captured screened iteration = screen, simulate the kept candidates, refit
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_plan_solve_screened_equals_eager_steps(B, lanes):
+    # the captured screened iteration = screen, simulate the kept candidates,
+    # refit (also with the rollout at 4 lanes per plan, as the A/B runs it)
     w = _short_pickplace(2048, 32)
     n_sim, iters = 256, 2
     with B.Mlp(seed=3, max_rows=2048) as m:
         _screening_setup(B, w, m, np.random.default_rng(9))
-        with B.Context(w, seed=4) as c:
+        with B.Context(w, seed=4, lanes=lanes) as c:
             r = m.plan_solve_screened(c, iters, n_sim)
             mu_g, S_g = c.get_theta()
-        with B.Context(w, seed=4) as c2:
+        with B.Context(w, seed=4, lanes=lanes) as c2:
             Zs = torch.empty((n_sim, 16), dtype=torch.float32, device="cuda:0")
             Ps = torch.empty((n_sim, 8), dtype=torch.float32, device="cuda:0")
             cost = torch.empty(n_sim, dtype=torch.float32, device="cuda:0")
