@@ -91,17 +91,14 @@ def _valu_ceiling():
 def auto_lanes(scene, pop, scenarios, simds=None):
     """Lanes per environment for a single robot instance: the most (8, 4, 2 or
     1) whose waves still fit one per SIMD (64 lanes a wave, 4 SIMDs a CU; the
-    device's unless `simds` is given), and no more than the object's world
-    tests (ground and static boxes; at least the four finger-object tests)
-    give work to."""
+    device's unless `simds` is given)."""
     if scene["kind"] == "push":
         return 1
     if simds is None:
         import torch
         simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
-    cap = 8 if len(scene.get("static_boxes", [])) + 1 > 4 else 4
     for G in (8, 4, 2):
-        if G <= cap and scenarios * G <= 64 and -(-pop * scenarios * G // 64) <= simds:
+        if scenarios * G <= 64 and -(-pop * scenarios * G // 64) <= simds:
             return G
     return 1
 

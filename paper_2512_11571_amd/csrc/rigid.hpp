@@ -41,8 +41,9 @@ __device__ __forceinline__ void apply(Wrench &W, V3f r, V3f F) {
 // corner heights come from the third row of R alone; the lever arm and the
 // force are formed once per corner below the plane of a lane, in ascending
 // corner order, so lanes whose corners below the plane differ share passes.
+// Only the corners in `vmask` (bit i: corner i) are taken.
 __device__ __forceinline__ void box_ground(const FreeBody &b, const M3f &R, V3f he, float k, float damp, float mu,
-                                           float eps2, Wrench &W) {
+                                           float eps2, Wrench &W, unsigned vmask = 0xFFu) {
   const float zx = he.x * R.r2.x, zy = he.y * R.r2.y, zz = he.z * R.r2.z;
   unsigned below = 0u;
 #pragma unroll
@@ -50,6 +51,7 @@ __device__ __forceinline__ void box_ground(const FreeBody &b, const M3f &R, V3f 
     const float rz = ((i & 4) ? zz : -zz) + ((i & 2) ? zy : -zy) + ((i & 1) ? zx : -zx);
     if (-(b.p.z + rz) > 0.0f) below |= 1u << i;
   }
+  below &= vmask;
   while (below != 0u) {  // at most eight passes
     const int i = __builtin_ctz(below);
     below &= below - 1u;

@@ -461,8 +461,9 @@ __device__ __forceinline__ bool face_separated(const Rel &r, V3f hA, V3f hB) {
 // the face search and the contact then run once per inside vertex of a lane,
 // so lanes whose inside vertices differ share passes (the wave runs as many
 // passes as its lane with the most vertices inside, not one per vertex index).
+// Only the vertices in `vmask` (bit i: vertex i) are taken.
 template <class F>
-__device__ __forceinline__ void verts_in_box(const Rel &r, V3f hA, const Box &B, F &&f) {
+__device__ __forceinline__ void verts_in_box(const Rel &r, V3f hA, const Box &B, F &&f, unsigned vmask = 0xFFu) {
   const V3f c0 = hA.x * col(r.M, 0), c1 = hA.y * col(r.M, 1), c2 = hA.z * col(r.M, 2);
   const V3f hb = B.h;
   unsigned inside = 0u;
@@ -471,6 +472,7 @@ __device__ __forceinline__ void verts_in_box(const Rel &r, V3f hA, const Box &B,
     const V3f xb = (r.t + ((i & 4) ? c2 : -c2) + ((i & 2) ? c1 : -c1)) + ((i & 1) ? c0 : -c0);
     if (fabsf(xb.x) < hb.x && fabsf(xb.y) < hb.y && fabsf(xb.z) < hb.z) inside |= 1u << i;
   }
+  inside &= vmask;
   while (inside != 0u) {  // at most eight passes
     const int i = __builtin_ctz(inside);
     inside &= inside - 1u;

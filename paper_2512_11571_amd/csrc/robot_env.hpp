@@ -429,10 +429,15 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       OB.R = rot_of(ob.q);
       OB.h = ohe;
       Wrench W{v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)};
-      // test u: 0 the ground, 1 + b static box b; this lane takes every G-th
-      for (int u = gi; u <= sc.n_static; u += G) {
+      // test u: 0 the ground, 1 + b static box b; this lane takes every G-th,
+      // or, with 8 lanes and at most four tests, every 4th on the half of
+      // the corners that gi / 4 picks (even or odd corner indices)
+      const bool w_halves = G == 8 && sc.n_static + 1 <= 4;
+      const int w_step = w_halves ? 4 : G;
+      const unsigned w_mask = w_halves ? ((gi & 4) ? 0xAAu : 0x55u) : 0xFFu;
+      for (int u = gi & (w_step - 1); u <= sc.n_static; u += w_step) {
         if (u == 0) {
-          box_ground(ob, OB.R, ohe, kc, damp, mu_o_ground, eps2, W);
+          box_ground(ob, OB.R, ohe, kc, damp, mu_o_ground, eps2, W, w_mask);
           continue;
         }
         const int b = u - 1;
@@ -444,12 +449,12 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
         verts_in_box(r, ohe, SB, [&](V3f x, V3f n, float d) {
           const V3f ro = x - ob.p;
           apply(W, ro, contact_force(true, n, d, ob.v + cross(ob.w, ro), kc, damp, mu, eps2));
-        });
+        }, w_mask);
         // static-box vertices in the object (A = static box, the object receives the negative)
         verts_in_box(rel_swap(r), SB.h, OB, [&](V3f x, V3f n, float d) {
           const V3f ro = x - ob.p;
           apply(W, ro, -contact_force(true, n, d, v3(0.0f, 0.0f, 0.0f) - (ob.v + cross(ob.w, ro)), kc, damp, mu, eps2));
-        });
+        }, w_mask);
       }
 
       // ---- ABA pass 1 (root to leaves): poses, velocities, bias terms ----
@@ -519,16 +524,21 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
             fm = fm + cross(x - pw2, F);
             ff = ff + F;
           };
-          for (int b = gi; b < sc.n_static; b += G) {
+          // every G-th static box, or with 8 lanes and at most four boxes
+          // every 4th on half of the corners, as for the object above
+          const bool b_halves = G == 8 && sc.n_static <= 4;
+          const int b_step = b_halves ? 4 : G;
+          const unsigned b_mask = b_halves ? ((gi & 4) ? 0xAAu : 0x55u) : 0xFFu;
+          for (int b = gi & (b_step - 1); b < sc.n_static; b += b_step) {
             const Box SB = static_box(sc, sk, b);
             const Rel r = rel_of(LB, SB);
             if (face_separated(r, LB.h, SB.h)) continue;
             verts_in_box(r, LB.h, SB, [&](V3f x, V3f n, float d) {
               link_f(x, contact_force(true, n, d, link_v(x), kc, damp, sc.mu_static, eps2));
-            });
+            }, b_mask);
             verts_in_box(rel_swap(r), SB.h, LB, [&](V3f x, V3f n, float d) {
               link_f(x, -contact_force(true, n, d, v3(0.0f, 0.0f, 0.0f) - link_v(x), kc, damp, sc.mu_static, eps2));
-            });
+            }, b_mask);
           }
           if (G > 1) {
             fm = group_sum(fm, G);
@@ -537,11 +547,13 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
           L.sv_put(R_P + 6 * BASEB, L.sv_at(R_P + 6 * BASEB) - sv(mulT(Rw2, fm), mulT(Rw2, ff)));
         }
         // the fingers against the object (their pose again from the palm's);
-        // G 1 takes both fingers, G 2 finger FL + gi, G 4 and 8 finger
-        // FL + gi / 2 in one direction (bit 0 of dirs: finger vertices in the
-        // object, bit 1: object vertices in the finger) on lanes gi < 4
+        // G 1 takes both fingers, G 2 finger FL + gi, G 4 finger FL + gi / 2
+        // in one direction (bit 0 of dirs: finger vertices in the object,
+        // bit 1: object vertices in the finger), G 8 the same on half of the
+        // corners
         const int jf0 = G == 1 ? FL : FL + (G == 2 ? gi : (gi >> 1) & 1), jf1 = G == 1 ? FR : jf0;
-        const int dirs = G <= 2 ? 3 : gi < 4 ? 1 << (gi & 1) : 0;
+        const int dirs = G <= 2 ? 3 : 1 << (gi & 1);
+        const unsigned f_mask = G == 8 ? ((gi & 4) ? 0xAAu : 0x55u) : 0xFFu;  // 8 lanes: half the corners each
         SV part = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));  // G > 1: this lane's body-frame share
         bool part_any = false;
         for (int j = jf0; j <= jf1; ++j) {
@@ -567,7 +579,7 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
               link_f(x, F);
               apply(W, ro, -F);
               any = true;
-            });
+            }, f_mask);
             // object vertices in the finger (A = object, B = finger)
             if (dirs & 2) verts_in_box(rel_swap(r), ohe, LB, [&](V3f x, V3f n, float d) {
               const V3f ro = x - ob.p;
@@ -575,7 +587,7 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
               apply(W, ro, F);
               link_f(x, -F);
               any = true;
-            });
+            }, f_mask);
           }
           if (G == 1) {
             if (last) {
