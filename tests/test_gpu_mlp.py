@@ -176,10 +176,10 @@ def _short_pickplace(pop, n_elite):
     return dict(pp, scene=dict(pp["scene"], horizon=400), cem=dict(pp["cem"], pop=pop, n_elite=n_elite))
 
 
-@pytest.mark.parametrize("lanes", [1, 8])
+@pytest.mark.parametrize("lanes", [1, 4])
 def test_plan_solve_screened_equals_eager_steps(B, lanes):
     # the captured screened iteration = screen, simulate the kept candidates,
-    # refit (also with the rollout at 8 lanes per plan, as the A/B runs it)
+    # refit (also with the rollout at 4 lanes per plan, as the A/B runs it)
     w = _short_pickplace(2048, 32)
     n_sim, iters = 256, 2
     with B.Mlp(seed=3, max_rows=2048) as m:

@@ -8,8 +8,9 @@ within two control steps).  The rows: iteration-0 rows of the region and
 Gaussian rows around the ramp plan and around a plan that passes the obstacle
 on its +y side, so that all of psi_g's outcomes occur.  Statistical: the
 median best cost of plan_solve with the region and a reduced schedule over 32
-seeds within 1e-2 relative.  Each test also runs at 8 lanes per plan, the
-launch the paper-setting benchmarks time, against the same oracle runs.
+seeds within 1e-2 relative.  Each test also runs at 4 lanes per plan, the
+launch the paper-setting benchmarks time (the rollouts also at 8), against
+the same oracle runs.
 """
 import copy
 
@@ -82,7 +83,7 @@ def _gpu_rollout(Context, w, Z, trace_steps=0, lanes=1):
         return cost.cpu().numpy().astype(np.float64), tier.cpu().numpy()
 
 
-@pytest.mark.parametrize("lanes", [1, 8])
+@pytest.mark.parametrize("lanes", [1, 4, 8])
 def test_trace_parity_first_100_steps(oracle, box, Context, lanes):
     Z = _rows(oracle, box, 0, 64)
     t0, t1 = _memo("trace", lambda: (oracle.rollout(box, 0, Z, trace_steps=100)[3],
@@ -107,7 +108,7 @@ def _certified(oracle, w, seed, Z):
     return ok, c0, t0
 
 
-@pytest.mark.parametrize("lanes", [1, 8])
+@pytest.mark.parametrize("lanes", [1, 4, 8])
 def test_full_horizon_cost_and_tier_parity(oracle, box, Context, lanes):
     Z = _rows(oracle, box, 1, 128)
     ok, c0, t0 = _memo("certified", lambda: _certified(oracle, box, 1, Z))
@@ -119,7 +120,7 @@ def test_full_horizon_cost_and_tier_parity(oracle, box, Context, lanes):
     assert np.max(np.abs(cg[same] - c0[same])) <= 2 * box["scene"]["dt"] + 1e-6
 
 
-@pytest.mark.parametrize("lanes", [1, 8])
+@pytest.mark.parametrize("lanes", [1, 4])
 def test_plan_solve_median_matches_oracle(oracle, box, Context, lanes):
     w = copy.deepcopy(box)
     w["cem"].update(pop=256, n_elite=16, pop_schedule={"final": 64, "iters": 2})
