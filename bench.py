@@ -119,6 +119,10 @@ def bench_batch(a):
     spec = workloads.load(a.workload)["batch"]
     kinds = list(spec["kinds"])
     insts = workloads.batch_instances(spec)
+    if a.settle_steps:                # early stop on the robot instances
+        for i in insts:
+            if i["workload"]["scene"]["kind"] != "push":
+                i["workload"]["scene"]["settle_steps"] = a.settle_steps
     K = a.steps if a.steps is not None else 3
     cap = min(i["iters"] for i in insts)
     if K > cap:
@@ -144,7 +148,7 @@ def bench_batch(a):
         step_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
         counted = sum(B.instance(k).env_steps() for k in range(len(insts))) - counted0
     env_steps_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"] for i in insts)
-    assert counted <= env_steps_iter * K, (counted, env_steps_iter * K)   # fewer only where rollouts diverged
+    assert counted <= env_steps_iter * K, (counted, env_steps_iter * K)   # fewer only where rollouts stopped early
     fps = {k: workloads.load(k).get("measurement", {}).get("flops_per_env_step") for k in kinds}
     flops_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"]
                      * (fps[i["workload"]["scene"]["kind"]] or 0.0) for i in insts)
@@ -161,7 +165,7 @@ def bench_batch(a):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (FP64 refit and Cholesky)", "data": "synthetic (seeded instances, scenes and Philox samples)",
         "config": {"workload": a.workload, "instances": len(insts), "env_steps_per_iter": env_steps_iter,
-                   "autotune": tune},
+                   "autotune": tune, "settle_steps": a.settle_steps},
         "env_steps_simulated": counted, "env_steps_full_horizon": env_steps_iter * K,
         "step_event_ms": roll_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
