@@ -7,7 +7,7 @@ line with env-steps/s (one env-step = one control step dt of one environment,
 with all its physics substeps), CE iterations/s, the roofline of the rollout
 kernel and the CPU oracle's throughput on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--settle-steps N] [--lanes auto|1|2|4|8]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--settle-steps N] [--lanes auto|1|2|4|8|16]
 
 Workloads: pickplace (the default: 1024 plans x 2000 steps), push, movepush,
 pickplace_paper and pickplace_box (iteration-0 regions, n_env schedule),
@@ -89,21 +89,21 @@ def _valu_ceiling():
 
 
 def auto_lanes(scene, pop, scenarios, simds=None):
-    """Lanes per environment for a single robot instance: the most (8, 4, 2 or
-    1) whose waves still fit one per SIMD (64 lanes a wave, 4 SIMDs a CU; the
-    device's unless `simds` is given).  Where the object has at most four
-    world tests, 8 lanes split corners rather than tests, which pays less:
-    then 8 only while the waves fit one per CU (measured: pick-and-place at
-    1024 plans 312 ms at 8 lanes against 326 at 4; at 3000 plans 317 against
-    305)."""
+    """Lanes per environment for a single robot instance: the most (16, 8, 4,
+    2 or 1) whose waves still fit one per SIMD (64 lanes a wave, 4 SIMDs a CU;
+    the device's unless `simds` is given).  Where the object has at most four
+    world tests, 8 or 16 lanes split corners rather than tests, which pays
+    less: then only while the waves fit one per CU (measured: pick-and-place
+    at 1024 plans 314 ms at 16 lanes, 318 at 8, 326 at 4; at 3000 plans 317 at
+    8 against 305 at 4)."""
     if scene["kind"] == "push":
         return 1
     if simds is None:
         import torch
         simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
     halves = len(scene.get("static_boxes", [])) + 1 <= 4
-    for G in (8, 4, 2):
-        limit = simds // 4 if (G == 8 and halves) else simds
+    for G in (16, 8, 4, 2):
+        limit = simds // 4 if (G >= 8 and halves) else simds
         if scenarios * G <= 64 and -(-pop * scenarios * G // 64) <= limit:
             return G
     return 1
@@ -388,7 +388,7 @@ def main():
                          "many control steps (0: every rollout runs the full horizon); throughput then counts the "
                          "steps actually simulated")
     ap.add_argument("--lanes", default="auto",
-                    help="lanes per environment of a single robot instance (1, 2, 4, 8; auto: the most whose "
+                    help="lanes per environment of a single robot instance (1, 2, 4, 8, 16; auto: the most whose "
                          "waves fit one per SIMD)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the known-size "

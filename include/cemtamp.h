@@ -165,8 +165,8 @@ typedef struct cem_problem {
   int32_t n_elite;              /* N_e, 1..min(pop, 256)                           */
   int32_t cov_mode;             /* 0 diagonal, 1 full                              */
   /* Lanes of a wave that share one environment of a robot scene (0 or 1: one
-   * lane each; 2, 4 or 8: the lanes split the environment's contact tests and
-   * sum their forces).  An implementation choice, not part of Alg. 1: it
+   * lane each; 2, 4, 8 or 16: the lanes split the environment's contact tests
+   * and sum their forces).  An implementation choice, not part of Alg. 1: it
    * fills more of the device when pop is small, and moves the FP32 rounding
    * of the contact sums.  Push scenes and batches take 0 or 1 only;
    * lanes_per_env * dr_scenarios <= 64.  Else CEM_E_ARG. */

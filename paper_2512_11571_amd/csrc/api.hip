@@ -257,7 +257,7 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
     return CEM_E_ARG;
   if (p->init_region && check_region(*p->init_region, D)) return CEM_E_ARG;
   const int lanes = p->lanes_per_env <= 1 ? 1 : p->lanes_per_env;
-  if (p->lanes_per_env < 0 || (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) ||
+  if (p->lanes_per_env < 0 || (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16) ||
       (lanes > 1 && p->scene->kind == CEM_SCENE_PUSH) || lanes * scenarios(*p->scene) > 64)
     return CEM_E_ARG;
 

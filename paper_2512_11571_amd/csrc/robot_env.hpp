@@ -92,9 +92,9 @@ __device__ __forceinline__ void c_put(const Lds &L, int j, SV c) {
     L.at(r) = c.b.x; L.at(r + 1) = c.b.y; L.at(r + 2) = c.b.z;
   }
 }
-// Sum over the G (1, 2, 4 or 8) adjacent lanes that share an environment, by
-// a butterfly: quad permutations for lane distances 1 and 2, a swizzle (xor 4
-// within 32 lanes) for 4.  Each level adds the same two operands on both
+// Sum over the G (1, 2, 4, 8 or 16) adjacent lanes that share an environment,
+// by a butterfly: quad permutations for lane distances 1 and 2, swizzles (xor
+// within 32 lanes) for 4 and 8.  Each level adds the same two operands on both
 // lanes of a pair, so every lane of the group ends with the same bits and the
 // group's lanes keep identical state.  The group's lanes are all active or
 // all inactive.
@@ -102,10 +102,18 @@ __device__ __forceinline__ float group_sum(float v, int G) {
   if (G >= 2) v = v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
   if (G >= 4) v = v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
   if (G >= 8) v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
+  if (G >= 16) v = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x201F));
   return v;
 }
 __device__ __forceinline__ V3f group_sum(V3f v, int G) {
   return v3(group_sum(v.x, G), group_sum(v.y, G), group_sum(v.z, G));
+}
+
+// With G = 8 or 16 lanes, a contact test split across G / 4 lanes: the
+// corners lane gi takes (G 8: even or odd indices; G 16: indices congruent to
+// gi / 4 mod 4).
+__device__ __forceinline__ unsigned corner_part(int gi, int G) {
+  return G == 8 ? 0x55u << ((gi >> 2) & 1) : G == 16 ? 0x11u << ((gi >> 2) & 3) : 0xFFu;
 }
 
 // Joint reference row (both fingers share one).
@@ -125,10 +133,11 @@ struct EnvOut {
 // coefficients) and mass `om`, and (TRACE) writes its per-step trace.
 // `lds_mem` is the block's R_ROWS x PP_LANES float array and `lane` this
 // lane's column in it.  The scene and its derived constants come from `st`.
-// G adjacent lanes (1, 2, 4 or 8; gi this lane's place among them) run the
-// same environment: each keeps the whole state, takes every G-th contact test
-// of the object and the base against the world, and a share of the
-// finger-object tests (G 2: one finger; G 4, 8: one finger, one direction);
+// G adjacent lanes (1, 2, 4, 8 or 16; gi this lane's place among them) run
+// the same environment: each keeps the whole state, takes every G-th contact
+// test of the object and the base against the world, and a share of the
+// finger-object tests (G 2: one finger; G 4: one finger, one direction; G 8,
+// 16: that, on part of the corners);
 // the forces are then summed over the group.  With G = 1 the sums run in the
 // original order; the MULTI = false instance compiles G = 1 in.
 template <bool TRACE, bool MULTI>
@@ -430,11 +439,11 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       OB.h = ohe;
       Wrench W{v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)};
       // test u: 0 the ground, 1 + b static box b; this lane takes every G-th,
-      // or, with 8 lanes and at most four tests, every 4th on the half of
-      // the corners that gi / 4 picks (even or odd corner indices)
-      const bool w_halves = G == 8 && sc.n_static + 1 <= 4;
+      // or, with 8 or 16 lanes and at most four tests, every 4th on the part
+      // of the corners that gi / 4 picks
+      const bool w_halves = G >= 8 && sc.n_static + 1 <= 4;
       const int w_step = w_halves ? 4 : G;
-      const unsigned w_mask = w_halves ? ((gi & 4) ? 0xAAu : 0x55u) : 0xFFu;
+      const unsigned w_mask = w_halves ? corner_part(gi, G) : 0xFFu;
       for (int u = gi & (w_step - 1); u <= sc.n_static; u += w_step) {
         if (u == 0) {
           box_ground(ob, OB.R, ohe, kc, damp, mu_o_ground, eps2, W, w_mask);
@@ -524,11 +533,11 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
             fm = fm + cross(x - pw2, F);
             ff = ff + F;
           };
-          // every G-th static box, or with 8 lanes and at most four boxes
-          // every 4th on half of the corners, as for the object above
-          const bool b_halves = G == 8 && sc.n_static <= 4;
+          // every G-th static box, or with 8 or 16 lanes and at most four
+          // boxes every 4th on part of the corners, as for the object above
+          const bool b_halves = G >= 8 && sc.n_static <= 4;
           const int b_step = b_halves ? 4 : G;
-          const unsigned b_mask = b_halves ? ((gi & 4) ? 0xAAu : 0x55u) : 0xFFu;
+          const unsigned b_mask = b_halves ? corner_part(gi, G) : 0xFFu;
           for (int b = gi & (b_step - 1); b < sc.n_static; b += b_step) {
             const Box SB = static_box(sc, sk, b);
             const Rel r = rel_of(LB, SB);
@@ -549,11 +558,11 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
         // the fingers against the object (their pose again from the palm's);
         // G 1 takes both fingers, G 2 finger FL + gi, G 4 finger FL + gi / 2
         // in one direction (bit 0 of dirs: finger vertices in the object,
-        // bit 1: object vertices in the finger), G 8 the same on half of the
-        // corners
+        // bit 1: object vertices in the finger), G 8 and 16 the same on part
+        // of the corners
         const int jf0 = G == 1 ? FL : FL + (G == 2 ? gi : (gi >> 1) & 1), jf1 = G == 1 ? FR : jf0;
         const int dirs = G <= 2 ? 3 : 1 << (gi & 1);
-        const unsigned f_mask = G == 8 ? ((gi & 4) ? 0xAAu : 0x55u) : 0xFFu;  // 8 lanes: half the corners each
+        const unsigned f_mask = corner_part(gi, G);  // 8 or 16 lanes: part of the corners each
         SV part = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));  // G > 1: this lane's body-frame share
         bool part_any = false;
         for (int j = jf0; j <= jf1; ++j) {

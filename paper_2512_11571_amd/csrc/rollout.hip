@@ -2,7 +2,7 @@
 //
 // Work is cut into items of up to 64 environments of one instance (one wave,
 // one environment per lane; a single robot instance may give each environment
-// 2, 4 or 8 adjacent lanes, which split its contact tests).  A single instance runs one workgroup per item.
+// 2, 4, 8 or 16 adjacent lanes, which split its contact tests).  A single instance runs one workgroup per item.
 // A batch of instances (independent CE problems with their own scene kind,
 // population and horizon) runs as one persistent launch: each workgroup pulls
 // the next item from an atomic queue until the list is exhausted, so the items
@@ -58,12 +58,12 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
     const bool active = !(check_iter && st->iter >= d.iters);  // wave-uniform
     const bool robot = d.kind != CEM_SCENE_PUSH;                // wave-uniform
     const int R = d.scen;  // scenarios per row: a power of two <= 64, aligned to the item (wave-uniform)
-    // lanes per environment: 1, 2, 4 or 8, with R * G <= 64 (wave-uniform; 1 unless MULTI)
+    // lanes per environment: 1, 2, 4, 8 or 16, with R * G <= 64 (wave-uniform; 1 unless MULTI)
     const int G = MULTI ? d.lanes : 1;
     int steps = 0;
     EnvOut o{0.0f, 0, 0, {0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f}};
     // lane layout: ((row * R) + scenario) * G + g, g the lane's place in its environment's group
-    const int lg = G == 8 ? 3 : G == 4 ? 2 : G == 2 ? 1 : 0;
+    const int lg = G == 16 ? 4 : G == 8 ? 3 : G == 4 ? 2 : G == 2 ? 1 : 0;
     const long vl = env0 + lane, env = vl >> lg, row = env / R;
     const int g = (int)(vl & (G - 1));
     if (active && lane < n) {
@@ -175,7 +175,7 @@ __global__ void pack_dataset_kernel(const float *__restrict__ Z, const float *__
 
 hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s) {
   if (d.scen < 1 || d.scen > 64 || (d.scen & (d.scen - 1))) return hipErrorInvalidValue;
-  if ((d.lanes != 1 && d.lanes != 2 && d.lanes != 4 && d.lanes != 8) || d.scen * d.lanes > 64 ||
+  if ((d.lanes != 1 && d.lanes != 2 && d.lanes != 4 && d.lanes != 8 && d.lanes != 16) || d.scen * d.lanes > 64 ||
       (d.lanes > 1 && d.kind == CEM_SCENE_PUSH))
     return hipErrorInvalidValue;
   const int n_items = (d.pop * d.scen * d.lanes + 63) / 64;

@@ -128,7 +128,7 @@ def test_lanes_per_env_is_validated_before_touching_the_device():
     import copy
     from paper_2512_11571_amd import binding, workloads
     pp = workloads.load("pickplace")
-    for lanes in (-1, 3, 16, 64):
+    for lanes in (-1, 3, 32, 64):
         _rejects(binding, pp, 1, lanes=lanes)
     _rejects(binding, workloads.load("push"), 1, lanes=2)    # robot scenes only
     w = copy.deepcopy(workloads.load("movepush"))
@@ -147,7 +147,7 @@ def test_bench_lane_choice():
     from paper_2512_11571_amd import workloads
     pick = lambda name, pop=None, R=1: bench.auto_lanes(workloads.load(name)["scene"],
                                                         pop or workloads.load(name)["cem"]["pop"], R, simds=1024)
-    assert pick("pickplace") == 8                 # 1024 plans: 128 waves, within one per CU
+    assert pick("pickplace") == 16                # 1024 plans: 256 waves, within one per CU
     assert pick("pickplace_paper") == 4           # 3000 plans: 375 waves at 8 lanes is over one per CU
     assert pick("pickplace", 4096) == 4           # the surrogate comparison's 4096 plans
     assert pick("movepush") == 8                  # 8192 plans: 1024 waves (seven object-world tests)

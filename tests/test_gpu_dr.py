@@ -8,7 +8,7 @@ mass, and the step count covers all pop x R rollouts.  Against the oracle:
 tier and cost on certified rows (cost within two control steps).  Batched
 instances with scenarios give the bits of their single runs.  Statistical:
 median best cost of plan_solve over 32 seeds within 1e-2 relative.  The
-composition, oracle and population tests also run with 2, 4 or 8 lanes per
+composition, oracle and population tests also run with 2 to 16 lanes per
 environment (the scenario butterfly then pairs lanes G, 2G, ... apart).
 """
 import copy
@@ -155,7 +155,7 @@ def test_plan_solve_median_matches_oracle(oracle, B):
 
 
 @pytest.mark.parametrize("name,R,lanes", [("pickplace", 1, 1), ("movepush", 64, 1), ("pickplace", 1, 4), ("movepush", 16, 4),
-                                          ("movepush", 8, 8)])
+                                          ("movepush", 8, 8), ("pickplace", 4, 16)])
 def test_rows_do_not_depend_on_the_population(oracle, B, name, R, lanes):
     # a row's outcome is the same whether it runs alone (pop 1 or 3; with 64
     # scenarios one row fills a wave) or among 100 rows

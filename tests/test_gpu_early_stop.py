@@ -10,7 +10,8 @@ tier and cost on certified rows as for the full horizon, and the total of
 simulated steps within 5 %.  With domain-randomisation scenarios the costs
 still equal the full-horizon ones, and batched instances that stop early give
 the bits and step counts of their single runs.  The cost-and-goal test also
-runs at the 8 lanes per plan the benchmarks use.
+runs at the lanes per plan the benchmarks use (8 for move-push, 16 for
+pick-and-place).
 """
 import copy
 
@@ -71,7 +72,7 @@ def test_full_horizon_counts_T_steps_per_rollout(oracle, Context, name):
         assert c.env_steps() == 2 * n * w["scene"]["horizon"]
 
 
-@pytest.mark.parametrize("name,lanes", [("movepush", 1), ("pickplace", 1), ("movepush", 8), ("pickplace", 8)])
+@pytest.mark.parametrize("name,lanes", [("movepush", 1), ("pickplace", 1), ("movepush", 8), ("pickplace", 16)])
 def test_early_stop_keeps_cost_and_goal(oracle, Context, name, lanes):
     w = workloads.load(name)
     H = w["scene"]["horizon"]

@@ -8,7 +8,7 @@ control steps, since action completion is decided on a threshold per step).
 Statistical: median best cost of plan_solve over seeds 0-31 within 1e-2
 relative at a reduced population.  Full size: the configured population and
 horizon, sampled rows checked one by one.
-Every parity test also runs with 2, 4 or 8 lanes per environment (the
+Every parity test also runs with 2, 4, 8 or 16 lanes per environment (the
 lanes split the contact tests and sum the forces), against the same oracle
 runs and the same tolerances.
 """
@@ -65,7 +65,7 @@ def _gpu_rollout(Context, w, Z, trace_steps=0, lanes=1):
         return cost.cpu().numpy().astype(np.float64), tier.cpu().numpy(), pose.cpu().numpy()
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
 def test_trace_parity_first_100_steps(oracle, pp, Context, lanes):
     Z = _rows(oracle, pp, 0, 64)
     key = ("trace", 0, Z.tobytes())
@@ -108,7 +108,7 @@ def _certified_full_uncached(oracle, w, seed, Z):
     return ok, c0, t0, p0
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
 def test_full_horizon_cost_and_tier_parity(oracle, pp, Context, lanes):
     Z = _rows(oracle, pp, 1, 128)
     ok, cr, tr, pr = _certified_full(oracle, pp, 1, Z)
@@ -122,7 +122,7 @@ def test_full_horizon_cost_and_tier_parity(oracle, pp, Context, lanes):
     assert set(np.unique(tr[ok])) <= set(np.unique(tg))
 
 
-@pytest.mark.parametrize("lanes", [1, 8])
+@pytest.mark.parametrize("lanes", [1, 16])
 def test_full_size_population_sampled_rows(oracle, pp, Context, lanes):
     # the configured population (and horizon) in one launch, as the benchmark runs it
     pop = pp["cem"]["pop"]
@@ -146,7 +146,7 @@ def test_full_size_population_sampled_rows(oracle, pp, Context, lanes):
     assert np.all(th < 3)                                  # nothing diverges on the GPU
 
 
-@pytest.mark.parametrize("lanes", [1, 8])
+@pytest.mark.parametrize("lanes", [1, 16])
 def test_plan_solve_median_matches_oracle(oracle, pp, Context, lanes):
     w = dict(pp, cem=dict(pp["cem"], pop=128, n_elite=16))
     iters = 3
