@@ -36,10 +36,10 @@ DEFAULT_WORKLOAD = "pickplace"
 # scaled by the copy-kernel calibration), keyed by workload; valid only while
 # the rollout sources hash to the recorded value.
 MEASURED_TRAFFIC = {
-    # rollout of 1024 pick-and-place plans over 2000 steps, 8 lanes per plan: FETCH_SIZE
-    # 838.25 KiB x 2.0 + WRITE_SIZE 12.0 KiB x 1.0 (a 256 MiB copy reads as 131083.5 / 262144 KiB)
-    "pickplace": {"bytes_per_launch": int((838.25 * 2.0 + 12.0 * 1.0) * 1024), "lanes": 8,
-                  "src_hash": "fd4ecd491ec607b2"},
+    # rollout of 1024 pick-and-place plans over 2000 steps, 16 lanes per plan: FETCH_SIZE
+    # 846.0 KiB x 2.0 + WRITE_SIZE 24.0 KiB x 1.0 (a 256 MiB copy reads as 131083.5 / 262144 KiB)
+    "pickplace": {"bytes_per_launch": int((846.0 * 2.0 + 24.0 * 1.0) * 1024), "lanes": 16,
+                  "src_hash": "98cd22a8968c7f3c"},
 }
 
 _KERNEL_FILES = ["rollout.hip", "push_env.hpp", "robot_env.hpp", "robot_dyn.hpp", "rigid.hpp", "devmath.hpp",
