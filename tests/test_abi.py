@@ -156,3 +156,13 @@ def test_bench_lane_choice():
     assert pick("pickplace", 1024, 16) == 4       # 16 scenarios x 4 lanes fill a wave per plan
     assert pick("push") == 1
     assert pick("pickplace", 65536) == 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: --gpus N > 1 exits with a message before touching a device
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
