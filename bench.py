@@ -9,12 +9,13 @@ kernel and the CPU oracle's throughput on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--settle-steps N] [--lanes auto|1|2|4|8|16]
 
-Workloads: pickplace (the default: 1024 plans x 2000 steps), push, movepush,
-pickplace_paper and pickplace_box (iteration-0 regions, n_env schedule),
-movepush_dr (8 friction/mass scenarios per plan), batch and batch_mixed
-(many instances in one persistent launch), surrogate (screened against plain
-CE to the same cost) and modes (the paper-setting pick-and-place on the ramp
-and box scenes for ten seeds: best costs and solution modes).
+Workloads: batch (the default: 64 push and pick-and-place instances with
+uneven horizons and populations, one persistent launch per CE iteration, the
+largest configuration that fits one GPU), batch_mixed (push, pick-and-place
+and move-push instances), pickplace (1024 plans x 2000 steps), push,
+movepush, pickplace_paper and pickplace_box (iteration-0 regions, n_env
+schedule), movepush_dr (8 friction/mass scenarios per plan) and surrogate
+(screened against plain CE to the same cost).
 """
 import argparse
 import hashlib
@@ -30,12 +31,15 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0   # dense BF16 MFMA
 MLP_FLOP_PER_ROW = 2 * (16 * 256 + 256 * 256 + 256 * 256 + 256 * 8)   # one forward pass, multiply-adds x 2
-DEFAULT_WORKLOAD = "pickplace"
+DEFAULT_WORKLOAD = "batch"
 
 # HBM traffic per rollout launch measured with rocprofv3 (FETCH_SIZE + WRITE_SIZE,
 # scaled by the copy-kernel calibration), keyed by workload; valid only while
 # the rollout sources hash to the recorded value.
 MEASURED_TRAFFIC = {
+    # one batched rollout launch (64 instances, 141,184 plans, 357.7 M env-steps): FETCH_SIZE 4157.25 KiB x 2.0
+    # + WRITE_SIZE 4719.75 KiB x 1.0; algorithmic 10,243,712 B (Z in, cost, tier and pose out)
+    "batch": {"bytes_per_launch": int((4157.25 * 2.0 + 4719.75 * 1.0) * 1024), "src_hash": "98cd22a8968c7f3c"},
     # rollout of 1024 pick-and-place plans over 2000 steps, 16 lanes per plan: FETCH_SIZE
     # 846.0 KiB x 2.0 + WRITE_SIZE 24.0 KiB x 1.0 (a 256 MiB copy reads as 131083.5 / 262144 KiB)
     "pickplace": {"bytes_per_launch": int((846.0 * 2.0 + 24.0 * 1.0) * 1024), "lanes": 16,
@@ -44,7 +48,8 @@ MEASURED_TRAFFIC = {
 
 _KERNEL_FILES = ["rollout.hip", "push_env.hpp", "robot_env.hpp", "robot_dyn.hpp", "rigid.hpp", "devmath.hpp",
                  "internal.hpp"]
-ROLLOUT_SOURCES = {"push": _KERNEL_FILES, "pickplace": _KERNEL_FILES, "movepush": _KERNEL_FILES}
+ROLLOUT_SOURCES = {"push": _KERNEL_FILES, "pickplace": _KERNEL_FILES, "movepush": _KERNEL_FILES,
+                   "batch": _KERNEL_FILES}
 
 
 def _src_hash(workload):
@@ -55,12 +60,21 @@ def _src_hash(workload):
     return h.hexdigest()[:16]
 
 
+# Host threads of the CPU baseline: every core the host shows, up to the 16
+# that one GPU's share of the GPU machine's host allows.
+CPU_SHARE = 16
+
+
+def cpu_threads():
+    return max(1, min(CPU_SHARE, os.cpu_count() or 1))
+
+
 def cpu_baseline(w, seed, budget_s):
-    """The oracle (FP64, all host threads up to 16) on a bounded sample of the same workload."""
+    """The oracle (FP64, all host threads up to the one-GPU share) on a bounded sample of the same workload."""
     import numpy as np
     from oracle import oracle as O
     cem = w["cem"]
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = cpu_threads()
     H = w["scene"]["horizon"]
     mu0 = np.asarray(cem["mu0"], np.float64)
     L, _ = O.factor_cov(np.diag(np.asarray(cem["cov0_diag"], np.float64)))
@@ -77,7 +91,8 @@ def cpu_baseline(w, seed, budget_s):
             break
     dt = time.perf_counter() - t0
     span = ("full horizon %d steps" % H) if not settle else ("horizon %d, early stop after %d settled steps" % (H, settle))
-    return {"value": done / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+    return {"value": done / dt, "unit": "env-steps/s", "cores": threads, "host_nproc": os.cpu_count(),
+            "kind": "oracle",
             "sample": "%d x %d rollouts of %d iteration-0 samples (%s), %.1f s" % (reps, n, n, span, dt),
             "env_steps": done, "seconds": dt}
 
@@ -110,8 +125,12 @@ def auto_lanes(scene, pop, scenarios, simds=None):
 
 
 def bench_batch(a):
-    """The batched workload: all instances, one CE iteration per step (graph replay)."""
-    import numpy as np
+    """The batched workload: all instances, one CE iteration of every instance per step (graph replay).
+
+    A timed step is one CE iteration of every instance.  Where the driver asks
+    for more steps than an instance's nominal iteration budget (5 push, 10
+    pick-and-place), the timed batch raises every budget to the step count, so
+    that each timed step still iterates all 64 instances."""
     import torch
     from paper_2512_11571_amd import workloads
     from paper_2512_11571_amd.binding import Batch
@@ -124,19 +143,18 @@ def bench_batch(a):
             if i["workload"]["scene"]["kind"] != "push":
                 i["workload"]["scene"]["settle_steps"] = a.settle_steps
     K = a.steps if a.steps is not None else 3
-    cap = min(i["iters"] for i in insts)
-    if K > cap:
-        raise SystemExit("--steps must be <= %d so that every instance runs in every timed step" % cap)
+    nominal = {k: int(spec["iters"][k]) for k in kinds}
+    timed = [dict(i, iters=max(i["iters"], K)) for i in insts]
     torch.cuda.set_device(0)
-    with Batch(insts) as B:          # warm-up on a batch of its own
+    with Batch([dict(i, iters=max(i["iters"], a.warmup)) for i in insts]) as B:   # warm-up on a batch of its own
         for _ in range(a.warmup):
             B.step()
         torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    with Batch(insts) as B:
-        tune = B.autotune()           # untimed
+    with Batch(timed) as B:
+        tune = B.autotune()           # untimed; leaves the CE state and step counters as they were
         torch.cuda.synchronize()
-        counted0 = sum(B.instance(k).env_steps() for k in range(len(insts)))
+        per0 = [B.instance(k).env_steps() for k in range(len(insts))]
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
         t0 = time.perf_counter()
         for j in range(K):            # one CE iteration of every instance per replay
@@ -146,17 +164,25 @@ def bench_batch(a):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         step_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
-        counted = sum(B.instance(k).env_steps() for k in range(len(insts))) - counted0
+        per = [B.instance(k).env_steps() - per0[k] for k in range(len(insts))]
+    counted = sum(per)
     env_steps_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"] for i in insts)
+    dims = {"push": 3, "pickplace": 16, "movepush": 12}
+    # HBM bytes the method must move per launch: each plan's parameter row in, its cost, tier and pose out
+    alg_bytes = sum(i["workload"]["cem"]["pop"] * (4 * dims[i["workload"]["scene"]["kind"]] + 4 + 1 + 28)
+                    for i in insts)
     assert counted <= env_steps_iter * K, (counted, env_steps_iter * K)   # fewer only where rollouts stopped early
     fps = {k: workloads.load(k).get("measurement", {}).get("flops_per_env_step") for k in kinds}
-    flops_iter = sum(i["workload"]["cem"]["pop"] * i["workload"]["scene"]["horizon"]
-                     * (fps[i["workload"]["scene"]["kind"]] or 0.0) for i in insts)
-    # the replayed step is sampling + the rollout launch + refit; the rollout is > 99.9 % of it,
+    # algorithmic FLOPs of the steps the rollouts actually simulated, per scene kind
+    flops = sum(n * (fps[i["workload"]["scene"]["kind"]] or 0.0) for n, i in zip(per, insts))
+    # the replayed step is sampling + the rollout launch + refit; the rollout is > 99.8 % of it,
     # so the step's event time bounds the rollout kernel's duration from above
     roll_s = sum(step_ms) / len(step_ms) / 1e3
-    achieved = flops_iter / roll_s / 1e12 if roll_s > 0 else None
+    achieved = flops / K / roll_s / 1e12 if roll_s > 0 else None
     ceiling = _valu_ceiling()
+    tr = MEASURED_TRAFFIC.get(a.workload)
+    traffic = (tr["bytes_per_launch"] if tr and tr.get("src_hash") == _src_hash(a.workload)
+               and not a.settle_steps else None)
     out = {
         "metric": "env-steps/s (CE iterations/s alongside)",
         "value": counted / elapsed,
@@ -164,12 +190,14 @@ def bench_batch(a):
         "ms_per_step": elapsed / K * 1e3, "cem_iters_per_s": K / elapsed,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (FP64 refit and Cholesky)", "data": "synthetic (seeded instances, scenes and Philox samples)",
-        "config": {"workload": a.workload, "instances": len(insts), "env_steps_per_iter": env_steps_iter,
-                   "autotune": tune, "settle_steps": a.settle_steps},
+        "config": {"workload": a.workload, "instances": len(insts), "kinds": kinds,
+                   "env_steps_per_iter": env_steps_iter, "nominal_iters": nominal,
+                   "timed_iters_per_instance": K, "autotune": tune, "settle_steps": a.settle_steps},
         "env_steps_simulated": counted, "env_steps_full_horizon": env_steps_iter * K,
         "step_event_ms": roll_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": traffic,
+                     "algorithmic_bytes": alg_bytes,
                      "flops_per_env_step": fps, "unpacked_fma_measured": ceiling,
                      "frac_of_measured": achieved / ceiling if achieved and ceiling else None},
     }
@@ -181,7 +209,8 @@ def bench_batch(a):
         tot_t = sum(p["seconds"] for p in per_kind)
         steps = sum(p["env_steps"] for p in per_kind)
         out["cpu_baseline"] = {"value": steps / tot_t, "unit": "env-steps/s", "cores": per_kind[0]["cores"],
-                               "kind": "oracle", "sample": "; ".join(p["sample"] for p in per_kind)}
+                               "host_nproc": os.cpu_count(), "kind": "oracle",
+                               "sample": "; ".join(p["sample"] for p in per_kind)}
     print(json.dumps(out))
 
 
@@ -191,68 +220,6 @@ def _first_reach(curve, target):
         if v <= target:
             return k
     return None
-
-
-def _mode_of(z, table2_near_x):
-    """Solution mode of a pick-and-place plan: the cube released over the obstacle
-    (short of table 2's near edge, to slide down the ramp), or the base taken
-    around the obstacle on its +y or -y side."""
-    if z[12] < table2_near_x:
-        return "over the obstacle"
-    return "around +y" if z[9] > 0 else "around -y"
-
-
-def bench_modes(a):
-    """The paper-setting pick-and-place on the ramp and the box scenes: plan_solve
-    over the configured iterations for seeds 0-9; median best cost, feasible
-    seeds, solution modes and wall time per scene."""
-    import numpy as np
-    import torch
-    from paper_2512_11571_amd import workloads
-    from paper_2512_11571_amd.binding import Context
-
-    torch.cuda.set_device(0)
-    out_scenes = {}
-    total_t, total_steps = 0.0, 0
-    for name in ("pickplace_paper", "pickplace_box"):
-        w = workloads.load(name)
-        iters = a.steps if a.steps is not None else w["cem"]["iters"]
-        t2 = w["scene"]["static_boxes"][1]                 # table 2: its near edge ends the obstacle
-        far_x = t2["center"][0] - t2["half"][0]
-        costs, tiers, modes, times, curves = [], [], {}, [], []
-        lanes = auto_lanes(w["scene"], w["cem"]["pop"], 1) if a.lanes == "auto" else int(a.lanes)
-        for seed in w["cem"]["seeds"]:
-            with Context(w, seed=seed, lanes=lanes) as c:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                r = c.plan_solve(iters)
-                dt = time.perf_counter() - t0
-                total_steps += c.env_steps()
-            total_t += dt
-            times.append(dt)
-            costs.append(r["best_cost"])
-            tiers.append(r["best_tier"])
-            curves.append([float(v) for v in r["stats"][:, 7]])
-            if r["best_tier"] == 0:
-                m = _mode_of(r["best_z"], far_x)
-                modes[m] = modes.get(m, 0) + 1
-        feas = [cst for cst, t in zip(costs, tiers) if t == 0]
-        out_scenes[name] = {
-            "iterations": iters, "seeds": len(costs), "feasible_seeds": len(feas),
-            "median_best_cost_s": float(np.median(feas)) if feas else None,
-            "modes": modes, "seconds_per_solve": float(np.median(times)), "lanes_per_env": lanes,
-            "median_best_so_far_by_iteration": [float(v) for v in np.median(np.array(curves), axis=0)],
-        }
-    ramp = out_scenes["pickplace_paper"]
-    print(json.dumps({
-        "metric": "paper-setting CE: median best plan cost over seeds (ramp scene)",
-        "value": ramp["median_best_cost_s"], "unit": "s", "n_gpus": 1, "steps": ramp["iterations"], "warmup": 0,
-        "ms_per_step": total_t / sum(v["iterations"] * v["seeds"] for v in out_scenes.values()) * 1e3,
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 (FP64 refit and Cholesky)", "data": "synthetic (seeded scene and Philox samples)",
-        "config": {"workload": "modes", "scenes": list(out_scenes)},
-        "env_steps_per_s": total_steps / total_t, "scenes": out_scenes,
-    }))
 
 
 def bench_surrogate(a):
@@ -413,9 +380,6 @@ def main():
         return
     if a.workload == "surrogate":
         bench_surrogate(a)
-        return
-    if a.workload == "modes":
-        bench_modes(a)
         return
 
     import torch

@@ -304,9 +304,11 @@ const char *cem_batch_last_error(const cem_batch *b);
 /* The context of instance i (owned by the batch: theta, factor, instance draws). */
 cem_ctx *cem_batch_instance(cem_batch *b, int32_t i);
 /* Times one rollout pass for each persistent grid (1, 2, 4 workgroups per CU)
- * and work-item size (64 or 32 environments) and keeps the fastest.
- * config_out (nullable, 3 ints): grid, environments per item, microseconds of
- * that pass.  Leaves the CE state untouched.  Synchronous. */
+ * and work-item size (64 or 32 environments) and keeps the fastest.  The
+ * passes roll out each instance's samples of its current iteration (drawn
+ * first; the same rows its next step draws).  config_out (nullable, 3 ints):
+ * grid, environments per item, microseconds of that pass.  Leaves the CE
+ * state and the step counters (cem_env_steps) as they were.  Synchronous. */
 int cem_batch_autotune(cem_batch *b, int32_t *config_out);
 /* One CE iteration of every instance under its cap, asynchronous on stream. */
 int cem_batch_step(cem_batch *b, void *stream);

@@ -671,6 +671,17 @@ int cem_batch_autotune(cem_batch *b, int32_t *config_out) {
   const int envs_opts[2] = {64, 32};
   float best = INFINITY;
   int best_grid = b->grid, best_envs = b->item_envs;
+  // the trial passes roll out the instances' current iteration's samples (the
+  // sampling does not advance the iteration counter, so the next step draws
+  // the same rows again); their simulated steps are not the CE run's, so each
+  // instance's step counter is put back afterwards
+  const int n = (int)b->ctx.size();
+  std::vector<unsigned long long> steps0(n);
+  BHIPCHK(b, hipStreamSynchronize(b->own));
+  BHIPCHK(b, hipDeviceSynchronize());
+  for (int i = 0; i < n; ++i)
+    BHIPCHK(b, hipMemcpy(&steps0[i], &b->ctx[i]->st->env_steps, sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  BHIPCHK(b, launch_sample_batch(b->insts, n, b->max_pop, b->own));
   hipEvent_t e0, e1;
   BHIPCHK(b, hipEventCreate(&e0));
   BHIPCHK(b, hipEventCreate(&e1));
@@ -694,6 +705,10 @@ int cem_batch_autotune(cem_batch *b, int32_t *config_out) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  for (int i = 0; i < n; ++i)
+    BHIPCHK(b, hipMemcpyAsync(&b->ctx[i]->st->env_steps, &steps0[i], sizeof(unsigned long long),
+                              hipMemcpyHostToDevice, b->own));
+  BHIPCHK(b, hipStreamSynchronize(b->own));
   b->grid = best_grid;
   int rc = build_items(b, best_envs);
   if (rc == CEM_OK) rc = build_graph(b);

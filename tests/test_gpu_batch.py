@@ -48,6 +48,8 @@ def test_autotune_changes_only_speed(binding):
     with binding.Batch(insts) as B:
         cfg = B.autotune()
         assert cfg["envs_per_item"] in (32, 64) and cfg["grid"] > 0 and cfg["rollout_us"] > 0
+        # the tuner's trial passes are not the CE run's: no counted steps, no iteration advanced
+        assert [B.instance(k).env_steps() for k in range(len(insts))] == [0] * len(insts)
         tuned = B.solve(3)
     with binding.Batch(copy.deepcopy(insts)) as B:
         plain = B.solve(3)
