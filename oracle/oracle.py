@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# CEM_ORACLE_LIB selects another build of the same sources (the sanitizer build)
+LIB_PATH = os.environ.get("CEM_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 SCENE_KIND = {"push": 1, "pickplace": 2, "movepush": 3}
 MAX_STATIC = 8
@@ -118,6 +119,17 @@ def lib():
         L.ref_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_long, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.ref_object_sim.argtypes = [P(RefScene), vp, vp, vp, ctypes.c_int, vp]
+        L.ref_set_face_cull.argtypes = [ctypes.c_int]
+        L.ref_set_face_cull.restype = None
+        L.ref_robot_log.argtypes = [P(RefScene), u64, u32, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, ctypes.c_int]
+        L.ref_grasp_check.argtypes = [P(RefScene), vp, vp, vp, vp]
+        L.ref_grasp_check.restype = None
+        L.ref_count_block.argtypes = [ctypes.c_int, vp]
+        L.ref_count_block.restype = None
+        L.ref_gelu_vec.argtypes = [vp, ctypes.c_int, vp, vp]
+        L.ref_gelu_vec.restype = None
+        L.ref_to_bf16_vec.argtypes = [vp, ctypes.c_int, vp]
+        L.ref_to_bf16_vec.restype = None
         if L.ref_tree_size() != ctypes.sizeof(Tree):
             raise RuntimeError("oracle Tree layout mismatch")
         L.ref_box_sim.argtypes = [vp, ctypes.c_int, vp]
@@ -532,3 +544,61 @@ def ik(workload, q, pt, Rt):
     lib().ref_ik(ctypes.byref(s), _ptr(_f64(q)), _ptr(_f64(pt)), _ptr(_f64(np.asarray(Rt).ravel())), _ptr(qo),
                  _ptr(pe), _ptr(Re))
     return qo, pe, Re.reshape(3, 3)
+
+
+def set_face_cull(on):
+    """Face-axis broadphase of the box-box tests on (default) or off."""
+    lib().ref_set_face_cull(1 if on else 0)
+
+
+def robot_log(workload, seed, z, steps=None, trace_steps=0, inst=0):
+    """One robot rollout with its action-sequencing record:
+    dict(act[steps], qref[steps][11], ends[4], ok bits, cost, tier, trace)."""
+    s = make_scene(workload)
+    steps = steps if steps is not None else workload["scene"]["horizon"]
+    z = np.ascontiguousarray(z, np.float32)
+    act = np.zeros(max(steps, 1), np.int32)
+    qref = np.zeros((max(steps, 1), 11), np.float64)
+    ends = np.zeros(4, np.int32)
+    ok = np.zeros(1, np.int32)
+    out = np.zeros(2, np.float64)
+    trace = np.zeros((trace_steps, 35), np.float64) if trace_steps else None
+    rc = lib().ref_robot_log(ctypes.byref(s), seed, inst, _ptr(z), steps, _ptr(act), _ptr(qref), _ptr(ends),
+                             _ptr(ok), _ptr(out), _ptr(trace) if trace is not None else None, trace_steps)
+    if rc != 0:
+        raise RuntimeError("robot_log needs a robot scene")
+    return dict(act=act[:steps], qref=qref[:steps], ends=ends, ok=int(ok[0]), cost=float(out[0]), tier=int(out[1]),
+                trace=trace)
+
+
+def grasp_check(workload, q, obj_p, obj_q):
+    """(left touches, right touches, centre between the fingers, all three) at a hand-set state."""
+    s = make_scene(workload)
+    out = np.zeros(4, np.int32)
+    lib().ref_grasp_check(ctypes.byref(s), _ptr(_f64(q)), _ptr(_f64(obj_p)), _ptr(_f64(obj_q)), _ptr(out))
+    return tuple(bool(v) for v in out)
+
+
+def count_block(which):
+    """Operation tally of one building block (0 free-body step, 1 penalty force, 2 cross, 3 quaternion matrix)."""
+    out = np.zeros(6, np.uint64)
+    lib().ref_count_block(int(which), _ptr(out))
+    d = dict(zip(["add", "mul", "fma", "div", "sqrt", "trans"], [int(v) for v in out]))
+    d["flops"] = d["add"] + d["mul"] + 2 * d["fma"] + d["div"] + d["sqrt"]
+    return d
+
+
+def gelu(x):
+    """The network's GELU (tanh form) and its derivative at the points x."""
+    x = _f64(np.atleast_1d(x))
+    y, dy = np.zeros_like(x), np.zeros_like(x)
+    lib().ref_gelu_vec(_ptr(x), x.size, _ptr(y), _ptr(dy))
+    return y, dy
+
+
+def to_bf16(x):
+    """The oracle's bfloat16 rounding (through FP32, ties to even), as float64 values."""
+    x = _f64(np.atleast_1d(x))
+    y = np.zeros_like(x)
+    lib().ref_to_bf16_vec(_ptr(x), x.size, _ptr(y))
+    return y

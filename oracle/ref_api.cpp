@@ -342,8 +342,115 @@ void ref_ik(const RefScene *s, const double *q, const double pt[3], const double
     for (int b = 0; b < 3; ++b) Re[a * 3 + b] = E.m[a][b];
 }
 
+// ---- pins of the plan layer ----
+
+// Switches the face-axis broadphase of the box-box tests on (1, the default)
+// or off (0: every pair runs its vertex tests).  Set only between calls.
+void ref_set_face_cull(int on) { g_face_cull = on != 0; }
+
+// One robot rollout of row z with its action-sequencing record: act[t] and
+// (nullable) the joint references qref[t][11] for the first `steps` control
+// steps, ends[4] (T_a + 1, or -1), the success bits, (cost, tier) and
+// optionally the state trace.
+int ref_robot_log(const RefScene *s, uint64_t seed, uint32_t inst, const float *z, int steps, int32_t *act,
+                  double *qref, int32_t ends[4], int32_t *ok, double out[2], double *trace, int trace_steps) {
+  if (s->kind != SCENE_PICKPLACE && s->kind != SCENE_MOVEPUSH) return 1;
+  const Instance in = draw_instance(*s, seed, inst);
+  RobotLog log;
+  log.act = act;
+  log.qref = qref;
+  log.steps = steps;
+  for (int t = 0; t < steps; ++t) act[t] = -1;
+  const RolloutOut o = robot_rollout<double>(*s, in, z, trace, trace_steps, &log);
+  for (int a = 0; a < 4; ++a) ends[a] = log.ends[a];
+  *ok = log.ok;
+  out[0] = o.cost;
+  out[1] = (double)o.tier;
+  return 0;
+}
+
+// The grasp predicates on a hand-set state: the robot at configuration q[11],
+// the object box at (p, quaternion w x y z).  out = (left finger touches,
+// right finger touches, object centre between the inner faces, all three).
+void ref_grasp_check(const RefScene *s, const double *q, const double obj_p[3], const double obj_q[4],
+                     int32_t out[4]) {
+  const Tree tr = tree_of(*s);
+  M3<double> Rw[MAXJ];
+  V3<double> pw[MAXJ];
+  forward_kinematics(tr, q, Rw, pw);
+  const V3<double> op(obj_p[0], obj_p[1], obj_p[2]);
+  Q4<double> oq;
+  oq.w = obj_q[0]; oq.x = obj_q[1]; oq.y = obj_q[2]; oq.z = obj_q[3];
+  const M3<double> oR = quat_to_mat(oq);
+  const V3<double> ohe(s->obj_half[0], s->obj_half[1], s->obj_half[2]);
+  for (int f = 0; f < 2; ++f) {
+    const int j = f == 0 ? FL : FR;
+    V3<double> fc, fh;
+    link_box(*s, j, Rw[j], pw[j], &fc, &fh);
+    Contact<double> a[8], b[8];
+    int na = 0, nb = 0;
+    finger_object_contacts(fc, Rw[j], fh, op, oR, ohe, a, &na, b, &nb);
+    out[f] = na + nb > 0;
+  }
+  out[2] = object_between_fingers(Rw[s->ee_body], pw[s->ee_body], q, op);
+  out[3] = out[0] && out[1] && out[2];
+}
+
+// Operation tallies of single building blocks on generic (non-structural)
+// operands, for checking the counter against hand counts: which = 0 one
+// free-body step (integrate_free), 1 one penalty contact force, 2 a 3-vector
+// cross product, 3 a quaternion's rotation matrix.  out: add, mul, fma, div,
+// sqrt, trans.
+void ref_count_block(int which, uint64_t out[6]) {
+  g_tally = Tally();
+  const Cnt a(0.3), b(-0.7), c(1.1), d(0.45), e(2.5), f(-1.3);
+  if (which == 0) {
+    Body<Cnt> bd;
+    bd.p = V3<Cnt>(a, b, c);
+    bd.q.w = Cnt(0.9); bd.q.x = Cnt(0.1); bd.q.y = Cnt(-0.3); bd.q.z = Cnt(0.2);
+    bd.v = V3<Cnt>(d, e, f);
+    bd.w = V3<Cnt>(b, c, d);
+    Wrench<Cnt> W;
+    W.f = V3<Cnt>(e, a, b);
+    W.tau = V3<Cnt>(c, f, a);
+    const V3<Cnt> Ib(Cnt(0.2), Cnt(0.3), Cnt(0.4)), gv(Cnt(0.0), Cnt(0.0), Cnt(-9.81));
+    g_tally = Tally();  // the set-up above performs no counted operation; start clean anyway
+    integrate_free(bd, W, Cnt(2.0), Ib, gv, Cnt(0.001));
+  } else if (which == 1) {
+    Contact<Cnt> ct;
+    ct.x = V3<Cnt>(a, b, c);
+    ct.n = V3<Cnt>(Cnt(0.6), Cnt(0.0), Cnt(0.8));
+    ct.d = Cnt(0.002);
+    const V3<Cnt> vA(d, e, f), vB(b, c, a);
+    g_tally = Tally();
+    penalty_force(ct, vA, vB, Cnt(1e4), Cnt(100.0), Cnt(0.5), Cnt(0.01));
+  } else if (which == 2) {
+    const V3<Cnt> x(a, b, c), y(d, e, f);
+    g_tally = Tally();
+    cross(x, y);
+  } else if (which == 3) {
+    Q4<Cnt> q;
+    q.w = Cnt(0.9); q.x = Cnt(0.1); q.y = Cnt(-0.3); q.z = Cnt(0.2);
+    g_tally = Tally();
+    quat_to_mat(q);
+  }
+  out[0] = g_tally.add; out[1] = g_tally.mul; out[2] = g_tally.fma;
+  out[3] = g_tally.div; out[4] = g_tally.sqrt; out[5] = g_tally.trans;
+}
+
 // ---- surrogate network ----
 long ref_mlp_n_params(void) { return mlp_n_params(); }
+
+// Elementwise building blocks of the network, for pins at known values.
+void ref_gelu_vec(const double *x, int n, double *y, double *dy) {
+  for (int i = 0; i < n; ++i) {
+    y[i] = gelu(x[i]);
+    dy[i] = gelu_grad(x[i]);
+  }
+}
+void ref_to_bf16_vec(const double *x, int n, double *y) {
+  for (int i = 0; i < n; ++i) y[i] = to_bf16(x[i]);
+}
 
 // He-normal initialisation: W entry p of layer l ~ N(0, 2 / fan_in) from the
 // normals of Philox stream 2 (block p / 4, sample 0, iteration 0, instance 0),

@@ -231,10 +231,15 @@ inline int sphere_box(const V3<T> &c, T r, const V3<T> &p, const M3<T> &R, const
 // the separating-axis test restricted to the six face normals.  Along the unit
 // axis a, box A covers p_A.a +- sum_k h_A,k |a . R_A e_k|, and likewise B; if
 // the two intervals are disjoint along one of these axes the boxes do not
-// intersect, so no vertex of either lies inside the other.
+// intersect, so no vertex of either lies inside the other.  It only skips
+// vertex tests that find nothing; g_face_cull = false switches it off (every
+// pair then runs the vertex tests), which the pins use to show that the
+// rollouts do not change.
+inline bool g_face_cull = true;
 template <class T>
 inline bool face_separated(const V3<T> &pA, const M3<T> &RA, const V3<T> &hA, const V3<T> &pB, const M3<T> &RB,
                            const V3<T> &hB) {
+  if (!g_face_cull) return false;
   const V3<T> d = pB - pA;
   const T ha[3] = {hA.x, hA.y, hA.z}, hb[3] = {hB.x, hB.y, hB.z};
   for (int side = 0; side < 2; ++side) {

@@ -176,8 +176,50 @@ template <class T> inline T smooth(T x) {
   return c * c * (T(3.0) - T(2.0) * c);
 }
 
+// Collision box of link j from its frame pose (Rw, pw): centre and half extents.
 template <class T>
-RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z, double *trace, int trace_steps) {
+inline void link_box(const RefScene &s, int j, const M3<T> &Rw, const V3<T> &pw, V3<T> *c, V3<T> *h) {
+  *c = pw + mul(Rw, V3<T>(T(s.b_com[j][0]), T(s.b_com[j][1]), T(s.b_com[j][2])));
+  *h = V3<T>(T(s.b_half[j][0]), T(s.b_half[j][1]), T(s.b_half[j][2]));
+}
+
+// The contacts between a finger box (fc, Rf, fh) and the object box (op, oR,
+// ohe), both ways: finger vertices inside the object (a[0..*na)) and object
+// vertices inside the finger (b[0..*nb)).  The finger touches the object when
+// there is at least one.
+template <class T>
+inline void finger_object_contacts(const V3<T> &fc, const M3<T> &Rf, const V3<T> &fh, const V3<T> &op, const M3<T> &oR,
+                                   const V3<T> &ohe, Contact<T> a[8], int *na, Contact<T> b[8], int *nb) {
+  const bool nearf = !face_separated(fc, Rf, fh, op, oR, ohe);
+  *na = nearf ? box_verts_in_box(fc, Rf, fh, op, oR, ohe, a) : 0;
+  *nb = nearf ? box_verts_in_box(op, oR, ohe, fc, Rf, fh, b) : 0;
+}
+
+// The gripper encloses the object (Eq. 5 and its text): the object's centre
+// lies between the fingers' inner faces.  The fingers slide along the palm's
+// y axis, the left one's inner face at palm y = q_L, the right one's at -q_R.
+template <class T>
+inline bool object_between_fingers(const M3<T> &R_palm, const V3<T> &p_palm, const T *q, const V3<T> &obj_p) {
+  const V3<T> ob_palm = mulT(R_palm, obj_p - p_palm);
+  return ob_palm.y < q[FL] && ob_palm.y > -q[FR];
+}
+
+// Per-step record of a robot rollout's action sequencing: act[t] the action
+// that controls step t (n_act once every action has ended) and, optionally,
+// the joint references of that step, for the first `steps` control steps;
+// ends[a] the step at which action a stopped controlling (T_a + 1 =
+// t_{0,a+1}, -1 if it never ended); ok the success bits of the actions.
+struct RobotLog {
+  int32_t *act = nullptr;
+  double *qref = nullptr;  // nullable: the joint references of each logged step, steps x 11
+  int steps = 0;
+  int32_t ends[4] = {-1, -1, -1, -1};
+  int32_t ok = 0;
+};
+
+template <class T>
+RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z, double *trace, int trace_steps,
+                         RobotLog *log = nullptr) {
   const Tree tr = tree_of(s);
   Mat6<T> Ibody[MAXJ];  // body inertias: constants of the tree, built once
   for (int j = 0; j < tr.n; ++j) Ibody[j] = body_inertia<T>(tr, j);
@@ -323,8 +365,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       M3<T> Rw[MAXJ];
       V3<T> pw[MAXJ];
       forward_kinematics(tr, q, Rw, pw);
-      const V3<T> ob_palm = mulT(Rw[s.ee_body], ob.p - pw[s.ee_body]);
-      const bool between = ob_palm.y < q[FL] && ob_palm.y > -q[FR];
+      const bool between = object_between_fingers(Rw[s.ee_body], pw[s.ee_body], q, ob.p);
       return touch[0] && touch[1] && between && err <= T(s.ee_tol);
     }
     const T tend = acts[a] == PUSH ? Ta + Td + Tq + Tr : Tp + Tr;
@@ -350,10 +391,15 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       const bool tout = r_val(tau) >= timeout_of(act);
       if (succ || tout) {
         ok[act] = succ;
+        if (log) {
+          log->ends[act] = t;
+          if (succ) log->ok |= 1 << act;
+        }
         ++act;
         if (act < n_act) start_action(act, t);
       }
     }
+    if (log && t < log->steps) log->act[t] = act;
     if (act < n_act) ++unsuccessful;
     // references for this control step
     if (act < n_act) {
@@ -394,6 +440,8 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
     }
     qref[FL] = finger_cmd;
     qref[FR] = finger_cmd;
+    if (log && log->qref && t < log->steps)
+      for (int j = 0; j < NJ; ++j) log->qref[(long)t * NJ + j] = r_val(qref[j]);
 
     for (int si = 0; si < s.substeps; ++si) {
       // kinematics and velocities of all links
@@ -439,25 +487,22 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       const bool last = si == s.substeps - 1;
       for (int f = 0; f < 2; ++f) {
         const int j = f == 0 ? FL : FR;
-        const V3<T> fc = pw[j] + mul(Rw[j], V3<T>(T(s.b_com[j][0]), T(s.b_com[j][1]), T(s.b_com[j][2])));
-        const V3<T> fh(T(s.b_half[j][0]), T(s.b_half[j][1]), T(s.b_half[j][2]));
-        bool any = false;
-        const bool nearf = !face_separated(fc, Rw[j], fh, ob.p, oR, ohe);
-        nc = nearf ? box_verts_in_box(fc, Rw[j], fh, ob.p, oR, ohe, cs) : 0;
+        V3<T> fc, fh;
+        link_box(s, j, Rw[j], pw[j], &fc, &fh);
+        Contact<T> cb[8];
+        int nb = 0;
+        finger_object_contacts(fc, Rw[j], fh, ob.p, oR, ohe, cs, &nc, cb, &nb);
         for (int i = 0; i < nc; ++i) {
           const V3<T> F = penalty_force(cs[i], link_vel(j, cs[i].x), obj_vel(cs[i].x), k, damp, T(mu_obj_tool), eps_v);
           link_force(j, cs[i].x, F);
           add_force(W, ob.p, cs[i].x, -F);
-          any = true;
         }
-        nc = nearf ? box_verts_in_box(ob.p, oR, ohe, fc, Rw[j], fh, cs) : 0;
-        for (int i = 0; i < nc; ++i) {
-          const V3<T> F = penalty_force(cs[i], obj_vel(cs[i].x), link_vel(j, cs[i].x), k, damp, T(mu_obj_tool), eps_v);
-          add_force(W, ob.p, cs[i].x, F);
-          link_force(j, cs[i].x, -F);
-          any = true;
+        for (int i = 0; i < nb; ++i) {
+          const V3<T> F = penalty_force(cb[i], obj_vel(cb[i].x), link_vel(j, cb[i].x), k, damp, T(mu_obj_tool), eps_v);
+          add_force(W, ob.p, cb[i].x, F);
+          link_force(j, cb[i].x, -F);
         }
-        if (last) touch[f] = any;
+        if (last) touch[f] = nc + nb > 0;
       }
       // base against static boxes, both ways
       {

@@ -96,3 +96,59 @@ def test_training_fits_a_smooth_target(oracle, P0):
         oracle.adam_step(P, g, m, v, k, lr=3e-3)
     l1 = oracle.mlp_loss_grad(P, x, t, False)[0]
     assert l1 < 0.1 * l0
+
+
+def test_gelu_at_known_values_and_against_the_library(oracle):
+    # tanh-form GELU: 0 at 0, x/2 (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))); its values at +-1 and 2 (the
+    # closed form evaluated with Python's libm); x for large x, 0 for very negative x; the derivative 1/2 at 0
+    y, dy = oracle.gelu([0.0, 1.0, -1.0, 2.0, 12.0, -12.0])
+    assert y[0] == 0.0 and dy[0] == 0.5
+    assert abs(y[1] - 0.8411919906082768) < 1e-15
+    assert abs(y[2] + 0.15880800939172324) < 1e-15
+    assert abs(y[3] - 1.954597694087775) < 1e-15
+    assert y[4] == 12.0 and abs(y[5]) < 1e-30
+    # against PyTorch's own tanh-form GELU and its autograd derivative, in float64
+    torch = pytest.importorskip("torch")
+    x = np.linspace(-6.0, 6.0, 241)
+    t = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    g = torch.nn.functional.gelu(t, approximate="tanh")
+    g.sum().backward()
+    y, dy = oracle.gelu(x)
+    assert np.max(np.abs(y - g.detach().numpy())) < 1e-15
+    assert np.max(np.abs(dy - t.grad.numpy())) < 1e-14
+
+
+def test_bf16_rounding_is_nearest_even(oracle):
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(8)
+    hi = rng.integers(0, 0x7F7F, 4000, dtype=np.uint32)         # finite bfloat16 patterns
+    ties = ((hi << 16) | 0x8000).view(np.float32).astype(np.float64)   # exactly halfway to the next bfloat16
+    up = ((hi << 16) | 0x8001).view(np.float32).astype(np.float64)
+    down = ((hi << 16) | 0x7FFF).view(np.float32).astype(np.float64)
+    got = oracle.to_bf16(ties)
+    # ties go to the even bfloat16: up when the kept pattern is odd, down when even
+    want = (((hi + (hi & 1)) << 16).astype(np.uint32)).view(np.float32).astype(np.float64)
+    assert np.array_equal(got, want)
+    assert np.array_equal(oracle.to_bf16(up), (((hi + 1) << 16).astype(np.uint32)).view(np.float32).astype(np.float64))
+    assert np.array_equal(oracle.to_bf16(down), ((hi << 16).astype(np.uint32)).view(np.float32).astype(np.float64))
+    # negative values, random values, the largest finite, infinities: as PyTorch's conversion
+    x = np.concatenate([-ties, rng.normal(size=4000) * 10.0 ** rng.uniform(-30, 30, 4000),
+                        [3.3895313892515355e38, 3.4e38, np.inf, -np.inf, 0.0, -0.0]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(oracle.to_bf16(x), ref)
+
+
+def test_adam_steps_two_and_three_match_the_library(oracle):
+    # three steps with different gradients: moments carried across steps, bias corrections at t = 2, 3
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(9)
+    P0 = rng.normal(size=500)
+    gs = [rng.normal(size=500) * s for s in (1.0, 0.3, 2.0)]
+    P, m, v = P0.copy(), np.zeros(500), np.zeros(500)
+    p = torch.tensor(P0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    for t, g in enumerate(gs, 1):
+        oracle.adam_step(P, g, m, v, t, lr=1e-3, eps=1e-8)
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        assert np.allclose(P, p.detach().numpy(), rtol=1e-13, atol=1e-16), t
