@@ -347,6 +347,19 @@ int cem_mlp_set_norm(cem_mlp *m, const float *host48);
 int cem_mlp_fit_norm(cem_mlp *m, const float *X_dev, const float *Y_dev, int64_t n, void *stream);
 /* predictions Y_dev (n x 8, de-standardised) of raw parameter rows X_dev (n x 16) */
 int cem_mlp_forward(cem_mlp *m, const float *X_dev, int32_t n, float *Y_dev, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * cem_mlp_forward with its work buffers - standardised inputs, two hidden
+ * layers, standardised outputs, 8.5 MiB in all - in a fixed array that the
+ * library holds on each device it runs on until the process ends, instead
+ * of the network's own buffers.  Same kernels, same results as
+ * cem_mlp_forward; calls no allocating routine.  X_dev (n x 16) and Y_dev
+ * (n x 8) as in cem_mlp_forward; n <= CEM_MLP_STATIC_ROWS, else CEM_E_ARG.
+ * Asynchronous on stream.  Every call on one device shares that device's
+ * array: calls ordered on one stream are safe, calls that overlap on one
+ * device (other streams, other host threads) race. */
+#define CEM_MLP_STATIC_ROWS 8192
+int cem_mlp_forward_static(cem_mlp *m, const float *X_dev, int32_t n, float *Y_dev, void *stream);
 /* mean squared error over n rows and 8 standardised outputs, and its gradient
  * w.r.t. the parameters (grad_dev, nullable) */
 int cem_mlp_loss_grad(cem_mlp *m, const float *X_dev, const float *Y_dev, int32_t n, float *grad_dev, float *loss_dev,

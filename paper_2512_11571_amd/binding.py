@@ -97,7 +97,7 @@ EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem
            "cem_batch_last_error", "cem_batch_instance", "cem_batch_autotune", "cem_batch_step", "cem_batch_solve",
            "cem_batch_record", "cem_mlp_init", "cem_mlp_free", "cem_mlp_n_params", "cem_mlp_last_error",
            "cem_mlp_get_params", "cem_mlp_set_params", "cem_mlp_get_norm", "cem_mlp_set_norm", "cem_mlp_fit_norm",
-           "cem_mlp_forward", "cem_mlp_loss_grad", "cem_mlp_train_step", "cem_mlp_train", "cem_screen",
+           "cem_mlp_forward", "cem_mlp_forward_static", "cem_mlp_loss_grad", "cem_mlp_train_step", "cem_mlp_train", "cem_screen",
            "plan_solve_screened"]
 
 _lib = None
@@ -158,6 +158,7 @@ def lib():
         L.cem_mlp_set_norm.argtypes = [vp, vp]
         L.cem_mlp_fit_norm.argtypes = [vp, vp, vp, i64, vp]
         L.cem_mlp_forward.argtypes = [vp, vp, _i, vp, vp]
+        L.cem_mlp_forward_static.argtypes = [vp, vp, _i, vp, vp]
         L.cem_mlp_loss_grad.argtypes = [vp, vp, vp, _i, vp, vp, vp]
         L.cem_mlp_train_step.argtypes = [vp, vp, vp, _i, ctypes.c_float, vp, vp]
         L.cem_mlp_train.argtypes = [vp, vp, vp, i64, _i, _i, ctypes.c_float, ctypes.c_uint64, vp]
@@ -567,6 +568,10 @@ class Mlp:
 
     def forward(self, X, Y, stream=None):
         self._check(lib().cem_mlp_forward(self.h, _dptr(X), X.shape[0], _dptr(Y), _stream(stream)))
+
+    def forward_static(self, X, Y, stream=None):
+        """The allocation-free forward (work buffers in the library's fixed device array)."""
+        self._check(lib().cem_mlp_forward_static(self.h, _dptr(X), X.shape[0], _dptr(Y), _stream(stream)))
 
     def loss_grad(self, X, Y, grad=None, loss=None, stream=None):
         self._check(lib().cem_mlp_loss_grad(self.h, _dptr(X), _dptr(Y), X.shape[0], _dptr(grad), _dptr(loss),

@@ -18,6 +18,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -504,6 +505,52 @@ __global__ void __launch_bounds__(256) screen_error_kernel(const float *__restri
 
 // ---- host side ---------------------------------------------------------------
 
+namespace cem {
+namespace {
+
+// Work buffers of cem_mlp_forward_static, for callers that cannot allocate:
+// standardised inputs (bf16, rows x 16), two hidden-layer buffers used in
+// turn (bf16, rows x 256 each) and the standardised outputs (fp32, rows x 8),
+// for up to CEM_MLP_STATIC_ROWS rows: 8.5 MiB, held by every device the
+// library runs on until the process ends.  Every region starts on a 256-byte
+// boundary.  Each call writes every element it reads, so nothing needs
+// clearing between calls.
+constexpr size_t SC_ROWS = CEM_MLP_STATIC_ROWS;
+constexpr size_t SC_XN = 0;
+constexpr size_t SC_H0 = SC_XN + SC_ROWS * IN * sizeof(uint16_t);
+constexpr size_t SC_H1 = SC_H0 + SC_ROWS * HID * sizeof(uint16_t);
+constexpr size_t SC_YN = SC_H1 + SC_ROWS * HID * sizeof(uint16_t);
+constexpr size_t SC_BYTES = SC_YN + SC_ROWS * OUT * sizeof(float);
+static_assert(SC_H0 % 256 == 0 && SC_H1 % 256 == 0 && SC_YN % 256 == 0, "256-byte aligned regions");
+
+__device__ __align__(256) unsigned char scratch[SC_BYTES];
+
+// The array's device address on each device (each device holds its own copy
+// at its own address).  Host code uses only these addresses: the array's name
+// in host code is not a device address.
+std::mutex scratch_mu;
+std::vector<void *> scratch_addr;
+
+// Looks up (once per device, with that device current) and returns the
+// current device's copy of the array; nullptr and *err set on failure.
+void *scratch_on_current_device(hipError_t *err) {
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess || dev < 0) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if ((size_t)dev >= scratch_addr.size()) scratch_addr.resize((size_t)dev + 1, nullptr);
+  if (!scratch_addr[dev]) {
+    void *p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    scratch_addr[dev] = p;
+  }
+  return scratch_addr[dev];
+}
+
+}  // namespace
+}  // namespace cem
+
 using namespace cem;
 
 struct cem_mlp {
@@ -668,6 +715,12 @@ int cem_mlp_init(uint64_t seed, int32_t max_rows, cem_mlp **out) {
     delete m;
     return CEM_E_ALLOC;
   }
+  hipError_t se = hipSuccess;
+  if (!scratch_on_current_device(&se)) {  // set-up of cem_mlp_forward_static on this device
+    mlp_release(m);
+    delete m;
+    return CEM_E_HIP;
+  }
   long w0[4], nw[4];
   int fan[4];
   for (int l = 0; l < 4; ++l) {
@@ -750,6 +803,46 @@ int cem_mlp_forward(cem_mlp *m, const float *X_dev, int32_t n, float *Y_dev, voi
   MHIPCHK(m, forward_n(m, X_dev, n, false, s));
   hipLaunchKernelGGL(denorm_out_kernel, dim3(blocks((long)n * OUT, 256)), dim3(256), 0, s, m->Yn, n,
                      m->norm + 2 * IN, m->norm + 2 * IN + OUT, Y_dev);
+  MHIPCHK(m, hipGetLastError());
+  return CEM_OK;
+}
+
+int cem_mlp_forward_static(cem_mlp *m, const float *X_dev, int32_t n, float *Y_dev, void *stream) {
+  if (!m) return CEM_E_ARG;
+  if (n < 0 || n > CEM_MLP_STATIC_ROWS)
+    return mfail(m, CEM_E_ARG, "n out of range [0, CEM_MLP_STATIC_ROWS = 8192] of the fixed work buffers");
+  if (n == 0) return CEM_OK;
+  if (!X_dev || !Y_dev) return mfail(m, CEM_E_ARG, "null buffer");
+  hipError_t e = hipSuccess;
+  unsigned char *scr = (unsigned char *)scratch_on_current_device(&e);
+  if (!scr) return mfail(m, CEM_E_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+  uint16_t *Xn = (uint16_t *)(scr + SC_XN);
+  uint16_t *Hs[2] = {(uint16_t *)(scr + SC_H0), (uint16_t *)(scr + SC_H1)};
+  float *Yn = (float *)(scr + SC_YN);
+  hipStream_t s = (hipStream_t)stream;
+  // the layers of forward_n, the hidden activations alternating between the
+  // two buffers (a layer reads one and writes the other)
+  hipLaunchKernelGGL(norm_in_kernel, dim3(blocks((long)n * IN, 256)), dim3(256), 0, s, X_dev, n, m->norm,
+                     m->norm + IN, Xn);
+  const uint16_t *in = Xn;
+  long a_m = IN;
+  for (int l = 0; l < NL; ++l) {
+    const int ni = DIMS[l], no = DIMS[l + 1];
+    const uint16_t *W = m->Pb + w_off(l);
+    const float *bias = m->P + b_off(l);
+    GemmArgs g;
+    if (l < NL - 1)
+      g = gargs(in, a_m, 1, W, 1, ni, n, no, ni, EPI_BIAS_GELU, bias, nullptr, nullptr, Hs[l & 1], no);
+    else
+      g = gargs(in, a_m, 1, W, 1, ni, n, no, ni, EPI_BIAS, bias, nullptr, Yn, nullptr, no);
+    MHIPCHK(m, gemm(g, s));
+    if (l < NL - 1) {
+      in = Hs[l & 1];
+      a_m = no;
+    }
+  }
+  hipLaunchKernelGGL(denorm_out_kernel, dim3(blocks((long)n * OUT, 256)), dim3(256), 0, s, Yn, n, m->norm + 2 * IN,
+                     m->norm + 2 * IN + OUT, Y_dev);
   MHIPCHK(m, hipGetLastError());
   return CEM_OK;
 }
