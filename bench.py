@@ -138,10 +138,10 @@ def bench_batch(a):
     spec = workloads.load(a.workload)["batch"]
     kinds = list(spec["kinds"])
     insts = workloads.batch_instances(spec)
-    if a.settle_steps:                # early stop on the robot instances
-        for i in insts:
-            if i["workload"]["scene"]["kind"] != "push":
-                i["workload"]["scene"]["settle_steps"] = a.settle_steps
+    for i in insts:                   # early stops on the robot instances
+        if i["workload"]["scene"]["kind"] != "push":
+            i["workload"]["scene"]["settle_steps"] = a.settle_steps
+            i["workload"]["scene"]["fail_stop"] = int(a.fail_stop)
     K = a.steps if a.steps is not None else 3
     nominal = {k: int(spec["iters"][k]) for k in kinds}
     timed = [dict(i, iters=max(i["iters"], K)) for i in insts]
@@ -182,7 +182,7 @@ def bench_batch(a):
     ceiling = _valu_ceiling()
     tr = MEASURED_TRAFFIC.get(a.workload)
     traffic = (tr["bytes_per_launch"] if tr and tr.get("src_hash") == _src_hash(a.workload)
-               and not a.settle_steps else None)
+               and not a.settle_steps and not a.fail_stop else None)
     out = {
         "metric": "env-steps/s (CE iterations/s alongside)",
         "value": counted / elapsed,
@@ -192,7 +192,8 @@ def bench_batch(a):
         "dtype": "f32 (FP64 refit and Cholesky)", "data": "synthetic (seeded instances, scenes and Philox samples)",
         "config": {"workload": a.workload, "instances": len(insts), "kinds": kinds,
                    "env_steps_per_iter": env_steps_iter, "nominal_iters": nominal,
-                   "timed_iters_per_instance": K, "autotune": tune, "settle_steps": a.settle_steps},
+                   "timed_iters_per_instance": K, "autotune": tune, "settle_steps": a.settle_steps,
+                   "fail_stop": int(a.fail_stop)},
         "env_steps_simulated": counted, "env_steps_full_horizon": env_steps_iter * K,
         "step_event_ms": roll_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -354,6 +355,9 @@ def main():
                     help="robot workloads: stop a rollout once its plan has ended and the object has rested this "
                          "many control steps (0: every rollout runs the full horizon); throughput then counts the "
                          "steps actually simulated")
+    ap.add_argument("--fail-stop", action="store_true",
+                    help="robot workloads: stop a rollout when an action fails (its plan can no longer be "
+                         "feasible); throughput then counts the steps actually simulated")
     ap.add_argument("--lanes", default="auto",
                     help="lanes per environment of a single robot instance (1, 2, 4, 8, 16; auto: the most whose "
                          "waves fit one per SIMD)")
@@ -387,11 +391,12 @@ def main():
     from paper_2512_11571_amd.binding import Context
 
     w = workloads.load(a.workload)
-    if a.settle_steps:
+    if a.settle_steps or a.fail_stop:
         if w["scene"]["kind"] == "push":
-            print("--settle-steps applies to the robot workloads only", file=sys.stderr)
+            print("--settle-steps and --fail-stop apply to the robot workloads only", file=sys.stderr)
             sys.exit(2)
         w["scene"]["settle_steps"] = a.settle_steps
+        w["scene"]["fail_stop"] = int(a.fail_stop)
     cem, sc = w["cem"], w["scene"]
     pop, H, D = cem["pop"], sc["horizon"], {"push": 3, "pickplace": 16, "movepush": 12}[sc["kind"]]
     sched = cem.get("pop_schedule")
@@ -442,7 +447,8 @@ def main():
     ceiling = _valu_ceiling()
     tr = MEASURED_TRAFFIC.get(a.workload)
     traffic = (tr["bytes_per_launch"] if tr and tr.get("src_hash") == _src_hash(a.workload)
-               and tr.get("lanes", 1) == lanes and not sc.get("settle_steps", 0) else None)
+               and tr.get("lanes", 1) == lanes and not sc.get("settle_steps", 0) and not sc.get("fail_stop", 0)
+               else None)
     out = {
         "metric": "env-steps/s (CE iterations/s alongside)",
         "value": value,
@@ -459,7 +465,8 @@ def main():
         "data": "synthetic (seeded scene and Philox samples)",
         "config": {"workload": a.workload, "pop": pop, "horizon": H, "substeps": sc["substeps"], "dim": D,
                    "n_elite": cem["n_elite"], "dt": sc["dt"], "seed": a.seed,
-                   "settle_steps": sc.get("settle_steps", 0), "pop_schedule": sched,
+                   "settle_steps": sc.get("settle_steps", 0), "fail_stop": sc.get("fail_stop", 0),
+                   "pop_schedule": sched,
                    "init_region": bool(cem.get("init_region")), "dr_scenarios": R, "lanes_per_env": lanes},
         "env_steps_simulated": env_steps,
         "env_steps_full_horizon": full,

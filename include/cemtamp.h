@@ -122,6 +122,14 @@ typedef struct cem_scene {
    * moving again afterwards can differ from the full-horizon result.  The
    * push scene ignores it. */
   int32_t settle_steps;
+  /* Stop of a robot rollout on a failed action (0: off).  When 1, a rollout
+   * ends at the control step at which an action ends without success (its
+   * timeout): the plan can no longer be feasible, since Problem 2 needs every
+   * action to succeed, and Alg. 1 evaluates only the costs of successful
+   * plans.  The stopped plan reports tier 2, the cost of the steps before the
+   * stop and the object's pose there; plans whose actions all succeed run as
+   * without the option.  The push scene ignores it. */
+  int32_t fail_stop;
   /* Domain randomisation (Sec. IV-C: plans made robust to bounded uncertainty
    * in friction or mass).  dr_scenarios R in {0, 1}: off.  R in {2, 4, ..., 64}
    * (robot scenes): every parameter row is rolled out under R scenarios.
@@ -284,6 +292,11 @@ int cem_get_scenarios(cem_ctx *c, float *mu, float *mass);
  * diverged.  Batched runs count into each instance's context.  Waits for all
  * work on the device first.  Synchronous. */
 int cem_env_steps(cem_ctx *c, uint64_t *steps);
+/* Outcomes of the rollouts into the context's own buffers (the iterations of
+ * plan_solve and of batched steps write them; the last iteration's remain):
+ * host cost[n], tier[n] and, if pose is non-NULL, pose[n][7] of rows 0..n-1,
+ * n <= pop.  Waits for all work on the device first.  Synchronous. */
+int cem_get_outcomes(cem_ctx *c, int32_t n, float *cost, uint8_t *tier, float *pose);
 /* Reset the best-so-far record and the iteration counter. Synchronous. */
 int cem_reset(cem_ctx *c);
 

@@ -46,7 +46,7 @@ class RefScene(ctypes.Structure):
         ("goal_static", _i), ("joint_speed_max", _d), ("accel_max", _d),
         ("push_vmin", _d), ("push_vmax", _d), ("push_dmax", _d), ("timeout_push", _d),
         ("obj_mu_lo", _d), ("obj_mu_hi", _d), ("goal_box_center", _d * 3), ("goal_box_half", _d * 3),
-        ("settle_steps", _i), ("dr_scenarios", _i), ("dr_reduce", _i),
+        ("settle_steps", _i), ("fail_stop", _i), ("dr_scenarios", _i), ("dr_reduce", _i),
         ("dr_mu_lo", _d), ("dr_mu_hi", _d), ("dr_mass_lo", _d), ("dr_mass_hi", _d),
     ]
 
@@ -93,7 +93,7 @@ def lib():
         L.ref_sample.argtypes = [u64, u32, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.ref_draw_instance.argtypes = [P(RefScene), u64, u32, vp]
         L.ref_rollout.argtypes = [P(RefScene), u64, u32, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int,
-                                  ctypes.c_int, vp]
+                                  ctypes.c_int, vp, vp, vp]
         L.ref_count_ops.argtypes = [P(RefScene), u64, u32, vp, vp]
         L.ref_select.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp]
         L.ref_cholesky.argtypes = [ctypes.c_int, vp, vp]
@@ -116,6 +116,8 @@ def lib():
         L.ref_mlp_forward.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int]
         L.ref_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, vp]
         L.ref_mlp_loss_grad.restype = ctypes.c_double
+        L.ref_mlp_loss_grad_bf16.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+        L.ref_mlp_loss_grad_bf16.restype = ctypes.c_double
         L.ref_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_long, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.ref_object_sim.argtypes = [P(RefScene), vp, vp, vp, ctypes.c_int, vp]
@@ -218,6 +220,7 @@ def make_scene(workload):
                 s.goal_box_half[k] = gb["half"][k]
     s.obj_mu_lo, s.obj_mu_hi = ob.get("mu", (0.0, 0.0))
     s.settle_steps = sc.get("settle_steps", 0)
+    s.fail_stop = int(sc.get("fail_stop", 0))
     dr = sc.get("domain_randomization")
     if dr:
         s.dr_scenarios = int(dr["scenarios"])
@@ -322,9 +325,10 @@ def draw_instance(workload, seed, inst=0):
     return g
 
 
-def rollout(workload, seed, Z, inst=0, trace_steps=0, threads=None, with_steps=False):
+def rollout(workload, seed, Z, inst=0, trace_steps=0, threads=None, with_steps=False, with_rest=False):
     """FP64 rollouts of the rows of Z: returns cost (f64), tier (u8), pose (pop x 7), trace or None
-    (and, with_steps, the control steps each rollout simulated)."""
+    (and, with_steps, the control steps each rollout simulated; with_rest, the object's final speed and
+    the consecutive final control steps it spent below the rest speed)."""
     s = make_scene(workload)
     Z = np.ascontiguousarray(Z, np.float32)
     pop = Z.shape[0]
@@ -335,13 +339,19 @@ def rollout(workload, seed, Z, inst=0, trace_steps=0, threads=None, with_steps=F
     trace = np.zeros((pop, trace_steps, tw), np.float64) if trace_steps else None
     threads = threads or default_threads()
     steps = np.zeros(pop, np.int32)
+    speed = np.zeros(pop, np.float64)
+    rest = np.zeros(pop, np.int32)
     rc = lib().ref_rollout(ctypes.byref(s), seed, inst, pop, _ptr(Z), _ptr(cost), _ptr(tier), _ptr(pose),
-                           _ptr(trace) if trace is not None else None, trace_steps, threads, _ptr(steps))
+                           _ptr(trace) if trace is not None else None, trace_steps, threads, _ptr(steps),
+                           _ptr(speed), _ptr(rest))
     if rc != 0:
         raise RuntimeError("oracle rollout failed (%d)" % rc)
+    out = (cost, tier, pose, trace)
     if with_steps:
-        return cost, tier, pose, trace, steps
-    return cost, tier, pose, trace
+        out = out + (steps,)
+    if with_rest:
+        out = out + (speed, rest)
+    return out
 
 
 def count_ops(workload, seed, z, inst=0):
@@ -501,10 +511,12 @@ def mlp_forward(P, x, bf16=False):
     return y
 
 
-def mlp_loss_grad(P, x, t, want_grad=True):
+def mlp_loss_grad(P, x, t, want_grad=True, bf16=False):
+    """MSE loss and its gradient; bf16: with BF16 operands in every product (forward and backward)."""
     x, t = _f64(x), _f64(t)
     g = np.zeros(mlp_n_params()) if want_grad else None
-    loss = lib().ref_mlp_loss_grad(_ptr(_f64(P)), _ptr(x), _ptr(t), x.shape[0], _ptr(g) if want_grad else None)
+    f = lib().ref_mlp_loss_grad_bf16 if bf16 else lib().ref_mlp_loss_grad
+    loss = f(_ptr(_f64(P)), _ptr(x), _ptr(t), x.shape[0], _ptr(g) if want_grad else None)
     return loss, g
 
 

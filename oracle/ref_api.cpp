@@ -117,7 +117,8 @@ void ref_draw_instance(const RefScene *s, uint64_t seed, uint32_t inst, double o
 
 // Roll out pop parameter rows; trace (optional) gets trace_steps states per env.
 int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const float *Z, double *cost,
-                uint8_t *tier, double *pose, double *trace, int trace_steps, int threads, int32_t *steps) {
+                uint8_t *tier, double *pose, double *trace, int trace_steps, int threads, int32_t *steps,
+                double *speed, int32_t *rest_steps) {
   const int D = param_dim(*s);
   const Instance in = draw_instance(*s, seed, inst);
   if (s->kind != SCENE_PUSH && s->kind != SCENE_PICKPLACE && s->kind != SCENE_MOVEPUSH) return 1;
@@ -140,6 +141,8 @@ int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const 
         n_steps += o.steps;
         if (r == 0 && pose)
           for (int c = 0; c < 7; ++c) pose[(long)i * 7 + c] = o.pose[c];
+        if (r == 0 && speed) speed[i] = o.speed;
+        if (r == 0 && rest_steps) rest_steps[i] = o.rest_steps;
       }
       cost[i] = s->dr_reduce ? c_max : c_sum / R;
       tier[i] = (uint8_t)t_max;
@@ -155,6 +158,8 @@ int ref_rollout(const RefScene *s, uint64_t seed, uint32_t inst, int pop, const 
     if (pose)
       for (int c = 0; c < 7; ++c) pose[(long)i * 7 + c] = o.pose[c];
     if (steps) steps[i] = o.steps;
+    if (speed) speed[i] = o.speed;
+    if (rest_steps) rest_steps[i] = o.rest_steps;
   });
   return 0;
 }
@@ -478,6 +483,11 @@ double ref_mlp_loss_grad(const double *P, const double *x, const double *t, int 
   return mlp_loss_grad(P, x, t, n, dP);
 }
 
+// The same with BF16 operands in the forward and backward products (bf16 = 1).
+double ref_mlp_loss_grad_bf16(const double *P, const double *x, const double *t, int n, double *dP) {
+  return mlp_loss_grad(P, x, t, n, dP, true);
+}
+
 void ref_adam_step(double *P, const double *g, double *m, double *v, long n, double lr, double b1, double b2,
                    double eps, int t) {
   adam_step(P, g, m, v, n, lr, b1, b2, eps, t);
@@ -526,7 +536,8 @@ int ref_plan_solve(const RefScene *s, uint64_t seed, uint32_t inst, int pop, int
       ref_sample_region(seed, inst, pop, D, lo, hi, n_rings, ring_dim, ring, Z.data());
     else
       ref_sample(seed, (uint32_t)j, inst, pop, D, mu.data(), L.data(), Z.data());
-    ref_rollout(s, seed, inst, pop, Z.data(), cost.data(), tier.data(), nullptr, nullptr, 0, threads, nullptr);
+    ref_rollout(s, seed, inst, pop, Z.data(), cost.data(), tier.data(), nullptr, nullptr, 0, threads, nullptr, nullptr,
+                nullptr);
     for (int i = 0; i < pop; ++i) costf[i] = (float)cost[i];
     int32_t mode, counts[4];
     const int ne = select_elites(pop, costf.data(), tier.data(), n_elite, elite.data(), &mode, counts);

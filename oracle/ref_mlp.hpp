@@ -97,10 +97,16 @@ inline void mlp_forward(const double *P, const double *x, int n, double *y, bool
 }
 
 // Mean squared error over n rows and gradient dP (same layout as P).
-inline double mlp_loss_grad(const double *P, const double *x, const double *t, int n, double *dP) {
+// bf16: the backward of a BF16-operand / FP32-accumulate matrix unit, up to
+// the accumulation order: the BF16 forward, and the operands of every product
+// of the backward - the output gradients dL/dz of each layer, the weights
+// and the activations - rounded to bfloat16, while the bias gradients sum the
+// unrounded dL/dz and the GELU derivative takes the FP32 pre-activation.
+inline double mlp_loss_grad(const double *P, const double *x, const double *t, int n, double *dP, bool bf16 = false) {
   MlpCache c;
   std::vector<double> y((size_t)n * MLP_DIMS[MLP_L]);
-  mlp_forward(P, x, n, y.data(), false, &c);
+  mlp_forward(P, x, n, y.data(), bf16, &c);
+  auto rnd = [&](double v) { return bf16 ? to_bf16(v) : v; };
   const int no = MLP_DIMS[MLP_L];
   const double scale = 1.0 / ((double)n * no);
   double loss = 0.0;
@@ -122,15 +128,17 @@ inline double mlp_loss_grad(const double *P, const double *x, const double *t, i
       for (int o = 0; o < nol; ++o) {
         const double g = dz[(size_t)r * nol + o];
         db[o] += g;
-        for (int i = 0; i < ni; ++i) dW[(long)o * ni + i] += g * ain[(size_t)r * ni + i];
+        const double gr = rnd(g);
+        for (int i = 0; i < ni; ++i) dW[(long)o * ni + i] += gr * ain[(size_t)r * ni + i];
       }
     if (l == 0) break;
     std::vector<double> dprev((size_t)n * ni, 0.0);
     for (int r = 0; r < n; ++r)
       for (int i = 0; i < ni; ++i) {
         double acc = 0.0;
-        for (int o = 0; o < nol; ++o) acc += dz[(size_t)r * nol + o] * W[(long)o * ni + i];
-        dprev[(size_t)r * ni + i] = acc * gelu_grad(c.z[l][(size_t)r * ni + i]);
+        for (int o = 0; o < nol; ++o) acc += rnd(dz[(size_t)r * nol + o]) * rnd(W[(long)o * ni + i]);
+        const double zp = c.z[l][(size_t)r * ni + i];
+        dprev[(size_t)r * ni + i] = acc * gelu_grad(bf16 ? (double)(float)zp : zp);
       }
     dz.swap(dprev);
   }

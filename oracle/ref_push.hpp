@@ -17,6 +17,11 @@ struct RolloutOut {
   int32_t tier;      // 0 ok, 3 diverged (the push plan has no other predicate)
   double pose[7];    // final object pose p (3), q (4)
   int32_t steps;     // control steps simulated
+  // observations for the parity tests, no part of the outcome: the object's
+  // final speed and the number of consecutive final control steps it spent
+  // slower than the scene's rest speed (robot scenes)
+  double speed = 0.0;
+  int32_t rest_steps = 0;
 };
 
 // Free-body state trace layout per control step: p(3) q(4) v(3) w(3).

@@ -383,6 +383,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
   bool diverged = false;
   int steps = s.horizon;
   int calm = 0;  // consecutive control steps with every action ended and the object at rest
+  int rest_run = 0;  // consecutive control steps with the object at rest (observed only)
   for (int t = 0; t < s.horizon; ++t) {
     // action sequencing
     if (act < n_act) {
@@ -396,6 +397,11 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
           if (succ) log->ok |= 1 << act;
         }
         ++act;
+        if (!succ && s.fail_stop) {
+          // the plan cannot become feasible any more: stop before step t
+          steps = t;
+          break;
+        }
         if (act < n_act) start_action(act, t);
       }
     }
@@ -543,6 +549,7 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
       for (int j = 0; j < NJ; ++j) { o[13 + j] = r_val(q[j]); o[24 + j] = r_val(qd[j]); }
     }
     if (!r_finite(ob.p.x) || !r_finite(q[0])) { diverged = true; steps = t + 1; break; }
+    rest_run = std::sqrt(r_val(dot(ob.v, ob.v))) < s.rest_speed ? rest_run + 1 : 0;
     if (s.settle_steps > 0) {
       // early stop: the plan has ended and the object has stayed at rest; the
       // cost no longer changes and psi_g is read at this step
@@ -568,6 +575,8 @@ RolloutOut robot_rollout(const RefScene &s, const Instance &inst, const float *z
   }
   RolloutOut out;
   out.steps = steps;
+  out.speed = std::sqrt(r_val(dot(ob.v, ob.v)));
+  out.rest_steps = rest_run;
   const T cost = T(s.time_weight) * dt * T((double)unsuccessful);
   out.cost = r_val(cost);
   out.pose[0] = r_val(ob.p.x); out.pose[1] = r_val(ob.p.y); out.pose[2] = r_val(ob.p.z);

@@ -56,6 +56,11 @@ struct RefScene {
   // early stop of a robot rollout (0 = off): once every action has ended, stop
   // after this many consecutive control steps with the object at rest
   int32_t settle_steps;
+  // stop a robot rollout when an action fails (0 = off): the plan can then no
+  // longer become feasible (every action must succeed, Problem 2), and Alg. 1
+  // evaluates only the costs of successful plans; the stopped plan reports
+  // tier 2 and the cost of the steps it ran
+  int32_t fail_stop;
   // domain randomisation (Sec. IV-C): R scenarios per parameter row (<= 1 off),
   // each with its own object friction / mass draw; the row's tier is the worst
   // and its cost the mean (dr_reduce 0) or maximum (1) over scenarios

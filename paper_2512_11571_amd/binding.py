@@ -60,7 +60,7 @@ class CemScene(ctypes.Structure):
         ("goal_static", _i), ("joint_speed_max", _f), ("accel_max", _f),
         ("push_vmin", _f), ("push_vmax", _f), ("push_dmax", _f), ("timeout_push", _f),
         ("obj_mu_lo", _f), ("obj_mu_hi", _f), ("goal_box_center", _f * 3), ("goal_box_half", _f * 3),
-        ("settle_steps", _i), ("dr_scenarios", _i), ("dr_reduce", _i),
+        ("settle_steps", _i), ("fail_stop", _i), ("dr_scenarios", _i), ("dr_reduce", _i),
         ("dr_mu_lo", _f), ("dr_mu_hi", _f), ("dr_mass_lo", _f), ("dr_mass_hi", _f),
     ]
 
@@ -92,7 +92,7 @@ class CemResult(ctypes.Structure):
 
 EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem_last_error", "cem_sample", "rollout_batch",
            "rollout_trace", "cem_refit", "plan_solve", "cem_get_theta", "cem_set_theta", "cem_get_factor",
-           "cem_get_instance", "cem_get_scenarios", "cem_env_steps", "cem_pop_at", "cem_reset",
+           "cem_get_instance", "cem_get_scenarios", "cem_env_steps", "cem_get_outcomes", "cem_pop_at", "cem_reset",
            "cem_valu_fma_rate", "cem_batch_init", "cem_batch_free", "cem_batch_size",
            "cem_batch_last_error", "cem_batch_instance", "cem_batch_autotune", "cem_batch_step", "cem_batch_solve",
            "cem_batch_record", "cem_mlp_init", "cem_mlp_free", "cem_mlp_n_params", "cem_mlp_last_error",
@@ -129,6 +129,7 @@ def lib():
         L.cem_get_factor.argtypes = [vp, vp]
         L.cem_get_instance.argtypes = [vp, vp]
         L.cem_env_steps.argtypes = [vp, P(ctypes.c_uint64)]
+        L.cem_get_outcomes.argtypes = [vp, _i, vp, vp, vp]
         L.cem_pop_at.argtypes = [vp, _i]
         L.cem_get_scenarios.argtypes = [vp, vp, vp]
         L.cem_valu_fma_rate.argtypes = [P(ctypes.c_double), vp]
@@ -250,6 +251,7 @@ def make_scene(workload):
                 s.goal_box_half[k] = gb["half"][k]
     s.obj_mu_lo, s.obj_mu_hi = ob.get("mu", (0.0, 0.0))
     s.settle_steps = int(sc.get("settle_steps", 0))
+    s.fail_stop = int(sc.get("fail_stop", 0))
     dr = sc.get("domain_randomization")
     if dr:
         s.dr_scenarios = int(dr["scenarios"])
@@ -345,6 +347,7 @@ class Context:
         self.D = DIM[self.kind]
         if handle is not None:          # borrowed from a batch, which owns it
             self.h, self._owned = handle, False
+            self.pop, self.n_elite = workload["cem"]["pop"], workload["cem"]["n_elite"]
             return
         p, self._keep = make_problem(workload, seed, instance, pop, n_elite, mu0, cov0, lanes)
         self.pop, self.n_elite = p.pop, p.n_elite
@@ -438,6 +441,15 @@ class Context:
         n = ctypes.c_uint64(0)
         self._check(lib().cem_env_steps(self.h, ctypes.byref(n)))
         return int(n.value)
+
+    def outcomes(self, n=None):
+        """(cost, tier, pose) of rows 0..n-1 of the context's own outcome buffers (the last iteration's)."""
+        n = self.pop if n is None else int(n)
+        cost = np.zeros(n, np.float32)
+        tier = np.zeros(n, np.uint8)
+        pose = np.zeros((n, 7), np.float32)
+        self._check(lib().cem_get_outcomes(self.h, n, _np_ptr(cost), _np_ptr(tier), _np_ptr(pose)))
+        return cost, tier, pose
 
     def reset(self):
         self._check(lib().cem_reset(self.h))

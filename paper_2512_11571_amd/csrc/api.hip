@@ -76,6 +76,7 @@ const char *check_scene(const cem_scene &s) {
   if (s.substeps < 1 || s.substeps > 1000) return "substeps out of range [1, 1000]";
   if (s.horizon < 1 || s.horizon > 100000) return "horizon out of range [1, 100000]";
   if (s.settle_steps < 0 || s.settle_steps > s.horizon) return "settle_steps out of range [0, horizon]";
+  if (s.fail_stop != 0 && s.fail_stop != 1) return "fail_stop must be 0 or 1";
   if (s.dr_scenarios < 0 || s.dr_scenarios > CEM_MAX_DR || (s.dr_scenarios & (s.dr_scenarios - 1)))
     return "dr_scenarios must be 0 or a power of two <= 64";
   if (s.dr_scenarios > 1 && s.kind == CEM_SCENE_PUSH) return "domain randomisation needs a robot scene";
@@ -490,6 +491,18 @@ int cem_env_steps(cem_ctx *c, uint64_t *steps) {
   return CEM_OK;
 }
 
+int cem_get_outcomes(cem_ctx *c, int32_t n, float *cost, uint8_t *tier, float *pose) {
+  if (!c) return CEM_E_ARG;
+  if (n < 0 || n > c->pop) return fail(c, CEM_E_ARG, "n out of range [0, pop]");
+  if (!cost || !tier) return fail(c, CEM_E_ARG, "null output");
+  HIPCHK(c, hipDeviceSynchronize());
+  if (n == 0) return CEM_OK;
+  HIPCHK(c, hipMemcpy(cost, c->cost, sizeof(float) * n, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(tier, c->tier, n, hipMemcpyDeviceToHost));
+  if (pose) HIPCHK(c, hipMemcpy(pose, c->pose, sizeof(float) * 7 * n, hipMemcpyDeviceToHost));
+  return CEM_OK;
+}
+
 int cem_reset(cem_ctx *c) {
   if (!c) return CEM_E_ARG;
   HIPCHK(c, hipDeviceSynchronize());
@@ -507,6 +520,7 @@ struct cem_batch {
   WorkItem *items = nullptr;
   int n_items = 0, max_pop = 0, item_envs = 64, grid = 0, n_cu = 0;
   int *queue = nullptr;
+  int *pool = nullptr;  // per instance: the next unstarted plan of its rollout (batched launch)
   hipStream_t own = nullptr;
   hipGraphExec_t graph = nullptr;
   std::string err;
@@ -571,7 +585,7 @@ int build_graph(cem_batch *b) {
   BHIPCHK(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
   const int n = (int)b->ctx.size();
   hipError_t e1 = launch_sample_batch(b->insts, n, b->max_pop, b->own);
-  hipError_t e2 = launch_rollout_batch(b->insts, b->items, b->n_items, b->queue, b->grid, b->own);
+  hipError_t e2 = launch_rollout_batch(b->insts, n, b->items, b->n_items, b->queue, b->pool, b->grid, b->own);
   hipError_t e3 = launch_select_refit_batch(b->insts, n, MAX_STATS_ITERS, b->own);
   hipError_t e4 = hipStreamEndCapture(b->own, &g);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
@@ -593,6 +607,7 @@ void batch_release(cem_batch *b) {
   (void)hipFree(b->insts);
   (void)hipFree(b->items);
   (void)hipFree(b->queue);
+  (void)hipFree(b->pool);
   for (cem_ctx *c : b->ctx) cem_free(c);
 }
 
@@ -630,6 +645,7 @@ int cem_batch_init(const cem_problem *problems, const int32_t *iters, int32_t n,
         hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&b->insts, sizeof(InstDesc) * n) != hipSuccess || hipMalloc(&b->queue, sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->pool, sizeof(int) * n) != hipSuccess ||
         hipMemcpy(b->insts, h.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice) != hipSuccess) {
       rc = CEM_E_HIP;
       b->err = "batch set-up";
@@ -691,7 +707,7 @@ int cem_batch_autotune(cem_batch *b, int32_t *config_out) {
     for (int mi = 0; mi < 3; ++mi) {
       const int grid = mults[mi] * b->n_cu;
       BHIPCHK(b, hipEventRecord(e0, b->own));
-      BHIPCHK(b, launch_rollout_batch(b->insts, b->items, b->n_items, b->queue, grid, b->own));
+      BHIPCHK(b, launch_rollout_batch(b->insts, n, b->items, b->n_items, b->queue, b->pool, grid, b->own));
       BHIPCHK(b, hipEventRecord(e1, b->own));
       BHIPCHK(b, hipEventSynchronize(e1));
       float ms = 0.0f;

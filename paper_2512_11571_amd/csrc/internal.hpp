@@ -94,8 +94,8 @@ hipError_t launch_select_refit(DevState *st, const float *Z, const float *cost, 
                                int advance_iter, hipStream_t s);
 hipError_t launch_select_refit_batch(const InstDesc *insts, int n_inst, int stats_cap, hipStream_t s);
 hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s);
-hipError_t launch_rollout_batch(const InstDesc *insts, const WorkItem *items, int n_items, int *queue, int grid,
-                                hipStream_t s);
+hipError_t launch_rollout_batch(const InstDesc *insts, int n_inst, const WorkItem *items, int n_items, int *queue,
+                                int *pool, int grid, hipStream_t s);
 hipError_t launch_scene_consts(DevState *st, hipStream_t s);
 hipError_t launch_pack_dataset(const InstDesc &d, float cost_cap, float *X, float *Y, hipStream_t s);
 

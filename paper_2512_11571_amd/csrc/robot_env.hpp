@@ -128,9 +128,18 @@ struct EnvOut {
   float pose[7];
 };
 
-// Rolls out row `env` of Z (16 parameters for pick-and-place, 12 for
-// move-push) with the object's friction `mu_obj` (0: the per-class
-// coefficients) and mass `om`, and (TRACE) writes its per-step trace.
+// Rolls out parameter rows of Z (16 parameters for pick-and-place, 12 for
+// move-push), one after another on this lane: first row0 (if live0), then
+// each row that `claim` hands out when a rollout ends, until it hands out
+// none.  Each rollout runs with the object's friction `mu_obj` (0: the
+// per-class coefficients) and mass `om`, and (TRACE) writes its per-step
+// trace; its outcome goes to finish(EnvOut, row).  Returns the control steps
+// this lane simulated.  The wave steps its lanes together, one control step
+// per loop iteration, each lane at its own step of its own rollout, so a lane
+// whose rollout ends can start the next while the others run on.
+//   claim(need, row, live): called by every lane of the wave at the same
+//     point; for each lane with `need` set it stores the next row in `row`
+//     and sets `live`, or clears `live` when there is none.
 // `lds_mem` is the block's R_ROWS x PP_LANES float array and `lane` this
 // lane's column in it.  The scene and its derived constants come from `st`.
 // G adjacent lanes (1, 2, 4, 8 or 16; gi this lane's place among them) run
@@ -138,12 +147,13 @@ struct EnvOut {
 // test of the object and the base against the world, and a share of the
 // finger-object tests (G 2: one finger; G 4: one finger, one direction; G 8,
 // 16: that, on part of the corners);
-// the forces are then summed over the group.  With G = 1 the sums run in the
-// original order; the MULTI = false instance compiles G = 1 in.
-template <bool TRACE, bool MULTI>
-__device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restrict__ Z, long env, float mu_obj,
-                                             float om, float *lds_mem, int lane, int gi_in, int G_in,
-                                             float *__restrict__ trace, int trace_steps) {
+// the forces are then summed over the group, whose lanes therefore start and
+// end their rollouts together.  With G = 1 the sums run in the original
+// order; the MULTI = false instance compiles G = 1 in.
+template <bool TRACE, bool MULTI, class Claim, class Finish>
+__device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict__ Z, long row0, bool live0,
+                                          float mu_obj, float om, float *lds_mem, int lane, int gi_in, int G_in,
+                                          float *__restrict__ trace, int trace_steps, Claim claim, Finish finish) {
   // !MULTI: one lane per environment, known at compile time
   const int G = MULTI ? G_in : 1, gi = MULTI ? gi_in : 0;
   CScene &sc = st->scene;
@@ -165,25 +175,7 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
   const V3f gv = v3(0.0f, 0.0f, -g);
 
   Params4 zp;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) zp.v[a][i] = 4 * a + i < n_par ? Z[(long)env * n_par + 4 * a + i] : 0.0f;
-
-  for (int j = 0; j < NJ; ++j) {
-    L.at(R_Q + j) = sc.q0[j];
-    L.at(R_QD + j) = 0.0f;
-    if (j <= FL) L.at(R_QREF + j) = sc.q0[j];
-  }
   FreeBody ob;
-  ob.p = v3(sc.obj_pos0[0], sc.obj_pos0[1], sc.obj_pos0[2] - om * g / (4.0f * kc));
-  {
-    float s, c;
-    sincosf(0.5f * sc.obj_yaw0, &s, &c);
-    ob.q = Q4f{c, 0.0f, 0.0f, s};
-  }
-  ob.v = v3(0.0f, 0.0f, 0.0f);
-  ob.w = v3(0.0f, 0.0f, 0.0f);
 
   // controller state
   int act = 0, t_start = 0;
@@ -305,131 +297,184 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
     }
   };
 
-  start_action(0, 0);
-  bool diverged = false;
-  int steps = sc.horizon;
-  int calm = 0;  // consecutive control steps with every action ended and the object at rest
-  for (int t = 0; t < sc.horizon; ++t) {
-    // ---- action sequencing (control rate) ----
-    if (act < n_act) {
-      float q[NJ];
-      load_q(q);
-      const float tau = (float)(t - t_start) * dt;
-      const int kind = act_kind(pnp, act);
-      bool succ;
-      if (kind == MOVE) {
-        float pz[4];
-        action_params(zp, act, pz);
-        const float dx = q[0] - pz[0], dy = q[1] - pz[1];
-        succ = sqrtf(dx * dx + dy * dy) <= sc.base_tol && fabsf(wrap_pi(q[2] - pz[2])) <= sc.yaw_tol;
-      } else {
-        M3f Rw[PALM + 1];
-        V3f pw[PALM + 1];
-        chain_fk(sc, q, Rw, pw);
-        const V3f pe = ee_point(sc, Rw[PALM], pw[PALM]);
-        const V3f de = pe - ptarget;
-        const bool near = sqrtf(dot(de, de)) <= sc.ee_tol;
-        if (kind == PICK) {
-          const float tend = Ta + Td + sc.t_close + Tl;
-          const V3f op = mulT(Rw[PALM], ob.p - pw[PALM]);
-          const bool between = op.y < q[FL] && op.y > -q[FR];
-          succ = tau >= tend && touchL && touchR && between && near;
-        } else if (kind == PUSH) {
-          succ = tau >= Ta + Td + Tq + sc.t_release && near;
-        } else {
-          succ = tau >= Tp + sc.t_release && near;
-        }
-      }
-      const float tout = kind == MOVE   ? sc.timeout_move
-                         : kind == PICK ? sc.timeout_pick
-                         : kind == PUSH ? sc.timeout_push
-                                        : sc.timeout_place;
-      if (succ || tau >= tout) {
-        if (succ) ok_bits |= 1u << act;
-        ++act;
-        if (act < n_act) start_action(act, t);
-      }
-    }
-    if (act < n_act) ++unsuccessful;
-    // ---- references ----
-    if (act < n_act) {
-      const float tau = (float)(t - t_start) * dt;
-      const int kind = act_kind(pnp, act);
-      float r[NARM + 3];
-      if (kind == MOVE) {
-        const float sft = smooth01(tau / t_move);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) r[c] = base_from[c] + sft * (base_to[c] - base_from[c]);
-#pragma unroll
-        for (int j = 0; j < NARM; ++j) r[3 + j] = qstart[ARM0 + j];
-      } else if (kind == PICK) {
-        const float Tc = sc.t_close;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) r[c] = qstart[c];
-#pragma unroll
-        for (int j = 0; j < NARM; ++j) {
-          float v;
-          const float s0 = qstart[ARM0 + j];
-          if (tau < Ta) v = s0 + smooth01(tau / Ta) * (qa[j] - s0);
-          else if (tau < Ta + Td) v = qa[j] + smooth01((tau - Ta) / Td) * (qb[j] - qa[j]);
-          else if (tau < Ta + Td + Tc) v = qb[j];
-          else if (tau < Ta + Td + Tc + Tl) v = qb[j] + smooth01((tau - Ta - Td - Tc) / Tl) * (qa[j] - qb[j]);
-          else v = qa[j];
-          r[3 + j] = v;
-        }
-        finger_cmd = tau < Ta + Td ? sc.finger_open : sc.finger_closed;
-      } else if (kind == PUSH) {
-        if (tau >= Ta + Td && !push_ready) {
-          float pw[4];
-          action_params(zp, 2, pw);
-          float sg, cg;
-          sincosf(pw[3], &sg, &cg);
-          M3f Rt;
-          Rt.r0 = v3(cg, sg, 0.0f);
-          Rt.r1 = v3(sg, -cg, 0.0f);
-          Rt.r2 = v3(0.0f, 0.0f, -1.0f);
-          float qq[NJ];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) qq[c] = qstart[c];
-#pragma unroll
-          for (int j = 0; j < NARM; ++j) qq[ARM0 + j] = qb[j];
-          qq[FL] = 0.0f;
-          qq[FR] = 0.0f;
-          ik_dls(sc, qq, ptarget, Rt);
-#pragma unroll
-          for (int j = 0; j < NARM; ++j) qa[j] = qq[ARM0 + j];
-          Tq = fmaxf(span(qb, qa, push_nominal), dt);
-          push_ready = true;
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) r[c] = qstart[c];
-#pragma unroll
-        for (int j = 0; j < NARM; ++j) {
-          // qa: the pre-push pose until the push phase, then the end-of-line anchor
-          float v;
-          const float s0 = qstart[ARM0 + j];
-          if (tau < Ta) v = s0 + smooth01(tau / Ta) * (qa[j] - s0);
-          else if (tau < Ta + Td) v = qa[j] + smooth01((tau - Ta) / Td) * (qb[j] - qa[j]);
-          else if (tau < Ta + Td + Tq) v = qb[j] + smooth01((tau - Ta - Td) / Tq) * (qa[j] - qb[j]);
-          else v = qa[j];
-          r[3 + j] = v;
-        }
-        finger_cmd = tau < Ta + Td + Tq ? sc.finger_closed : sc.finger_open;
-      } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) r[c] = qstart[c];
-#pragma unroll
-        for (int j = 0; j < NARM; ++j) {
-          const float s0 = qstart[ARM0 + j];
-          r[3 + j] = tau < Tp ? s0 + smooth01(tau / Tp) * (qa[j] - s0) : qa[j];
-        }
-        finger_cmd = tau < Tp ? sc.finger_closed : sc.finger_open;
-      }
-#pragma unroll
-      for (int j = 0; j < NARM + 3; ++j) L.at(R_QREF + j) = r[j];
-    }
-    L.at(R_QREF + FL) = finger_cmd;
 
+  // a rollout from its first step: row r's parameters, the robot at q0 and at
+  // rest, the object at its start pose, the controllers and the success record
+  // cleared, the first action started
+  auto init_plan = [&](long r) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) zp.v[a][i] = 4 * a + i < n_par ? Z[r * n_par + 4 * a + i] : 0.0f;
+    for (int j = 0; j < NJ; ++j) {
+      L.at(R_Q + j) = sc.q0[j];
+      L.at(R_QD + j) = 0.0f;
+      if (j <= FL) L.at(R_QREF + j) = sc.q0[j];
+    }
+    ob.p = v3(sc.obj_pos0[0], sc.obj_pos0[1], sc.obj_pos0[2] - om * g / (4.0f * kc));
+    {
+      float s, c;
+      sincosf(0.5f * sc.obj_yaw0, &s, &c);
+      ob.q = Q4f{c, 0.0f, 0.0f, s};
+    }
+    ob.v = v3(0.0f, 0.0f, 0.0f);
+    ob.w = v3(0.0f, 0.0f, 0.0f);
+    act = 0;
+    t_start = 0;
+    ok_bits = 0;
+    ptarget = v3(0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { base_from[c] = 0.0f; base_to[c] = 0.0f; }
+    t_move = 1.0f;
+    Ta = sc.t_approach; Td = sc.t_descend; Tl = sc.t_lift; Tp = sc.t_transfer; Tq = dt;
+    push_nominal = 0.0f;
+    push_ready = false;
+    finger_cmd = sc.finger_open;
+    touchL = false;
+    touchR = false;
+    unsuccessful = 0;
+#pragma unroll
+    for (int j = 0; j < NARM; ++j) { qa[j] = 0.0f; qb[j] = 0.0f; }
+    start_action(0, 0);
+  };
+
+  long row = row0;
+  bool live = live0;
+  bool diverged = false;
+  int steps = sc.horizon, calm = 0, t = 0, total = 0;
+  if (live) init_plan(row);
+  while (__ballot(live) != 0ull) {
+    bool ended = false;
+    if (live) {
+      // ---- action sequencing (control rate) ----
+      if (act < n_act) {
+        float q[NJ];
+        load_q(q);
+        const float tau = (float)(t - t_start) * dt;
+        const int kind = act_kind(pnp, act);
+        bool succ;
+        if (kind == MOVE) {
+          float pz[4];
+          action_params(zp, act, pz);
+          const float dx = q[0] - pz[0], dy = q[1] - pz[1];
+          succ = sqrtf(dx * dx + dy * dy) <= sc.base_tol && fabsf(wrap_pi(q[2] - pz[2])) <= sc.yaw_tol;
+        } else {
+          M3f Rw[PALM + 1];
+          V3f pw[PALM + 1];
+          chain_fk(sc, q, Rw, pw);
+          const V3f pe = ee_point(sc, Rw[PALM], pw[PALM]);
+          const V3f de = pe - ptarget;
+          const bool near = sqrtf(dot(de, de)) <= sc.ee_tol;
+          if (kind == PICK) {
+            const float tend = Ta + Td + sc.t_close + Tl;
+            const V3f op = mulT(Rw[PALM], ob.p - pw[PALM]);
+            const bool between = op.y < q[FL] && op.y > -q[FR];
+            succ = tau >= tend && touchL && touchR && between && near;
+          } else if (kind == PUSH) {
+            succ = tau >= Ta + Td + Tq + sc.t_release && near;
+          } else {
+            succ = tau >= Tp + sc.t_release && near;
+          }
+        }
+        const float tout = kind == MOVE   ? sc.timeout_move
+                           : kind == PICK ? sc.timeout_pick
+                           : kind == PUSH ? sc.timeout_push
+                                          : sc.timeout_place;
+        if (succ || tau >= tout) {
+          if (succ) ok_bits |= 1u << act;
+          ++act;
+          if (!succ && sc.fail_stop) {
+            // the plan can no longer become feasible: it ends before step t
+            ended = true;
+            steps = t;
+          } else if (act < n_act) {
+            start_action(act, t);
+          }
+        }
+      }
+      if (!ended) {
+        if (act < n_act) ++unsuccessful;
+        // ---- references ----
+        if (act < n_act) {
+          const float tau = (float)(t - t_start) * dt;
+          const int kind = act_kind(pnp, act);
+          float r[NARM + 3];
+          if (kind == MOVE) {
+            const float sft = smooth01(tau / t_move);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r[c] = base_from[c] + sft * (base_to[c] - base_from[c]);
+#pragma unroll
+            for (int j = 0; j < NARM; ++j) r[3 + j] = qstart[ARM0 + j];
+          } else if (kind == PICK) {
+            const float Tc = sc.t_close;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r[c] = qstart[c];
+#pragma unroll
+            for (int j = 0; j < NARM; ++j) {
+              float v;
+              const float s0 = qstart[ARM0 + j];
+              if (tau < Ta) v = s0 + smooth01(tau / Ta) * (qa[j] - s0);
+              else if (tau < Ta + Td) v = qa[j] + smooth01((tau - Ta) / Td) * (qb[j] - qa[j]);
+              else if (tau < Ta + Td + Tc) v = qb[j];
+              else if (tau < Ta + Td + Tc + Tl) v = qb[j] + smooth01((tau - Ta - Td - Tc) / Tl) * (qa[j] - qb[j]);
+              else v = qa[j];
+              r[3 + j] = v;
+            }
+            finger_cmd = tau < Ta + Td ? sc.finger_open : sc.finger_closed;
+          } else if (kind == PUSH) {
+            if (tau >= Ta + Td && !push_ready) {
+              float pw[4];
+              action_params(zp, 2, pw);
+              float sg, cg;
+              sincosf(pw[3], &sg, &cg);
+              M3f Rt;
+              Rt.r0 = v3(cg, sg, 0.0f);
+              Rt.r1 = v3(sg, -cg, 0.0f);
+              Rt.r2 = v3(0.0f, 0.0f, -1.0f);
+              float qq[NJ];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) qq[c] = qstart[c];
+#pragma unroll
+              for (int j = 0; j < NARM; ++j) qq[ARM0 + j] = qb[j];
+              qq[FL] = 0.0f;
+              qq[FR] = 0.0f;
+              ik_dls(sc, qq, ptarget, Rt);
+#pragma unroll
+              for (int j = 0; j < NARM; ++j) qa[j] = qq[ARM0 + j];
+              Tq = fmaxf(span(qb, qa, push_nominal), dt);
+              push_ready = true;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r[c] = qstart[c];
+#pragma unroll
+            for (int j = 0; j < NARM; ++j) {
+              // qa: the pre-push pose until the push phase, then the end-of-line anchor
+              float v;
+              const float s0 = qstart[ARM0 + j];
+              if (tau < Ta) v = s0 + smooth01(tau / Ta) * (qa[j] - s0);
+              else if (tau < Ta + Td) v = qa[j] + smooth01((tau - Ta) / Td) * (qb[j] - qa[j]);
+              else if (tau < Ta + Td + Tq) v = qb[j] + smooth01((tau - Ta - Td) / Tq) * (qa[j] - qb[j]);
+              else v = qa[j];
+              r[3 + j] = v;
+            }
+            finger_cmd = tau < Ta + Td + Tq ? sc.finger_closed : sc.finger_open;
+          } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r[c] = qstart[c];
+#pragma unroll
+            for (int j = 0; j < NARM; ++j) {
+              const float s0 = qstart[ARM0 + j];
+              r[3 + j] = tau < Tp ? s0 + smooth01(tau / Tp) * (qa[j] - s0) : qa[j];
+            }
+            finger_cmd = tau < Tp ? sc.finger_closed : sc.finger_open;
+          }
+#pragma unroll
+          for (int j = 0; j < NARM + 3; ++j) L.at(R_QREF + j) = r[j];
+        }
+        L.at(R_QREF + FL) = finger_cmd;
+      }
+    }
+    if (live && !ended) {
     for (int si = 0; si < sc.substeps; ++si) {
       const bool last = si == sc.substeps - 1;
       // ---- the object against the world (ground, static boxes) ----
@@ -698,58 +743,80 @@ __device__ __forceinline__ EnvOut robot_env(CDevState *st, const float *__restri
       integrate(ob, W, inv_om, oIb, gv, h);
     }
     if (TRACE && t < trace_steps && gi == 0) {
-      float *o = trace + ((long)env * trace_steps + t) * CEM_TRACE_ROBOT;
+      float *o = trace + (row * trace_steps + t) * CEM_TRACE_ROBOT;
       o[0] = ob.p.x; o[1] = ob.p.y; o[2] = ob.p.z;
       o[3] = ob.q.w; o[4] = ob.q.x; o[5] = ob.q.y; o[6] = ob.q.z;
       o[7] = ob.v.x; o[8] = ob.v.y; o[9] = ob.v.z;
       o[10] = ob.w.x; o[11] = ob.w.y; o[12] = ob.w.z;
       for (int j = 0; j < NJ; ++j) { o[13 + j] = L.at(R_Q + j); o[24 + j] = L.at(R_QD + j); }
     }
-    if (!isfinite(ob.p.x) || !isfinite(L.at(R_Q + 0))) {
-      diverged = true;
-      steps = t + 1;
-      break;
-    }
-    if (sc.settle_steps > 0) {
-      // early stop: the cost is final once the last action has ended; after
-      // settle_steps steps of the object at rest psi_g is read at this step
-      const bool at_rest = sqrtf(dot(ob.v, ob.v)) < sc.rest_speed;
-      calm = (act >= n_act && at_rest) ? calm + 1 : 0;
-      if (calm >= sc.settle_steps) {
+      if (!isfinite(ob.p.x) || !isfinite(L.at(R_Q + 0))) {
+        diverged = true;
         steps = t + 1;
-        break;
+        ended = true;
+      } else {
+        if (sc.settle_steps > 0) {
+          // early stop: the cost is final once the last action has ended; after
+          // settle_steps steps of the object at rest psi_g is read at this step
+          const bool at_rest = sqrtf(dot(ob.v, ob.v)) < sc.rest_speed;
+          calm = (act >= n_act && at_rest) ? calm + 1 : 0;
+          if (calm >= sc.settle_steps) {
+            steps = t + 1;
+            ended = true;
+          }
+        }
+        if (!ended && t + 1 >= sc.horizon) {
+          steps = sc.horizon;
+          ended = true;
+        }
       }
+      ++t;
+    }
+    if (live && ended) {
+      // goal psi_g: the object at rest, on the goal table's top face or with its centre inside the goal box
+      bool goal = false;
+      const bool rest = sqrtf(dot(ob.v, ob.v)) < sc.rest_speed;
+      if (sc.goal_static >= 0 && sc.goal_static < sc.n_static) {
+        const int b = sc.goal_static;
+        const float top = sc.st_center[b][2] + sc.st_half[b][2];
+        goal = fabsf(ob.p.x - sc.st_center[b][0]) <= sc.st_half[b][0] && fabsf(ob.p.y - sc.st_center[b][1]) <= sc.st_half[b][1] &&
+               ob.p.z >= top && ob.p.z <= top + 2.0f * sc.obj_half[2] && rest;
+      } else if (sc.goal_static < 0) {
+        goal = fabsf(ob.p.x - sc.goal_box_center[0]) <= sc.goal_box_half[0] &&
+               fabsf(ob.p.y - sc.goal_box_center[1]) <= sc.goal_box_half[1] &&
+               fabsf(ob.p.z - sc.goal_box_center[2]) <= sc.goal_box_half[2] && rest;
+      }
+      const float pose[7] = {ob.p.x, ob.p.y, ob.p.z, ob.q.w, ob.q.x, ob.q.y, ob.q.z};
+      bool fin = !diverged;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) fin = fin && isfinite(pose[i]);
+      for (int j = 0; j < NJ; ++j) fin = fin && isfinite(L.at(R_Q + j)) && fabsf(L.at(R_Q + j)) < 1e3f;
+      fin = fin && fabsf(ob.p.x) < 1e3f && fabsf(ob.p.y) < 1e3f && fabsf(ob.p.z) < 1e3f;
+      const bool all_ok = ok_bits == (1u << n_act) - 1u;
+      const int tier = !fin ? 3 : (all_ok ? (goal ? 0 : 1) : 2);
+      EnvOut out;
+      out.cost = fin ? sc.time_weight * dt * (float)unsuccessful : __int_as_float(0x7F800000);
+      out.tier = tier;
+      out.steps = steps;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) out.pose[i] = pose[i];
+      finish(out, row);
+      total += steps;
+    }
+    // the next rollout for every lane whose rollout ended
+    const bool need = live && ended;
+    claim(need, row, live);
+    if (need && live) {
+      init_plan(row);
+      diverged = false;
+      steps = sc.horizon;
+      calm = 0;
+      t = 0;
     }
   }
-  // goal psi_g: the object at rest, on the goal table's top face or with its centre inside the goal box
-  bool goal = false;
-  const bool rest = sqrtf(dot(ob.v, ob.v)) < sc.rest_speed;
-  if (sc.goal_static >= 0 && sc.goal_static < sc.n_static) {
-    const int b = sc.goal_static;
-    const float top = sc.st_center[b][2] + sc.st_half[b][2];
-    goal = fabsf(ob.p.x - sc.st_center[b][0]) <= sc.st_half[b][0] && fabsf(ob.p.y - sc.st_center[b][1]) <= sc.st_half[b][1] &&
-           ob.p.z >= top && ob.p.z <= top + 2.0f * sc.obj_half[2] && rest;
-  } else if (sc.goal_static < 0) {
-    goal = fabsf(ob.p.x - sc.goal_box_center[0]) <= sc.goal_box_half[0] &&
-           fabsf(ob.p.y - sc.goal_box_center[1]) <= sc.goal_box_half[1] &&
-           fabsf(ob.p.z - sc.goal_box_center[2]) <= sc.goal_box_half[2] && rest;
-  }
-  const float pose[7] = {ob.p.x, ob.p.y, ob.p.z, ob.q.w, ob.q.x, ob.q.y, ob.q.z};
-  bool fin = !diverged;
-#pragma unroll
-  for (int i = 0; i < 7; ++i) fin = fin && isfinite(pose[i]);
-  for (int j = 0; j < NJ; ++j) fin = fin && isfinite(L.at(R_Q + j)) && fabsf(L.at(R_Q + j)) < 1e3f;
-  fin = fin && fabsf(ob.p.x) < 1e3f && fabsf(ob.p.y) < 1e3f && fabsf(ob.p.z) < 1e3f;
-  const bool all_ok = ok_bits == (1u << n_act) - 1u;
-  const int tier = !fin ? 3 : (all_ok ? (goal ? 0 : 1) : 2);
-  EnvOut out;
-  out.cost = fin ? sc.time_weight * dt * (float)unsuccessful : __int_as_float(0x7F800000);
-  out.tier = tier;
-  out.steps = steps;
-#pragma unroll
-  for (int i = 0; i < 7; ++i) out.pose[i] = pose[i];
-  return out;
+  return total;
 }
+
 
 }  // namespace
 }  // namespace cem

@@ -7,9 +7,14 @@
 // population and horizon) runs as one persistent launch: each workgroup pulls
 // the next item from an atomic queue until the list is exhausted, so the items
 // of long-horizon instances, put first in the list, overlap with the many short
-// ones and no workgroup idles while work remains.  Both modes execute the same
-// per-environment code in the same kernel, so an instance's results do not
-// depend on whether it ran alone or in a batch.
+// ones and no workgroup idles while work remains.  In a batch, the plans of a
+// robot instance (without domain randomisation) come from a per-instance pool
+// instead of the item's fixed range: an item's wave takes the next 64
+// unstarted plans of its instance, and each lane whose rollout ends early
+// (settled, failed, diverged) takes the instance's next unstarted plan, so the
+// lanes stay busy while the instance has plans left.  Both modes execute the
+// same per-environment code in the same kernel, so an instance's results do
+// not depend on whether it ran alone or in a batch.
 #include "internal.hpp"
 #include "robot_env.hpp"
 #include "push_env.hpp"
@@ -20,8 +25,9 @@ namespace {
 template <bool TRACE, bool MULTI>
 __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, const InstDesc *__restrict__ insts,
                                                            const WorkItem *__restrict__ items, int n_items,
-                                                           int *__restrict__ queue, int check_iter,
-                                                           float *__restrict__ trace, int trace_steps) {
+                                                           int *__restrict__ queue, int *__restrict__ pool,
+                                                           int check_iter, float *__restrict__ trace,
+                                                           int trace_steps) {
   __shared__ float lds[R_ROWS * PP_LANES];
   const int lane = threadIdx.x;
   int it = blockIdx.x;
@@ -33,9 +39,10 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
     }
     if (it >= n_items) break;  // every wave of the grid reaches this once the queue is drained
     InstDesc d;
-    int env0, n;
+    int env0, n, inst = 0;
     if (insts) {
       const CWorkItem &w = ((CWorkItem *)items)[it];
+      inst = w.inst;
       const CInstDesc &di = ((CInstDesc *)insts)[w.inst];
       d.st = di.st;
       d.Z = di.Z;
@@ -66,7 +73,37 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
     const int lg = G == 16 ? 4 : G == 8 ? 3 : G == 4 ? 2 : G == 2 ? 1 : 0;
     const long vl = env0 + lane, env = vl >> lg, row = env / R;
     const int g = (int)(vl & (G - 1));
-    if (active && lane < n) {
+    const bool pooled = pool && robot && R == 1;  // wave-uniform
+    if (active && pooled) {
+      // the item's plans: the next 64 of the instance's pool; then, lane by
+      // lane as rollouts end, one more each (one atomic add per wave)
+      const int pop = d.pop;
+      int e0 = 0;
+      if (lane == 0) e0 = atomicAdd(&pool[inst], 64);
+      e0 = __builtin_amdgcn_readfirstlane(e0);
+      const long row0 = (long)e0 + lane;
+      auto claim = [&](bool need, long &r, bool &live) {
+        const unsigned long long want = __ballot(need);
+        if (want == 0ull) return;
+        const int leader = __builtin_ctzll(want);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&pool[inst], __popcll(want));
+        base = __shfl(base, leader);
+        if (need) {
+          r = (long)base + __popcll(want & ((1ull << lane) - 1ull));
+          live = r < pop;
+        }
+      };
+      auto finish = [&](const EnvOut &e, long r) {
+        if (d.cost) d.cost[r] = e.cost;
+        if (d.tier) d.tier[r] = (uint8_t)e.tier;
+        if (d.pose)
+#pragma unroll
+          for (int i = 0; i < 7; ++i) d.pose[r * 7 + i] = e.pose[i];
+      };
+      steps = robot_env<false, false>(st, d.Z, row0, row0 < pop, st->obj_mu, st->scene.obj_mass, lds, lane, 0, 1,
+                                      nullptr, 0, claim, finish);
+    } else if (active && lane < n) {
       if (!robot) {
         push_env<TRACE>(st->scene, st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
         steps = st->scene.horizon;
@@ -77,11 +114,17 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
           if (st->scene.dr_mu_hi > 0.0f) mu = st->dr_mu[r];
           if (st->scene.dr_mass_hi > 0.0f) m = st->dr_mass[r];
         }
-        o = robot_env<TRACE, MULTI>(st, d.Z, row, mu, m, lds, lane, g, G, trace, trace_steps);
-        steps = g == 0 ? o.steps : 0;
+        // this lane's one rollout (its group's, with G lanes per environment)
+        auto one = [](bool need, long &, bool &live) {
+          if (need) live = false;
+        };
+        auto keep = [&](const EnvOut &e, long) { o = e; };
+        const int s = robot_env<TRACE, MULTI>(st, d.Z, row, true, mu, m, lds, lane, g, G, trace, trace_steps, one,
+                                              keep);
+        steps = g == 0 ? s : 0;
       }
     }
-    if (active && robot) {
+    if (active && robot && !pooled) {
       // a row's scenarios sit in R adjacent lanes: the worst tier, and the
       // mean or the largest cost, by a fixed butterfly over the group
       const bool use_max = st->scene.dr_reduce != 0;
@@ -110,7 +153,7 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
   }
 }
 
-using RolloutKernel = void (*)(InstDesc, const InstDesc *, const WorkItem *, int, int *, int, float *, int);
+using RolloutKernel = void (*)(InstDesc, const InstDesc *, const WorkItem *, int, int *, int *, int, float *, int);
 
 // Scene constants used every substep, derived once per context: the static
 // boxes' rotations Rz(yaw) Ry(pitch) and each body's spatial inertia about its
@@ -134,8 +177,13 @@ __global__ void scene_consts_kernel(DevState *st) {
   }
 }
 
-__global__ void reset_counter_kernel(int *q) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
+// Clears the work queue's ticket and the instances' plan pools before a
+// batched launch (a kernel rather than a memset, so the clearing can sit in a
+// captured graph).
+__global__ void reset_counters_kernel(int *q, int *pool, int n_pool) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *q = 0;
+  if (pool && i < n_pool) pool[i] = 0;
 }
 
 // Training pairs of one instance: X row = its parameter row, Y row = (cost,
@@ -183,7 +231,7 @@ hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_step
   const bool multi = d.lanes > 1;
   const RolloutKernel k = trace ? (multi ? rollout_items_kernel<true, true> : rollout_items_kernel<true, false>)
                                 : (multi ? rollout_items_kernel<false, true> : rollout_items_kernel<false, false>);
-  hipLaunchKernelGGL(k, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items, nullptr, 0, trace,
+  hipLaunchKernelGGL(k, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items, nullptr, nullptr, 0, trace,
                      trace ? trace_steps : 0);
   return hipGetLastError();
 }
@@ -200,12 +248,12 @@ hipError_t launch_pack_dataset(const InstDesc &d, float cost_cap, float *X, floa
   return hipGetLastError();
 }
 
-hipError_t launch_rollout_batch(const InstDesc *insts, const WorkItem *items, int n_items, int *queue, int grid,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, queue);
+hipError_t launch_rollout_batch(const InstDesc *insts, int n_inst, const WorkItem *items, int n_items, int *queue,
+                                int *pool, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counters_kernel, dim3((n_inst + 255) / 256 + 1), dim3(256), 0, s, queue, pool, n_inst);
   InstDesc none{};
   const RolloutKernel k = rollout_items_kernel<false, false>;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, s, none, insts, items, n_items, queue, 1, nullptr, 0);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, s, none, insts, items, n_items, queue, pool, 1, nullptr, 0);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 
 from paper_2512_11571_amd import workloads
+from parity_util import certify, tier_mismatches
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -91,25 +92,20 @@ def test_early_stop_keeps_cost_and_goal(oracle, Context, name, lanes):
 
 
 def _certified(oracle, w, seed, Z):
-    """Oracle outcome, steps, and the rows whose cost and tier a one-ulp nudge
-    of every parameter either way does not change."""
-    c0, t0, _, _, s0 = oracle.rollout(w, seed, Z, with_steps=True)
-    up = np.nextafter(Z, np.float32(np.inf)).astype(np.float32)
-    dn = np.nextafter(Z, np.float32(-np.inf)).astype(np.float32)
-    c1, t1, _, _ = oracle.rollout(w, seed, up)
-    c2, t2, _, _ = oracle.rollout(w, seed, dn)
-    ok = (t0 == t1) & (t0 == t2) & (np.abs(c1 - c0) < 1e-9) & (np.abs(c2 - c0) < 1e-9)
-    return ok, c0, t0, s0
+    """Oracle outcome, the certified rows (cost and tier), the rows whose tier is
+    certified, and the steps each rollout simulated."""
+    r = certify(oracle, w, seed, Z)
+    return r["ok"], r["cost"], r["tier"], r["okt"], r["steps"]
 
 
 def test_early_stop_parity_with_the_oracle(oracle, Context):
     w = _early(workloads.load("movepush"))
     seed = 1
     Z = _rows(oracle, w, seed, 128)
-    ok, cr, tr, sr = _certified(oracle, w, seed, Z)
+    ok, cr, tr, dec, sr = _certified(oracle, w, seed, Z)
     assert ok.sum() >= 48
     cg, tg, sg = _gpu(Context, w, Z, seed)
-    assert np.mean(tg[ok] == tr[ok]) >= 0.95
+    assert not tier_mismatches("movepush early stop", dec, tg, tr, cg, cr)
     same = ok & (tg == tr) & (tr < 3)
     assert np.max(np.abs(cg[same] - cr[same])) <= 2 * w["scene"]["dt"] + 1e-6
     assert abs(sg - int(sr.sum())) <= 0.05 * sr.sum()
@@ -145,3 +141,99 @@ def test_early_stop_with_scenarios_and_in_a_batch(oracle, Context):
             s = c.plan_solve(inst["iters"])
             assert c.env_steps() == n
         assert r["best_cost"] == s["best_cost"] and np.array_equal(r["mu"], s["mu"])
+
+
+# ---- stop on a failed action (scene fail_stop = 1) ----
+
+def _failstop(w):
+    wf = copy.deepcopy(w)
+    wf["scene"]["fail_stop"] = 1
+    return wf
+
+
+def _gpu_full(Context, w, Z, seed, lanes=1):
+    n = Z.shape[0]
+    with Context(w, seed=seed, pop=max(n, 64), n_elite=1, lanes=lanes) as c:
+        Zd = torch.from_numpy(np.ascontiguousarray(Z)).to("cuda:0")
+        cost = torch.empty(n, dtype=torch.float32, device="cuda:0")
+        tier = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        pose = torch.empty((n, 7), dtype=torch.float32, device="cuda:0")
+        c.rollout_batch(Zd, cost, tier, pose)
+        torch.cuda.synchronize()
+        return cost.cpu().numpy().astype(np.float64), tier.cpu().numpy(), pose.cpu().numpy(), c.env_steps()
+
+
+@pytest.mark.parametrize("name,lanes", [("pickplace", 1), ("pickplace", 16), ("movepush", 1), ("movepush", 8)])
+def test_fail_stop_against_the_gpus_full_run(oracle, Context, name, lanes):
+    # plans whose actions all succeed are untouched, to the bit; the others
+    # report tier 2 and stop early, at a cost no larger than the full run's
+    w = workloads.load(name)
+    n = 256
+    Z = _rows(oracle, w, 5, n)
+    cf, tf, pf, sf = _gpu_full(Context, w, Z, 5, lanes)
+    cs, ts, ps, ss = _gpu_full(Context, _failstop(w), Z, 5, lanes)
+    keep = tf <= 1
+    assert np.array_equal(cs[keep], cf[keep]) and np.array_equal(ts[keep], tf[keep])
+    assert np.array_equal(ps[keep], pf[keep])
+    stopped = ~keep & (ts == 2)
+    assert np.all(ts[~keep] >= 2)
+    assert np.all(cs[stopped] <= cf[stopped] + 1e-6)
+    assert ss < sf and stopped.sum() > 0
+    print("%s, %d lanes: %d of %d plans stopped early, %.1f %% of the full run's steps"
+          % (name, lanes, stopped.sum(), n, 100.0 * ss / sf))
+
+
+def test_fail_stop_parity_with_the_oracle(oracle, Context):
+    w = _failstop(workloads.load("pickplace"))
+    seed = 6
+    Z = _rows(oracle, w, seed, 128)
+    ok, cr, tr, dec, sr = _certified(oracle, w, seed, Z)
+    assert ok.sum() >= 48
+    cg, tg, sg = _gpu(Context, w, Z, seed)
+    assert not tier_mismatches("pickplace fail stop", dec, tg, tr, cg, cr)
+    same = ok & (tg == tr) & (tr < 3)
+    assert np.max(np.abs(cg[same] - cr[same])) <= 2 * w["scene"]["dt"] + 1e-6
+    assert abs(sg - int(sr.sum())) <= 0.05 * sr.sum()
+
+
+def test_fail_stop_leaves_the_ce_run_unchanged(Context):
+    # the update reads tier 0 and tier 1 samples only, which the stop does not touch
+    w = copy.deepcopy(workloads.load("pickplace"))
+    w["cem"].update(pop=256, n_elite=16)
+    for seed in (0, 1):
+        with Context(w, seed=seed) as c:
+            a = c.plan_solve(3)
+            na = c.env_steps()
+        with Context(_failstop(w), seed=seed) as c:
+            b = c.plan_solve(3)
+            nb = c.env_steps()
+        assert np.array_equal(a["mu"], b["mu"]) and np.array_equal(a["cov"], b["cov"])
+        assert np.array_equal(a["stats"][:, [1, 2, 5, 6]], b["stats"][:, [1, 2, 5, 6]])
+        if a["best_tier"] <= 1:
+            assert a["best_cost"] == b["best_cost"] and np.array_equal(a["best_z"], b["best_z"])
+        assert nb < na
+
+
+def test_pooled_batch_with_stops_equals_single_runs(oracle, Context):
+    # in a batch, lanes whose rollout stopped take the instance's next plan; the
+    # outcomes and step counts are those of the instances run alone
+    from paper_2512_11571_amd import binding
+    insts = []
+    for k, name in enumerate(("pickplace", "movepush", "pickplace")):
+        w = _failstop(_early(workloads.load(name)))
+        w["scene"]["horizon"] = 900 + 300 * k
+        w["cem"].update(pop=200 + 64 * k, n_elite=8)
+        insts.append({"workload": w, "seed": k, "instance": k, "iters": 2})
+    with binding.Batch(insts) as bt:
+        res = bt.solve(2)
+        counted = [bt.instance(k).env_steps() for k in range(3)]
+        last = [bt.instance(k).outcomes() for k in range(3)]
+    for inst, r, n, (cb, tb, pb) in zip(insts, res, counted, last):
+        with Context(inst["workload"], seed=inst["seed"], instance=inst["instance"]) as c:
+            s = c.plan_solve(inst["iters"])
+            assert c.env_steps() == n
+            cs, ts, ps = c.outcomes()
+        assert r["best_cost"] == s["best_cost"] and np.array_equal(r["mu"], s["mu"])
+        assert np.array_equal(cb, cs) and np.array_equal(tb, ts) and np.array_equal(pb, ps)
+        full = inst["iters"] * inst["workload"]["cem"]["pop"] * inst["workload"]["scene"]["horizon"]
+        assert n < full

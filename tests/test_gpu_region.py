@@ -85,3 +85,30 @@ def test_batch_rejects_a_schedule(B):
     w = _push_region()
     with pytest.raises(B.CemError):
         B.Batch([{"workload": w, "seed": 0, "instance": 0, "iters": 2}])
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_diverged_rows_against_the_oracle(oracle, B, lanes):
+    # the paper setting's iteration-0 region rows (3000): every row the GPU
+    # reports as diverged (tier 3) is one the oracle also cannot complete
+    # (tier 2: an action fails, or tier 3: it diverges too), so no plan that
+    # could enter the update is lost to FP32 arithmetic alone
+    w = copy.deepcopy(workloads.load("pickplace_paper"))
+    w["cem"].pop("pop_schedule")
+    seed, pop = 0, 3000
+    with B.Context(w, seed=seed, pop=pop, n_elite=50, lanes=lanes) as c:
+        Z = torch.empty((pop, 16), dtype=torch.float32, device="cuda:0")
+        cost = torch.empty(pop, dtype=torch.float32, device="cuda:0")
+        tier = torch.empty(pop, dtype=torch.uint8, device="cuda:0")
+        c.cem_sample(0, Z)
+        c.rollout_batch(Z, cost, tier)
+        torch.cuda.synchronize()
+        Zh, th = Z.cpu().numpy(), tier.cpu().numpy()
+    bad = np.nonzero(th == 3)[0]
+    print("pickplace_paper iteration 0, %d lanes: %d of %d rows diverged on the GPU: %s"
+          % (lanes, bad.size, pop, bad.tolist()))
+    if bad.size:
+        cr, tr, _, _ = oracle.rollout(w, seed, Zh[bad])
+        print("  oracle tiers of those rows:", tr.tolist())
+        assert np.all(tr >= 2), list(zip(bad.tolist(), tr.tolist()))
+    assert bad.size <= 0.01 * pop

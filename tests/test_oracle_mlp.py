@@ -152,3 +152,24 @@ def test_adam_steps_two_and_three_match_the_library(oracle):
         p.grad = torch.tensor(g, dtype=torch.float64)
         opt.step()
         assert np.allclose(P, p.detach().numpy(), rtol=1e-13, atol=1e-16), t
+
+
+def test_bf16_backward_pins(oracle, P0):
+    # the backward with BF16 operands: its loss is the BF16 forward's mean squared
+    # error, its last bias gradient the unrounded dL/dy summed over rows (closed
+    # forms from the forward alone), and every gradient within the BF16 bound of
+    # the FP64 backward (itself pinned by central differences)
+    rng = np.random.default_rng(12)
+    P = P0 + rng.normal(size=P0.size) * 0.01
+    x = rng.normal(size=(64, 16))
+    t = rng.normal(size=(64, 8))
+    lb, gb = oracle.mlp_loss_grad(P, x, t, bf16=True)
+    l64, g64 = oracle.mlp_loss_grad(P, x, t)
+    yb = oracle.mlp_forward(P, x, bf16=True)
+    assert abs(lb - np.mean((yb - t) ** 2)) <= 1e-15 * lb
+    b4 = oracle.mlp_slices()[3][2]
+    assert np.allclose(gb[b4], 2.0 * np.sum(yb - t, axis=0) / t.size, rtol=1e-12, atol=1e-16)
+    for ws, shape, bs in oracle.mlp_slices():
+        for sl in (ws, bs):
+            assert np.max(np.abs(gb[sl] - g64[sl])) <= 2e-2 * np.max(np.abs(g64[sl]))
+    assert not np.array_equal(gb, g64)
