@@ -7,10 +7,10 @@
 // full simulation decides every cost that enters the refit.
 //
 // All matrix products run on the MFMA units: BF16 operands, FP32
-// accumulation (v_mfma_f32_16x16x16_bf16), 64x64 output tiles per workgroup
-// of four waves, each wave a 32x32 quadrant of 2x2 MFMA tiles, the K
-// dimension staged through LDS 16 at a time; bias, GELU and its derivative are
-// fused into the epilogue.  Master weights and Adam moments are FP32; the
+// accumulation (gfx950's v_mfma_f32_16x16x32_bf16), 128x128 output tiles per
+// workgroup of four waves, each wave a 64x64 quadrant of 4x4 MFMA tiles, the
+// K dimension staged through LDS 32 at a time; bias, GELU and its derivative
+// are fused into the epilogue.  Master weights and Adam moments are FP32; the
 // BF16 copy of the weights is refreshed by the Adam kernel.
 #include <hip/hip_runtime.h>
 
@@ -39,7 +39,7 @@ __host__ __device__ constexpr long w_off(int l) {
 __host__ __device__ constexpr long b_off(int l) { return w_off(l) + (long)DIMS[l] * DIMS[l + 1]; }
 constexpr long N_PARAMS = w_off(NL);
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16 bits, round to nearest even (inf/nan kept).
@@ -103,73 +103,80 @@ __device__ __forceinline__ void stage8(const uint16_t *__restrict__ p, long stri
   }
 }
 
-// 64x64 tile of C per workgroup (256 threads = 4 waves, 32x32 each), 32 of the
-// contraction per step (two MFMA 16-steps in ascending k, as a plain loop over
-// 16-steps would take them).  Each operand is staged along its contiguous axis
-// with 16-byte loads and kept in LDS with the contraction contiguous ([m][k]
-// and [n][k]), so a lane reads each 4-element MFMA fragment as one 8-byte word.
+// 128x128 tile of C per workgroup (256 threads = 4 waves, 64x64 each), 32 of
+// the contraction per step: one v_mfma_f32_16x16x32_bf16 per 16x16 tile and
+// step, in which lane l holds A[l % 16][8 (l / 16) + e] and
+// B[8 (l / 16) + e][l % 16] (e = 0..7) and gets D[4 (l / 16) + t][l % 16]
+// (t = 0..3).  Each operand is staged along its contiguous axis with 16-byte
+// loads and kept in LDS with the contraction contiguous ([m][k] and [n][k]),
+// so a lane reads each 8-element fragment as one 16-byte word.
+constexpr int TILE = 128;
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   constexpr int KS = 32, LDK = KS + 8;  // 80-byte LDS rows: 16-byte aligned, banks staggered
-  __shared__ __align__(16) uint16_t As[64][LDK];
-  __shared__ __align__(16) uint16_t Bs[64][LDK];
+  __shared__ __align__(16) uint16_t As[TILE][LDK];
+  __shared__ __align__(16) uint16_t Bs[TILE][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int kbeg = blockIdx.z * g.kc, kend = min(g.K, kbeg + g.kc);
   const bool a_kfast = g.a_k == 1, b_kfast = g.b_k == 1 && g.b_n != 1;
-  f32x4 acc[2][2];
+  f32x4 acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = kbeg; k0 < kend; k0 += KS) {
-    // A (64 x 32): 64 rows x 4 chunks of k, or 32 k x 8 chunks of m
-    if (a_kfast) {
-      const int am = tid >> 2, ak = (tid & 3) * 8, m = m0 + am, k = k0 + ak;
-      const uint16_t *p = g.A + (long)m * g.a_m + k;
-      stage8(p, 1, m < g.M && k + 7 < kend, [&](int e) { return m < g.M && k + e < kend; },
-             [&](int e) -> uint16_t & { return As[am][ak + e]; });
-    } else {
-      const int ak = tid >> 3, am = (tid & 7) * 8, m = m0 + am, k = k0 + ak;
-      const uint16_t *p = g.A + (long)m * g.a_m + (long)k * g.a_k;
-      stage8(p, g.a_m, k < kend && m + 7 < g.M, [&](int e) { return k < kend && m + e < g.M; },
-             [&](int e) -> uint16_t & { return As[am + e][ak]; });
+    // A (128 x 32): two chunks of 8 per thread, 128 rows x 4 chunks of k or 32 k x 16 chunks of m
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = tid + 256 * h;
+      if (a_kfast) {
+        const int am = c >> 2, ak = (c & 3) * 8, m = m0 + am, k = k0 + ak;
+        const uint16_t *p = g.A + (long)m * g.a_m + k;
+        stage8(p, 1, m < g.M && k + 7 < kend, [&](int e) { return m < g.M && k + e < kend; },
+               [&](int e) -> uint16_t & { return As[am][ak + e]; });
+      } else {
+        const int ak = c >> 4, am = (c & 15) * 8, m = m0 + am, k = k0 + ak;
+        const uint16_t *p = g.A + (long)m * g.a_m + (long)k * g.a_k;
+        stage8(p, g.a_m, k < kend && m + 7 < g.M, [&](int e) { return k < kend && m + e < g.M; },
+               [&](int e) -> uint16_t & { return As[am + e][ak]; });
+      }
     }
-    // B (32 x 64): 64 columns x 4 chunks of k, or 32 k x 8 chunks of n
-    if (b_kfast) {
-      const int bn = tid >> 2, bk = (tid & 3) * 8, n = n0 + bn, k = k0 + bk;
-      const uint16_t *p = g.B + (long)k + (long)n * g.b_n;
-      stage8(p, 1, n < g.N && k + 7 < kend, [&](int e) { return n < g.N && k + e < kend; },
-             [&](int e) -> uint16_t & { return Bs[bn][bk + e]; });
-    } else {
-      const int bk = tid >> 3, bn = (tid & 7) * 8, n = n0 + bn, k = k0 + bk;
-      const uint16_t *p = g.B + (long)k * g.b_k + (long)n * g.b_n;
-      stage8(p, g.b_n, k < kend && n + 7 < g.N, [&](int e) { return k < kend && n + e < g.N; },
-             [&](int e) -> uint16_t & { return Bs[bn + e][bk]; });
+    // B (32 x 128): the same for 128 columns
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = tid + 256 * h;
+      if (b_kfast) {
+        const int bn = c >> 2, bk = (c & 3) * 8, n = n0 + bn, k = k0 + bk;
+        const uint16_t *p = g.B + (long)k + (long)n * g.b_n;
+        stage8(p, 1, n < g.N && k + 7 < kend, [&](int e) { return n < g.N && k + e < kend; },
+               [&](int e) -> uint16_t & { return Bs[bn][bk + e]; });
+      } else {
+        const int bk = c >> 4, bn = (c & 15) * 8, n = n0 + bn, k = k0 + bk;
+        const uint16_t *p = g.B + (long)k * g.b_k + (long)n * g.b_n;
+        stage8(p, g.b_n, k < kend && n + 7 < g.N, [&](int e) { return k < kend && n + e < g.N; },
+               [&](int e) -> uint16_t & { return Bs[bn + e][bk]; });
+      }
     }
     __syncthreads();
     const int r = lane & 15, q = lane >> 4;
+    bf16x8 af[4], bfr[4];
 #pragma unroll
-    for (int kk = 0; kk < KS; kk += 16) {
-      bf16x4 af[2], bfr[2];
+    for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + r][8 * q]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x4 *>(&As[wm + 16 * i + r][kk + 4 * q]);
+    for (int j = 0; j < 4; ++j) bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * j + r][8 * q]);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x4 *>(&Bs[wn + 16 * j + r][kk + 4 * q]);
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
-    }
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
   // lane holds D[4q + t][r] of each 16x16 tile
   const int r = lane & 15, q = lane >> 4;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int m = m0 + wm + 16 * i + 4 * q + t, n = n0 + wn + 16 * j + r;
@@ -196,7 +203,7 @@ hipError_t gemm(GemmArgs g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   g.kc = g.K;
   g.c_split = 0;
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.N + 63) / 64, (g.M + 63) / 64, 1), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE, 1), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
@@ -213,20 +220,21 @@ __global__ void reduce_splits_kernel(const float *__restrict__ part, int splits,
 
 constexpr int MAX_SPLITS = 32;
 // C (M x N, ldc = N) = A B with a long contraction K: the K range is cut into
-// up to MAX_SPLITS chunks of whole 16-steps so that small outputs (weight
+// up to MAX_SPLITS chunks of whole 32-steps so that small outputs (weight
 // gradients) still spread over the chip; partial sums go to `part`
 // (MAX_SPLITS x M x N floats) and are reduced in a fixed order.
 hipError_t gemm_split(GemmArgs g, float *part, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  const int tiles = ((g.N + 63) / 64) * ((g.M + 63) / 64);
+  const int tiles = ((g.N + TILE - 1) / TILE) * ((g.M + TILE - 1) / TILE);
   int splits = std::max(1, std::min(MAX_SPLITS, 512 / tiles));
-  g.kc = ((g.K + splits - 1) / splits + 15) / 16 * 16;
+  g.kc = ((g.K + splits - 1) / splits + 31) / 32 * 32;
   splits = std::max(1, (g.K + g.kc - 1) / g.kc);
   float *out = g.C;
   g.C = part;
   g.c_split = (long)g.M * g.ldc;
   g.epi = EPI_STORE;
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.N + 63) / 64, (g.M + 63) / 64, splits), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE, splits), dim3(256), 0,
+                     s, g);
   const long n = (long)g.M * g.ldc;
   hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, splits, n, n, out);
   return hipGetLastError();

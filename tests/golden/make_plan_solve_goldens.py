@@ -7,7 +7,12 @@ runs that the GPU's plan_solve medians are compared with.
 - batch_push: the push instances of the batched workload (jittered goals,
   their own horizon, population and N_e), each for its iteration budget, as
   the batch runs them (seed of the batch recipe, instance id as the Philox
-  instance).
+  instance);
+- box_small: the box-obstacle scene in the paper's setting (iteration-0
+  region, n_env schedule) at pop 256 -> 64 by iteration 2, N_e 16, 3
+  iterations, seeds 0-31;
+- dr_small: pick-and-place with 4 domain-randomisation scenarios (block
+  friction and mass), pop 64, N_e 8, 2 iterations, seeds 0-31.
 
 Only the oracle and the seeded workload descriptions are used.  Results are
 saved after every run, so an interrupted run keeps what it finished and a new
@@ -41,6 +46,13 @@ def problems():
     mp = workloads.load("movepush")
     mp["cem"].update(pop=1024, n_elite=64)
     out["movepush"] = (mp, [(str(s), s, 0, 5) for s in SEEDS])
+    box = workloads.load("pickplace_box")
+    box["cem"].update(pop=256, n_elite=16, pop_schedule={"final": 64, "iters": 2})
+    out["box_small"] = (box, [(str(s), s, 0, 3) for s in SEEDS])
+    dr = workloads.load("pickplace")
+    dr["scene"]["domain_randomization"] = {"scenarios": 4, "reduce": "mean", "mu": [0.3, 0.7], "mass": [0.2, 0.4]}
+    dr["cem"].update(pop=64, n_elite=8)
+    out["dr_small"] = (dr, [(str(s), s, 0, 2) for s in SEEDS])
     for inst in workloads.batch_instances():
         if inst["workload"]["scene"]["kind"] == "push":
             out.setdefault("batch_push", ([], []))

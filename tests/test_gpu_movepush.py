@@ -5,9 +5,8 @@ Tolerance: FP32 robot joint angles / block pose within 1e-3 (rad, m) over the
 first 100 control steps on rows the oracle certifies as non-chaotic; over the
 full horizon, tier and cost agree on certified rows (cost to within two
 control steps).  Full size: the configured population (8192) and horizon
-(3000) in one launch, sampled rows checked one by one.  Statistical: median
-best cost of plan_solve over seeds 0-31 within 1e-2 relative at a reduced
-population.
+(3000) in one launch, sampled rows checked one by one.  (The median of
+plan_solve over seeds at pop 1024 is in test_gpu_ce_medians.py.)
 Every parity test also runs with 2, 4 or 8 lanes per environment (the
 lanes split the contact tests and sum the forces), against the same oracle
 runs and the same tolerances.
@@ -156,23 +155,3 @@ def test_full_size_population_sampled_rows(oracle, mp, Context, lanes):
     assert np.all(th < 3)
     # every tier the population produces is a valid class; some plans succeed
     assert (th == 0).sum() > 0
-
-
-@pytest.mark.parametrize("lanes", [1, 8])
-def test_plan_solve_median_matches_oracle(oracle, mp, Context, lanes):
-    w = dict(mp, cem=dict(mp["cem"], pop=96, n_elite=12))
-    iters = 2
-    g, r = [], []
-    # 32 seeds rather than the workload's 10: CE over contact dynamics is
-    # chaotic, so FP32 and FP64 runs that share iteration 0 exactly can pick
-    # different elites later, and a 10-seed median of quantised costs moves
-    # by a whole order statistic when one seed does
-    for seed in range(32):
-        with Context(w, seed=seed, lanes=lanes) as c:
-            res = c.plan_solve(iters)
-        g.append(res["best_cost"])
-        key = ("plan_solve", seed)
-        if key not in _MEMO:
-            _MEMO[key] = oracle.plan_solve(w, seed, iters=iters)["best_cost"]
-        r.append(_MEMO[key])
-    assert abs(np.median(g) - np.median(r)) <= 1e-2 * np.median(r)

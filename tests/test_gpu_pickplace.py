@@ -5,9 +5,9 @@ Tolerance: FP32 robot joint angles / object pose within 1e-3 (rad, m) over
 the first 100 control steps on rows the oracle certifies as non-chaotic; over
 the full horizon, tier and cost agree on certified rows (cost to within two
 control steps, since action completion is decided on a threshold per step).
-Statistical: median best cost of plan_solve over seeds 0-31 within 1e-2
-relative at a reduced population.  Full size: the configured population and
-horizon, sampled rows checked one by one.
+Full size: the configured population and horizon, sampled rows checked one
+by one.  (The median of plan_solve over seeds at the configured size is in
+test_gpu_ce_medians.py.)
 Every parity test also runs with 2, 4, 8 or 16 lanes per environment (the
 lanes split the contact tests and sum the forces), against the same oracle
 runs and the same tolerances.
@@ -132,23 +132,3 @@ def test_full_size_population_sampled_rows(oracle, pp, Context, lanes):
     sel = ok & (th[idx] == tr) & (tr < 3)
     assert np.max(np.abs(ch[idx][sel] - cr[sel])) <= 2 * pp["scene"]["dt"] + 1e-6
     assert np.all(th < 3)                                  # nothing diverges on the GPU
-
-
-@pytest.mark.parametrize("lanes", [1, 16])
-def test_plan_solve_median_matches_oracle(oracle, pp, Context, lanes):
-    w = dict(pp, cem=dict(pp["cem"], pop=128, n_elite=16))
-    iters = 3
-    g, r = [], []
-    # 32 seeds rather than the workload's 10: CE over contact dynamics is
-    # chaotic, so FP32 and FP64 runs that share iteration 0 exactly can pick
-    # different elites later, and a 10-seed median of quantised costs moves
-    # by a whole order statistic when one seed does
-    for seed in range(32):
-        with Context(w, seed=seed, lanes=lanes) as c:
-            res = c.plan_solve(iters)
-        g.append(res["best_cost"])
-        key = ("plan_solve", seed)
-        if key not in _MEMO:
-            _MEMO[key] = oracle.plan_solve(w, seed, iters=iters)["best_cost"]
-        r.append(_MEMO[key])
-    assert abs(np.median(g) - np.median(r)) <= 1e-2 * np.median(r)
