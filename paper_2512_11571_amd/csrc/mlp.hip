@@ -42,23 +42,32 @@ constexpr long N_PARAMS = w_off(NL);
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16 bits, round to nearest even (inf/nan kept).
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16 bits, round to nearest even (v_cvt_pk_bf16_f32; inf kept, NaN
+// stays NaN), one value or two packed (a in the low half).
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ float gelu(float x) {
-  const float c = 0.7978845608028654f;  // sqrt(2/pi)
-  return 0.5f * x * (1.0f + tanhf(c * (x + 0.044715f * x * x * x)));
+// GELU, tanh form: 0.5 x (1 + tanh u), u = sqrt(2/pi) (x + 0.044715 x^3),
+// evaluated as x s with s = 1 / (1 + e^(-2u)) (the same function: 1 + tanh u =
+// 2 / (1 + e^(-2u))), e^(-2u) = 2^(-2 u log2 e) and the reciprocal from the
+// hardware's exp2 and rcp (about 1 ulp each: far below the BF16 rounding of
+// the activations); its derivative s + 2 x s (1 - s) sqrt(2/pi) (1 + 3 0.044715 x^2).
+constexpr float GELU_C = 0.7978845608028654f, GELU_A = 0.044715f;
+constexpr float GELU_K = (float)(-2.0 * 0.7978845608028654 * 1.4426950408889634);
+__device__ __forceinline__ float gelu_s(float x) {
+  const float u = x * fmaf(GELU_A * x, x, 1.0f);
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(GELU_K * u));
 }
+__device__ __forceinline__ float gelu(float x) { return x * gelu_s(x); }
 __device__ __forceinline__ float gelu_grad(float x) {
-  const float c = 0.7978845608028654f;
-  const float t = tanhf(c * (x + 0.044715f * x * x * x));
-  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * x * x);
+  const float s = gelu_s(x);
+  return s + 2.0f * x * s * (1.0f - s) * GELU_C * fmaf(3.0f * GELU_A * x, x, 1.0f);
 }
 
 enum Epi : int {
@@ -165,38 +174,67 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
     for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + r][8 * q]);
 #pragma unroll
     for (int j = 0; j < 4; ++j) bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * j + r][8 * q]);
+    // the transposed tile, C^T = B^T A^T: B's fragment as the first operand
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
-  // lane holds D[4q + t][r] of each 16x16 tile
+  // lane holds C[m][n + t] (t = 0..3), m = wm + 16 i + l % 16, n = wn + 16 j +
+  // 4 (l / 16): four adjacent outputs of a row, stored as one 16-byte (fp32)
+  // or 8-byte (bf16) word where the row stride and the buffers allow
   const int r = lane & 15, q = lane >> 4;
+  const bool vec = (g.ldc & 3) == 0 && ((uintptr_t)g.C & 15u) == 0 && ((uintptr_t)g.H & 7u) == 0 &&
+                   ((uintptr_t)g.Zin & 15u) == 0 && ((uintptr_t)g.bias & 15u) == 0;
+  const float *out_bias = g.bias;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+      const int m = m0 + wm + 16 * i + r, nb = n0 + wn + 16 * j + 4 * q;
+      if (m >= g.M || nb >= g.N) continue;
+      const long o = (long)m * g.ldc + nb;
+      float v[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
+      if (vec && nb + 3 < g.N) {
+        if (g.epi == EPI_STORE) {
+          *reinterpret_cast<float4 *>(g.C + o + blockIdx.z * g.c_split) = float4{v[0], v[1], v[2], v[3]};
+        } else if (g.epi == EPI_BIAS) {
+          const float4 b = *reinterpret_cast<const float4 *>(out_bias + nb);
+          *reinterpret_cast<float4 *>(g.C + o) = float4{v[0] + b.x, v[1] + b.y, v[2] + b.z, v[3] + b.w};
+        } else if (g.epi == EPI_BIAS_GELU) {
+          const float4 b = *reinterpret_cast<const float4 *>(out_bias + nb);
+          v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
+          if (g.C) *reinterpret_cast<float4 *>(g.C + o) = float4{v[0], v[1], v[2], v[3]};
+          *reinterpret_cast<uint2 *>(g.H + o) = uint2{f2bf2(gelu(v[0]), gelu(v[1])), f2bf2(gelu(v[2]), gelu(v[3]))};
+        } else {
+          const float4 z = *reinterpret_cast<const float4 *>(g.Zin + o);
+          v[0] *= gelu_grad(z.x); v[1] *= gelu_grad(z.y); v[2] *= gelu_grad(z.z); v[3] *= gelu_grad(z.w);
+          if (g.C) *reinterpret_cast<float4 *>(g.C + o) = float4{v[0], v[1], v[2], v[3]};
+          *reinterpret_cast<uint2 *>(g.H + o) = uint2{f2bf2(v[0], v[1]), f2bf2(v[2], v[3])};
+        }
+        continue;
+      }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int m = m0 + wm + 16 * i + 4 * q + t, n = n0 + wn + 16 * j + r;
-        if (m >= g.M || n >= g.N) continue;
-        const long o = (long)m * g.ldc + n;
-        float v = acc[i][j][t];
+        const int n = nb + t;
+        if (n >= g.N) continue;
+        float x = v[t];
         if (g.epi == EPI_STORE) {
-          g.C[o + blockIdx.z * g.c_split] = v;
+          g.C[o + t + blockIdx.z * g.c_split] = x;
         } else if (g.epi == EPI_BIAS) {
-          g.C[o] = v + g.bias[n];
+          g.C[o + t] = x + out_bias[n];
         } else if (g.epi == EPI_BIAS_GELU) {
-          v += g.bias[n];
-          if (g.C) g.C[o] = v;
-          g.H[o] = f2bf(gelu(v));
+          x += out_bias[n];
+          if (g.C) g.C[o + t] = x;
+          g.H[o + t] = f2bf(gelu(x));
         } else {
-          v *= gelu_grad(g.Zin[o]);
-          if (g.C) g.C[o] = v;
-          g.H[o] = f2bf(v);
+          x *= gelu_grad(g.Zin[o + t]);
+          if (g.C) g.C[o + t] = x;
+          g.H[o + t] = f2bf(x);
         }
       }
+    }
 }
 
 hipError_t gemm(GemmArgs g, hipStream_t s) {
@@ -205,6 +243,122 @@ hipError_t gemm(GemmArgs g, hipStream_t s) {
   g.c_split = 0;
   hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE, 1), dim3(256), 0, s, g);
   return hipGetLastError();
+}
+
+// The whole network's inference over 128 rows per workgroup (256 threads = 4
+// waves): the inputs standardised, three hidden layers and the output layer,
+// the outputs de-standardised.  The activations stay in LDS (one bf16
+// 128 x 256 buffer, 66 KB: two workgroups per CU), so HBM sees only x in and
+// y out.  A layer computes its transpose, out^T (n x 128) = W H^T, with
+// v_mfma_f32_16x16x32_bf16: the first operand is W (lane l holds
+// W[n0 + l % 16][k0 + 8 (l / 16) + e], one 16-byte load from global memory,
+// the same weights for every workgroup, so the caches serve them; the next
+// step's are loaded ahead) and the second the activations
+// (H[m0 + l % 16][k0 + 8 (l / 16) + e], one 16-byte read from LDS); lane l
+// then holds out[m0 + l % 16][n0 + 4 (l / 16) + t] (t = 0..3), four adjacent
+// outputs of one row, stored as one 8-byte word once every wave has read the
+// layer's input.  Wave w takes the outputs 64 w .. 64 w + 63 of a hidden
+// layer for all 128 rows (each weight fragment serves eight row tiles: the
+// weights are read from the caches once per 128 rows), and rows
+// 32 w .. 32 w + 31 of the output layer.  Per output the contraction runs in
+// ascending 32-steps (the 16 inputs padded with zeros to one step), and the
+// prologue and epilogues are the expressions of norm_in_kernel,
+// gemm_bf16_kernel's bias / GELU epilogues and denorm_out_kernel.
+constexpr int FT = 128, FLD = HID + 8, MT = FT / 16;  // rows per workgroup; LDS row stride in bf16 (528 B); row tiles
+static_assert(w_off(1) % 8 == 0 && w_off(2) % 8 == 0 && w_off(3) % 8 == 0, "16-byte aligned weight blocks");
+__device__ __forceinline__ bf16x8 ld16(const uint16_t *p) { return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p)); }
+__global__ void __launch_bounds__(256, 2) mlp_fused_kernel(const float *__restrict__ X, int n,
+                                                        const float *__restrict__ norm,
+                                                        const uint16_t *__restrict__ Pb,
+                                                        const float *__restrict__ P, float *__restrict__ Y) {
+  __shared__ __align__(16) uint16_t Hs[FT][FLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const long row0 = (long)blockIdx.x * FT;
+  const bf16x8 zero8 = __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u});
+  // standardised inputs in columns 0..15, zeros in 16..31; rows past n are zero
+  for (int i = tid; i < FT * 32; i += 256) {
+    const int m = i >> 5, c = i & 31;
+    uint16_t v = 0;
+    if (c < IN && row0 + m < n) v = f2bf((X[(row0 + m) * IN + c] - norm[c]) / norm[IN + c]);
+    Hs[m][c] = v;
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int l = 0; l < NL - 1; ++l) {
+    const int ni = l == 0 ? IN : HID, steps = (ni + 31) / 32;
+    const uint16_t *__restrict__ W = Pb + w_off(l);
+    const float *__restrict__ bias = P + b_off(l);
+    const uint16_t(*Hin)[FLD] = Hs;
+    uint16_t(*Hout)[FLD] = Hs;
+    f32x4 acc[4][MT];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < MT; ++i) acc[j][i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 wf[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wf[j] = 8 * q < ni ? ld16(W + (long)(64 * wave + 16 * j + r) * ni + 8 * q) : zero8;
+#pragma unroll 1
+    for (int ks = 0; ks < steps; ++ks) {
+      const int k0 = 32 * ks;
+      bf16x8 wn[4];  // the next step's weights, loaded ahead
+      const bool more = ks + 1 < steps;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        wn[j] = more ? ld16(W + (long)(64 * wave + 16 * j + r) * ni + k0 + 32 + 8 * q) : zero8;
+      bf16x8 hf[MT];
+#pragma unroll
+      for (int i = 0; i < MT; ++i) hf[i] = *reinterpret_cast<const bf16x8 *>(&Hin[16 * i + r][k0 + 8 * q]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < MT; ++i) acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], hf[i], acc[j][i], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wf[j] = wn[j];
+    }
+    __syncthreads();  // every wave has read the layer's input
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int nb = 64 * wave + 16 * j + 4 * q;
+      const float b0 = bias[nb], b1 = bias[nb + 1], b2 = bias[nb + 2], b3 = bias[nb + 3];
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        const uint32_t h01 = f2bf2(gelu(acc[j][i][0] + b0), gelu(acc[j][i][1] + b1));
+        const uint32_t h23 = f2bf2(gelu(acc[j][i][2] + b2), gelu(acc[j][i][3] + b3));
+        *reinterpret_cast<uint2 *>(&Hout[16 * i + r][nb]) = uint2{h01, h23};
+      }
+    }
+    __syncthreads();
+  }
+  // output layer: 8 outputs, weight rows 8..15 of the 16-row operand are zero;
+  // wave w takes the row tiles 2 w and 2 w + 1
+  const uint16_t *__restrict__ W3 = Pb + w_off(NL - 1);
+  const float *__restrict__ b3 = P + b_off(NL - 1);
+#pragma unroll
+  for (int h = 0; h < MT / 4; ++h) {
+    const int mt = (MT / 4) * wave + h;
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < HID / 32; ++ks) {
+      const int k0 = 32 * ks;
+      const bf16x8 wf = r < OUT ? ld16(W3 + (long)r * HID + k0 + 8 * q) : zero8;
+      const bf16x8 hf = *reinterpret_cast<const bf16x8 *>(&Hs[16 * mt + r][k0 + 8 * q]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf, hf, acc, 0, 0, 0);
+    }
+    const long m = row0 + 16 * mt + r;
+    if (q < 2 && m < n) {
+      const float *mean = norm + 2 * IN, *sd = norm + 2 * IN + OUT;
+      float y[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = 4 * q + t;
+        const float yn = acc[t] + b3[c];
+        y[t] = yn * sd[c] + mean[c];
+      }
+      *reinterpret_cast<float4 *>(Y + m * OUT + 4 * q) = float4{y[0], y[1], y[2], y[3]};
+    }
+  }
 }
 
 // out[i] = sum over z of part[z * stride + i], z ascending (a fixed order, so
@@ -219,6 +373,7 @@ __global__ void reduce_splits_kernel(const float *__restrict__ part, int splits,
 }
 
 constexpr int MAX_SPLITS = 32;
+constexpr int COLSUM_CHUNKS = 32;  // row chunks of the bias-gradient column sums (partials in the split buffer)
 // C (M x N, ldc = N) = A B with a long contraction K: the K range is cut into
 // up to MAX_SPLITS chunks of whole 32-steps so that small outputs (weight
 // gradients) still spread over the chip; partial sums go to `part`
@@ -295,25 +450,25 @@ __global__ void __launch_bounds__(1024) sum_kernel(const float *__restrict__ v, 
   if (threadIdx.x == 0) *out = (float)(part[0] / (double)scale);
 }
 
-// Column sums (bias gradients): out[c] = sum_r M[r * cols + c].  A 32 x 32
-// block covers 32 columns: thread (x, y) sums rows y, y + 32, ... of column x
-// (neighbouring threads read neighbouring columns), then the 32 partial sums of
-// each column are added in row order, so the result is deterministic.
-__global__ void __launch_bounds__(1024) colsum_kernel(const float *__restrict__ M, int rows, int cols,
-                                                      float *__restrict__ out) {
-  __shared__ float part[32][33];
-  const int x = threadIdx.x & 31, y = threadIdx.x >> 5;
-  const int c = blockIdx.x * 32 + x;
+// Column sums (bias gradients), first of two deterministic stages:
+// part[z * cols + c] = sum of M[r * cols + c] over the rows r of chunk z
+// (chunks of ceil(rows / gridDim.y) rows).  A 256-thread block covers 64
+// columns of one chunk: thread (x, y) sums rows y, y + 4, ... of the chunk in
+// column x (neighbouring threads read neighbouring columns), then the four
+// partial sums are added in order.  reduce_splits_kernel adds the chunks in
+// ascending z.
+__global__ void __launch_bounds__(256) colsum_part_kernel(const float *__restrict__ M, int rows, int cols,
+                                                          float *__restrict__ part) {
+  __shared__ float p4[4][64];
+  const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + x;
+  const int chunk = (rows + gridDim.y - 1) / gridDim.y, r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
   float acc = 0.0f;
   if (c < cols)
-    for (int r = y; r < rows; r += 32) acc += M[(long)r * cols + c];
-  part[y][x] = acc;
+    for (int r = r0 + y; r < r1; r += 4) acc += M[(long)r * cols + c];
+  p4[y][x] = acc;
   __syncthreads();
-  if (y == 0 && c < cols) {
-    float t = 0.0f;
-    for (int k = 0; k < 32; ++k) t += part[k][x];
-    out[c] = t;
-  }
+  if (y == 0 && c < cols) part[(long)blockIdx.y * cols + c] = ((p4[0][x] + p4[1][x]) + p4[2][x]) + p4[3][x];
 }
 
 // Adam (Kingma & Ba) with bias correction; refreshes the BF16 weight copy.
@@ -650,7 +805,10 @@ hipError_t loss_grad_n(cem_mlp *m, const float *X, const float *T, int n, hipStr
     e = gemm_split(gargs(dZ, 1, nz, Hin[l], ni, 1, nz, ni, n, EPI_STORE, nullptr, nullptr, m->G + w_off(l), nullptr, ni),
                    m->part, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_kernel, dim3((nz + 31) / 32), dim3(1024), 0, s, dZf, n, nz, m->G + b_off(l));
+    // bias gradient: column sums of dZ in COLSUM_CHUNKS row chunks, then the chunks in order
+    hipLaunchKernelGGL(colsum_part_kernel, dim3((nz + 63) / 64, COLSUM_CHUNKS), dim3(256), 0, s, dZf, n, nz, m->part);
+    hipLaunchKernelGGL(reduce_splits_kernel, dim3(blocks(nz, 256)), dim3(256), 0, s, m->part, COLSUM_CHUNKS, (long)nz,
+                       (long)nz, m->G + b_off(l));
     if (l == 0) break;
     // dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1})
     uint16_t *out = m->dZb[(NL - 1 - l) & 1];
@@ -808,9 +966,7 @@ int cem_mlp_forward(cem_mlp *m, const float *X_dev, int32_t n, float *Y_dev, voi
   if (n == 0) return CEM_OK;
   if (!X_dev || !Y_dev) return mfail(m, CEM_E_ARG, "null buffer");
   hipStream_t s = (hipStream_t)stream;
-  MHIPCHK(m, forward_n(m, X_dev, n, false, s));
-  hipLaunchKernelGGL(denorm_out_kernel, dim3(blocks((long)n * OUT, 256)), dim3(256), 0, s, m->Yn, n,
-                     m->norm + 2 * IN, m->norm + 2 * IN + OUT, Y_dev);
+  hipLaunchKernelGGL(mlp_fused_kernel, dim3(blocks(n, FT)), dim3(256), 0, s, X_dev, n, m->norm, m->Pb, m->P, Y_dev);
   MHIPCHK(m, hipGetLastError());
   return CEM_OK;
 }
@@ -941,10 +1097,8 @@ int cem_mlp_train(cem_mlp *m, const float *X_dev, const float *Y_dev, int64_t n,
 static int screen_into(cem_ctx *c, cem_mlp *m, int32_t iter, int32_t n_sim, float *Zsim, float *pred, hipStream_t s) {
   hipError_t e = launch_sample(c->seed, c->inst, iter, c->st, c->pop, c->D, c->Z, s);
   if (e != hipSuccess) return mfail(m, CEM_E_HIP, "sample");
-  e = forward_n(m, c->Z, c->pop, false, s);
-  if (e != hipSuccess) return mfail(m, CEM_E_HIP, "forward");
-  hipLaunchKernelGGL(denorm_out_kernel, dim3(blocks((long)c->pop * OUT, 256)), dim3(256), 0, s, m->Yn, c->pop,
-                     m->norm + 2 * IN, m->norm + 2 * IN + OUT, m->Ypred);
+  hipLaunchKernelGGL(mlp_fused_kernel, dim3(blocks(c->pop, FT)), dim3(256), 0, s, c->Z, c->pop, m->norm, m->Pb, m->P,
+                     m->Ypred);
   hipLaunchKernelGGL(screen_keys_kernel, dim3(blocks(c->pop, 256)), dim3(256), 0, s, m->Ypred, c->pop, c->st, m->keys);
   hipLaunchKernelGGL(topk_kernel, dim3(1), dim3(1024), 0, s, m->keys, c->pop, n_sim, m->sel);
   hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks(n_sim, 256)), dim3(256), 0, s, c->Z, c->D, m->Ypred, m->sel,

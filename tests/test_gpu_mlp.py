@@ -1,6 +1,8 @@
 """The BF16-MFMA surrogate network against the oracle: bit-exact He
-initialisation, forward against the oracle's BF16-emulated forward, loss and
-gradients against the oracle's FP64 backward, Adam against the oracle's Adam,
+initialisation, forward against the oracle's BF16-emulated forward (up to
+16,384 rows), the whole-network inference kernel against the layer-by-layer
+GEMMs bit for bit, loss and gradients against the oracle's FP64 backward, Adam
+against the oracle's Adam,
 training progress, the screening top-k against a host sort of the same keys,
 and the recorded dataset against the simulator's own outputs."""
 import numpy as np
@@ -31,10 +33,10 @@ def test_init_bit_exact(oracle, B):
     assert np.array_equal(P.astype(np.float64), Pr)
 
 
-@pytest.mark.parametrize("n", [1, 77, 1000])
+@pytest.mark.parametrize("n", [1, 77, 1000, 16384])
 def test_forward_matches_bf16_oracle(oracle, B, n):
     rng = np.random.default_rng(n)
-    with B.Mlp(seed=3, max_rows=4096) as m:
+    with B.Mlp(seed=3, max_rows=16384) as m:
         P = m.get_params()
         P = P + rng.normal(size=P.size).astype(np.float32) * 0.01   # nonzero biases
         m.set_params(P)
@@ -50,6 +52,29 @@ def test_forward_matches_bf16_oracle(oracle, B, n):
     # hidden activations are the only differences
     assert np.max(np.abs(y - yr)) <= 2e-2 * scale
     assert np.max(np.abs(y - y64)) <= 5e-2 * scale
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 8192])
+def test_fused_forward_equals_the_layer_by_layer_forward(B, n):
+    # the whole-network kernel (64 rows per workgroup, activations in LDS)
+    # against the layer-by-layer tiled GEMMs of the allocation-free entry, bit
+    # for bit: the same BF16 operands, the same MFMA per 32-step of the
+    # contraction in the same order, the same epilogue expressions; n spans
+    # one row, ragged and whole workgroups and the fixed array's limit
+    rng = np.random.default_rng(100 + n)
+    with B.Mlp(seed=5, max_rows=8192) as m:
+        m.set_params(m.get_params() + rng.normal(size=m.n_params).astype(np.float32) * 0.01)
+        m.set_norm(np.concatenate([rng.normal(size=16), rng.uniform(0.5, 2.0, 16),
+                                   rng.normal(size=8), rng.uniform(0.5, 2.0, 8)]).astype(np.float32))
+        x = _dev(rng.normal(size=(n, 16)) * 2.0)
+        y_f = torch.full((n, 8), float("nan"), dtype=torch.float32, device="cuda:0")
+        y_l = torch.full((n, 8), float("nan"), dtype=torch.float32, device="cuda:0")
+        m.forward(x, y_f)
+        m.forward_static(x, y_l)
+        torch.cuda.synchronize()
+        a, b = y_f.cpu().numpy(), y_l.cpu().numpy()
+    assert np.all(np.isfinite(a))
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (n, np.max(np.abs(a - b)))
 
 
 @pytest.mark.parametrize("n", [200, 4096])
