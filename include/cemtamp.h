@@ -224,6 +224,18 @@ int cem_valu_fma_rate(double *flops_per_s, void *stream);
  * 3 cem_init_region; else 0),
  * for bindings to check their layouts. */
 int cem_sizeof(int which);
+/* The rollout kernel has an instance compiled for one robot: the mobile
+ * manipulator of the robot scenes (joint types and axes, joint origins, body
+ * masses, centres of mass and half extents; robot_model.hpp), with the
+ * articulated-body passes unrolled and the products with the robot's
+ * structural zeros left out (Problem 1's dynamics, Featherstone's algorithm;
+ * the same arithmetic otherwise, so its results differ from the generic
+ * instance's only by rounding).  A launch takes it when its scene's robot
+ * equals the model field for field, the generic instance otherwise.
+ * enable = 0 makes every launch prepared after the call (a context's
+ * rollout, a batch's captured iteration) take the generic instance; nonzero
+ * restores the default.  Process-wide; no error. */
+void cem_set_robot_specialization(int32_t enable);
 const char *cem_strerror(int code);
 const char *cem_last_error(const cem_ctx *c);
 

@@ -98,7 +98,7 @@ EXPORTS = ["cem_init", "cem_free", "cem_dim", "cem_sizeof", "cem_strerror", "cem
            "cem_batch_record", "cem_mlp_init", "cem_mlp_free", "cem_mlp_n_params", "cem_mlp_last_error",
            "cem_mlp_get_params", "cem_mlp_set_params", "cem_mlp_get_norm", "cem_mlp_set_norm", "cem_mlp_fit_norm",
            "cem_mlp_forward", "cem_mlp_forward_static", "cem_mlp_loss_grad", "cem_mlp_train_step", "cem_mlp_train", "cem_screen",
-           "plan_solve_screened"]
+           "plan_solve_screened", "cem_set_robot_specialization"]
 
 _lib = None
 
@@ -133,6 +133,8 @@ def lib():
         L.cem_pop_at.argtypes = [vp, _i]
         L.cem_get_scenarios.argtypes = [vp, vp, vp]
         L.cem_valu_fma_rate.argtypes = [P(ctypes.c_double), vp]
+        L.cem_set_robot_specialization.argtypes = [ctypes.c_int32]
+        L.cem_set_robot_specialization.restype = None
         L.cem_reset.argtypes = [vp]
         L.cem_sizeof.argtypes = [ctypes.c_int]
         L.cem_batch_init.argtypes = [vp, vp, _i, P(vp)]
@@ -179,6 +181,12 @@ def valu_fma_rate(stream=None):
     if rc != CEM_OK:
         raise CemError(rc, lib().cem_strerror(rc).decode())
     return r.value
+
+
+def set_robot_specialization(enable):
+    """cem_set_robot_specialization: False makes launches prepared afterwards take the
+    generic rollout instance instead of the one compiled for the robot model."""
+    lib().cem_set_robot_specialization(1 if enable else 0)
 
 
 class CemError(RuntimeError):

@@ -150,6 +150,7 @@ InstDesc desc_of(cem_ctx *c, const float *Z, int pop, float *cost, uint8_t *tier
   d.iters = 1 << 30;
   d.scen = scenarios(c->scene);
   d.lanes = c->lanes;
+  d.spec = robot_spec_for(c->scene) ? 1 : 0;
   return d;
 }
 
@@ -533,6 +534,14 @@ int bfail(cem_batch *b, int code, const std::string &msg) {
   return code;
 }
 
+// The batch takes the rollout instance specialised to the robot model when
+// every robot instance's robot is the model.
+bool batch_spec(const cem_batch *b) {
+  for (const cem_ctx *c : b->ctx)
+    if (c->scene.kind != CEM_SCENE_PUSH && !robot_spec_for(c->scene)) return false;
+  return true;
+}
+
 #define BHIPCHK(b, expr)                                                                        \
   do {                                                                                          \
     hipError_t e_ = (expr);                                                                     \
@@ -585,7 +594,8 @@ int build_graph(cem_batch *b) {
   BHIPCHK(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
   const int n = (int)b->ctx.size();
   hipError_t e1 = launch_sample_batch(b->insts, n, b->max_pop, b->own);
-  hipError_t e2 = launch_rollout_batch(b->insts, n, b->items, b->n_items, b->queue, b->pool, b->grid, b->own);
+  hipError_t e2 = launch_rollout_batch(b->insts, n, b->items, b->n_items, b->queue, b->pool, b->grid, batch_spec(b),
+                                       b->own);
   hipError_t e3 = launch_select_refit_batch(b->insts, n, MAX_STATS_ITERS, b->own);
   hipError_t e4 = hipStreamEndCapture(b->own, &g);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
@@ -707,7 +717,8 @@ int cem_batch_autotune(cem_batch *b, int32_t *config_out) {
     for (int mi = 0; mi < 3; ++mi) {
       const int grid = mults[mi] * b->n_cu;
       BHIPCHK(b, hipEventRecord(e0, b->own));
-      BHIPCHK(b, launch_rollout_batch(b->insts, n, b->items, b->n_items, b->queue, b->pool, grid, b->own));
+      BHIPCHK(b, launch_rollout_batch(b->insts, n, b->items, b->n_items, b->queue, b->pool, grid, batch_spec(b),
+                                      b->own));
       BHIPCHK(b, hipEventRecord(e1, b->own));
       BHIPCHK(b, hipEventSynchronize(e1));
       float ms = 0.0f;

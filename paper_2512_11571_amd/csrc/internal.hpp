@@ -62,6 +62,7 @@ struct InstDesc {
   int32_t kind, pop, D, iters;  // iters: iteration cap in batched runs
   int32_t scen;                 // scenarios per row (1: no domain randomisation); pop * scen environments
   int32_t lanes;                // lanes per environment (1, 2, 4); pop * scen * lanes lanes
+  int32_t spec;                 // 1: the robot is the compiled-in model (robot_spec_for), use its instance
 };
 // Up to 64 environments [env0, env0 + n) of instance `inst`.
 struct WorkItem {
@@ -95,7 +96,10 @@ hipError_t launch_select_refit(DevState *st, const float *Z, const float *cost, 
 hipError_t launch_select_refit_batch(const InstDesc *insts, int n_inst, int stats_cap, hipStream_t s);
 hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s);
 hipError_t launch_rollout_batch(const InstDesc *insts, int n_inst, const WorkItem *items, int n_items, int *queue,
-                                int *pool, int grid, hipStream_t s);
+                                int *pool, int grid, bool spec, hipStream_t s);
+// Whether the scene's robot is the compiled-in model (every joint and body
+// field equal) and the specialised rollout instance is switched on.
+bool robot_spec_for(const cem_scene &sc);
 hipError_t launch_scene_consts(DevState *st, hipStream_t s);
 hipError_t launch_pack_dataset(const InstDesc &d, float cost_cap, float *X, float *Y, hipStream_t s);
 

@@ -1140,6 +1140,7 @@ int plan_solve_screened(cem_ctx *c, cem_mlp *m, int32_t iters, int32_t n_sim, ce
     d.st = c->st; d.Z = m->Zs; d.cost = c->cost; d.tier = c->tier; d.pose = nullptr; d.stats = c->stats;
     d.kind = c->scene.kind; d.pop = n_sim; d.D = c->D; d.iters = 1 << 30; d.scen = scenarios(c->scene);
     d.lanes = c->lanes;
+    d.spec = robot_spec_for(c->scene) ? 1 : 0;
     hipError_t e2 = launch_rollout_single(d, nullptr, 0, m->own);
     hipLaunchKernelGGL(screen_error_kernel, dim3(1), dim3(256), 0, m->own, m->Ps, c->cost, n_sim, c->st, m->err,
                        MAX_STATS_ITERS);

@@ -309,84 +309,6 @@ __device__ __forceinline__ V3f ee_point(CScene &sc, const M3f &Rp, V3f pp) {
   return pp + mul(Rp, v3(sc.ee_offset[0], sc.ee_offset[1], sc.ee_offset[2]));
 }
 
-// Damped least squares on the arm joints 3..8 toward (pt, Rt):
-// dq = J^T (J J^T + lambda^2 I)^-1 e, e = (pt - p_ee, 1/2 sum_k r_k x rt_k).
-__device__ __forceinline__ void ik_dls(CScene &sc, float *q, V3f pt, const M3f &Rt) {
-  const float lam2 = sc.ik_lambda * sc.ik_lambda;
-  for (int it = 0; it < sc.ik_iters; ++it) {
-    M3f Rw[PALM + 1];
-    V3f pw[PALM + 1];
-    chain_fk(sc, q, Rw, pw);
-    const V3f pe = ee_point(sc, Rw[PALM], pw[PALM]);
-    const V3f ep = pt - pe;
-    const M3f &Re = Rw[PALM];
-    const V3f eo = cross(v3(Re.r0.x, Re.r1.x, Re.r2.x), v3(Rt.r0.x, Rt.r1.x, Rt.r2.x)) +
-                   cross(v3(Re.r0.y, Re.r1.y, Re.r2.y), v3(Rt.r0.y, Rt.r1.y, Rt.r2.y)) +
-                   cross(v3(Re.r0.z, Re.r1.z, Re.r2.z), v3(Rt.r0.z, Rt.r1.z, Rt.r2.z));
-    const float e[6] = {ep.x, ep.y, ep.z, 0.5f * eo.x, 0.5f * eo.y, 0.5f * eo.z};
-    float J[6][NARM];
-#pragma unroll
-    for (int c = 0; c < NARM; ++c) {
-      const int j = ARM0 + c;
-      const int ax = sc.j_axis[j], k = ax % 3;
-      const float sg = ax < 3 ? 1.0f : -1.0f;
-      const V3f z = mul(Rw[j], v3(k == 0 ? sg : 0.0f, k == 1 ? sg : 0.0f, k == 2 ? sg : 0.0f));
-      const V3f jv = cross(z, pe - pw[j]);
-      J[0][c] = jv.x; J[1][c] = jv.y; J[2][c] = jv.z;
-      J[3][c] = z.x; J[4][c] = z.y; J[5][c] = z.z;
-    }
-    float A[6][6];
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        float acc = r == c ? lam2 : 0.0f;
-#pragma unroll
-        for (int k = 0; k < NARM; ++k) acc += J[r][k] * J[c][k];
-        A[r][c] = acc;
-      }
-    // Cholesky solve
-    float L[6][6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      float d = A[j][j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-      const float ljj = sqrtf(d), inv = 1.0f / ljj;
-      L[j][j] = ljj;
-#pragma unroll
-      for (int i = j + 1; i < 6; ++i) {
-        float t = A[i][j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-        L[i][j] = t * inv;
-      }
-    }
-    float y[6], x[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      float t = e[i];
-#pragma unroll
-      for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
-      y[i] = t / L[i][i];
-    }
-#pragma unroll
-    for (int i = 5; i >= 0; --i) {
-      float t = y[i];
-#pragma unroll
-      for (int k = i + 1; k < 6; ++k) t -= L[k][i] * x[k];
-      x[i] = t / L[i][i];
-    }
-#pragma unroll
-    for (int c = 0; c < NARM; ++c) {
-      float d = 0.0f;
-#pragma unroll
-      for (int r = 0; r < 6; ++r) d += J[r][c] * x[r];
-      q[ARM0 + c] += d;
-    }
-  }
-}
-
 __device__ __forceinline__ float smooth01(float x) {
   const float c = fminf(1.0f, fmaxf(0.0f, x));
   return c * c * (3.0f - 2.0f * c);

@@ -39,7 +39,7 @@
 // for z in and (cost, tier, pose) out; the scene is read through wave-uniform
 // scalar loads.
 #pragma once
-#include "robot_dyn.hpp"
+#include "robot_spec.hpp"
 
 namespace cem {
 namespace {
@@ -92,6 +92,48 @@ __device__ __forceinline__ void c_put(const Lds &L, int j, SV c) {
     L.at(r) = c.b.x; L.at(r + 1) = c.b.y; L.at(r + 2) = c.b.z;
   }
 }
+// The LDS row of component i (0..5 over [w; v]) of c_J, for the components
+// c_mask<J>() keeps (the rows c_put writes); the masked-out ones are zero.
+template <int J> constexpr int c_row(int i) {
+  return J == 2 ? R_C + (i - 3)
+                : (J <= PALM ? R_C + 3 + 6 * (J - 3) + i : R_C + 3 + 6 * NARM + 3 * (J - FL) + (i - 3));
+}
+template <int J> __device__ __forceinline__ void c_put_t(const Lds &L, SV c) {
+  constexpr unsigned M = c_mask<J>();
+  const float x[6] = {c.a.x, c.a.y, c.a.z, c.b.x, c.b.y, c.b.z};
+  sfor<0, 6>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr ((M >> i) & 1u) L.at(c_row<J>(i)) = x[i];
+  });
+}
+// The specialised passes leave the rows of c_J's structural zeros unwritten;
+// they hold the cosine and sine of revolute joint J (2..PALM) from the first
+// pass for the second and third: an arm joint's in its own body's axis rows,
+// the base yaw's in body 2's zero row and finger FL's.
+template <int J> constexpr int cs_row(int which) {
+  return J == 2 ? (which == 0 ? c_row<2>(3 + rmx::kax(2)) : c_row<FL>(3 + rmx::kax(FL)))
+                : c_row<J>(which == 0 ? rmx::kax(J) : 3 + rmx::kax(J));
+}
+// those rows are outside the masks of the components c_put_t writes
+static_assert(!((c_mask<2>() >> (3 + rmx::kax(2))) & 1u) && !((c_mask<FL>() >> (3 + rmx::kax(FL))) & 1u),
+              "spare rows for the base yaw's cosine and sine");
+template <int J> __device__ __forceinline__ void cs_put_t(const Lds &L, const JT &X) {
+  static_assert(J >= 2 && J <= PALM && rmx::rev(J), "revolute joints 2..PALM");
+  static_assert(J == 2 || (!((c_mask<J>() >> rmx::kax(J)) & 1u) && !((c_mask<J>() >> (3 + rmx::kax(J))) & 1u)),
+                "spare rows of an arm body");
+  L.at(cs_row<J>(0)) = X.c;
+  L.at(cs_row<J>(1)) = X.s;
+}
+template <int J> __device__ __forceinline__ SV c_get_t(const Lds &L) {
+  constexpr unsigned M = c_mask<J>();
+  float x[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  sfor<0, 6>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr ((M >> i) & 1u) x[i] = L.at(c_row<J>(i));
+  });
+  return sv(v3(x[0], x[1], x[2]), v3(x[3], x[4], x[5]));
+}
+
 // Sum over the G (1, 2, 4, 8 or 16) adjacent lanes that share an environment,
 // by a butterfly: quad permutations for lane distances 1 and 2, swizzles (xor
 // within 32 lanes) for 4 and 8.  Each level adds the same two operands on both
@@ -150,7 +192,7 @@ struct EnvOut {
 // the forces are then summed over the group, whose lanes therefore start and
 // end their rollouts together.  With G = 1 the sums run in the original
 // order; the MULTI = false instance compiles G = 1 in.
-template <bool TRACE, bool MULTI, class Claim, class Finish>
+template <bool TRACE, bool MULTI, bool SPEC, class Claim, class Finish>
 __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict__ Z, long row0, bool live0,
                                           float mu_obj, float om, float *lds_mem, int lane, int gi_in, int G_in,
                                           float *__restrict__ trace, int trace_steps, Claim claim, Finish finish) {
@@ -239,10 +281,10 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
       float qs[NARM];
 #pragma unroll
       for (int j = 0; j < NARM; ++j) qs[j] = q[ARM0 + j];
-      ik_dls(sc, q, ps + v3(0.0f, 0.0f, dz), Rt);
+      ik_dls<SPEC>(sc, q, ps + v3(0.0f, 0.0f, dz), Rt);
 #pragma unroll
       for (int j = 0; j < NARM; ++j) qa[j] = q[ARM0 + j];
-      ik_dls(sc, q, ps, Rt);
+      ik_dls<SPEC>(sc, q, ps, Rt);
 #pragma unroll
       for (int j = 0; j < NARM; ++j) qb[j] = q[ARM0 + j];
       // the end-of-line anchor (IK from (base at action start, qb) toward pe)
@@ -280,11 +322,11 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
       float qs[NARM];
 #pragma unroll
       for (int j = 0; j < NARM; ++j) qs[j] = q[ARM0 + j];
-      ik_dls(sc, q, pfin, Rt);
+      ik_dls<SPEC>(sc, q, pfin, Rt);
 #pragma unroll
       for (int j = 0; j < NARM; ++j) qa[j] = q[ARM0 + j];
       if (kind == PICK) {
-        ik_dls(sc, q, pgoal, Rt);
+        ik_dls<SPEC>(sc, q, pgoal, Rt);
 #pragma unroll
         for (int j = 0; j < NARM; ++j) qb[j] = q[ARM0 + j];
         Ta = span(qs, qa, sc.t_approach);
@@ -361,7 +403,8 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
         } else {
           M3f Rw[PALM + 1];
           V3f pw[PALM + 1];
-          chain_fk(sc, q, Rw, pw);
+          if constexpr (SPEC) chain_fk_t(q, Rw, pw);
+          else chain_fk(sc, q, Rw, pw);
           const V3f pe = ee_point(sc, Rw[PALM], pw[PALM]);
           const V3f de = pe - ptarget;
           const bool near = sqrtf(dot(de, de)) <= sc.ee_tol;
@@ -438,7 +481,7 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
               for (int j = 0; j < NARM; ++j) qq[ARM0 + j] = qb[j];
               qq[FL] = 0.0f;
               qq[FR] = 0.0f;
-              ik_dls(sc, qq, ptarget, Rt);
+              ik_dls<SPEC>(sc, qq, ptarget, Rt);
 #pragma unroll
               for (int j = 0; j < NARM; ++j) qa[j] = qq[ARM0 + j];
               Tq = fmaxf(span(qb, qa, push_nominal), dt);
@@ -514,46 +557,80 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
       // ---- ABA pass 1 (root to leaves): poses, velocities, bias terms ----
       // The chain (bodies 0..PALM), then the fingers, children of the palm:
       // separate loops, so the parent's pose needs no per-body select.
-      auto pass1 = [&](int j, const M3f &Rp, V3f pp, const SV &vp, M3f &Rb, V3f &pb, SV &vb) {
-        const float qj = L.at(R_Q + j);
-        const JT X = joint_of(sc, j, qj);
-        Rb = rot_right(Rp, X);
-        pb = pp + mul(Rp, X.r);
-        const SV vJ = s_vec(sc, j, L.at(R_QD + j));
-        vb = (j == 0 ? sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)) : x_motion(X, vp)) + vJ;
-        c_put(L, j, crm(vb, vJ));
-        L.sv_put(R_P + 6 * j, crf(vb, sym_mul(inertia_of(sk, j), vb)));
-      };
       M3f Rw;  // world pose and velocity of the latest chain body (the palm's after the chain)
       V3f pw = v3(0.0f, 0.0f, 0.0f);
       SV vprev = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));
       Rw.r0 = v3(1.0f, 0.0f, 0.0f); Rw.r1 = v3(0.0f, 1.0f, 0.0f); Rw.r2 = v3(0.0f, 0.0f, 1.0f);
-      for (int j = 0; j <= BASEB; ++j) {
-        M3f Rb;
-        V3f pb;
-        SV vb;
-        pass1(j, Rw, pw, vprev, Rb, pb, vb);
-        Rw = Rb;
-        pw = pb;
-        vprev = vb;
-      }
-      const M3f Rw2 = Rw;  // the base link's pose and velocity, for its contacts
-      const V3f pw2 = pw;
-      const SV v2 = vprev;
-      for (int j = BASEB + 1; j <= PALM; ++j) {
-        M3f Rb;
-        V3f pb;
-        SV vb;
-        pass1(j, Rw, pw, vprev, Rb, pb, vb);
-        Rw = Rb;
-        pw = pb;
-        vprev = vb;
-      }
-      for (int j = FL; j <= FR; ++j) {
-        M3f Rb;
-        V3f pb;
-        SV vb;
-        pass1(j, Rw, pw, vprev, Rb, pb, vb);
+      M3f Rw2;  // the base link's pose and velocity, for its contacts
+      V3f pw2;
+      SV v2;
+      if constexpr (SPEC) {
+        // the model's bodies in order, unrolled; the chain's pose and velocity
+        // stay the palm's once the fingers come
+        sfor<0, NJ>([&](auto jc) {
+          constexpr int J = decltype(jc)::value;
+          const float qj = L.at(R_Q + J), qdj = L.at(R_QD + J);
+          const JT X = joint_t<J>(qj);
+          if constexpr (J >= 2 && J <= PALM) cs_put_t<J>(L, X);
+          const M3f Rb = rot_right_k<rmx::kax(J)>(Rw, X.c, X.s);
+          V3f pb;
+          if constexpr (rmx::rev(J)) pb = pw + rot_org<J>(Rw);
+          else pb = pw + mul(Rw, X.r);
+          const SV vJ = s_vec_t<J>(qdj);
+          SV vb;
+          if constexpr (J == 0) vb = vJ;
+          else vb = x_motion_t<J>(X, vprev) + vJ;
+          c_put_t<J>(L, crm_s<J>(vb, qdj));
+          L.sv_put(R_P + 6 * J, crf(vb, body_mul<J>(vb)));
+          if constexpr (J <= PALM) {
+            Rw = Rb;
+            pw = pb;
+            vprev = vb;
+          }
+          if constexpr (J == BASEB) {
+            Rw2 = Rb;
+            pw2 = pb;
+            v2 = vb;
+          }
+        });
+      } else {
+        auto pass1 = [&](int j, const M3f &Rp, V3f pp, const SV &vp, M3f &Rb, V3f &pb, SV &vb) {
+          const float qj = L.at(R_Q + j);
+          const JT X = joint_of(sc, j, qj);
+          Rb = rot_right(Rp, X);
+          pb = pp + mul(Rp, X.r);
+          const SV vJ = s_vec(sc, j, L.at(R_QD + j));
+          vb = (j == 0 ? sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)) : x_motion(X, vp)) + vJ;
+          c_put(L, j, crm(vb, vJ));
+          L.sv_put(R_P + 6 * j, crf(vb, sym_mul(inertia_of(sk, j), vb)));
+        };
+        for (int j = 0; j <= BASEB; ++j) {
+          M3f Rb;
+          V3f pb;
+          SV vb;
+          pass1(j, Rw, pw, vprev, Rb, pb, vb);
+          Rw = Rb;
+          pw = pb;
+          vprev = vb;
+        }
+        Rw2 = Rw;  // the base link's pose and velocity, for its contacts
+        pw2 = pw;
+        v2 = vprev;
+        for (int j = BASEB + 1; j <= PALM; ++j) {
+          M3f Rb;
+          V3f pb;
+          SV vb;
+          pass1(j, Rw, pw, vprev, Rb, pb, vb);
+          Rw = Rb;
+          pw = pb;
+          vprev = vb;
+        }
+        for (int j = FL; j <= FR; ++j) {
+          M3f Rb;
+          V3f pb;
+          SV vb;
+          pass1(j, Rw, pw, vprev, Rb, pb, vb);
+        }
       }
 
       // ---- contacts on the base link and the fingers: world forces become body
@@ -681,65 +758,124 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
       // with the source and destination fixed, so no per-body selects.  The
       // parent's bias force receives its child's share in registers (pA8 for
       // the palm, pAc along the chain) instead of a round trip through LDS.
-      Sym6 IA8 = inertia_of(sk, PALM);
-      Sym6 IAc = IA8;
-      SV pA8 = L.sv_at(R_P + 6 * PALM), pAc;
-      auto pass2 = [&](int j, Sym6 &IA, const SV &pA_in, auto into_palm) {
-        constexpr bool TO_PALM = decltype(into_palm)::value;
-        const SV pAj = pA_in;
-        const float qj = L.at(R_Q + j), qdj = L.at(R_QD + j);
-        const float lim = sc.j_inom[j] * sc.accel_max;
-        const float tq = fmaxf(-lim, fminf(lim, sc.j_inom[j] * (wc * wc * (L.at(qref_row(j)) - qj) - 2.0f * zeta * wc * qdj)));
-        const SV Uj = s_sign(sc, j) * sym_col(IA, s_index(sc, j));
-        const float di = 1.0f / s_comp(sc, j, Uj);
-        const float u = tq - s_comp(sc, j, pAj);
-        L.sv_put(R_P + 6 * j, di * Uj);  // pA of body j is consumed: its row now holds U / D
-        L.at(R_UD + j) = u * di;
-        if (j > 0) {
-          sym_rank1(IA, Uj, di);
-          SV pa = pAj + (u * di) * Uj;
-          if (j >= 2) pa = pa + sym_mul(IA, c_at(L, j));
-          const JT X = joint_of(sc, j, qj);
-          const int p = parent_of(j);
-          // fold body j into its parent, with the transform specialised to the joint's axis
-          auto fold = [&](auto axis) {
-            constexpr int K = decltype(axis)::value;
-            const Sym6 Ip = congruence_k<K>(X, IA);
-            if constexpr (TO_PALM) {
-              pA8 = pA8 + x_force_T_k<K>(X, pa);
+      if constexpr (SPEC) {
+        // the same passes over the model's bodies, unrolled
+        Sym6 IA8 = body_sym<PALM>();
+        Sym6 IAc;
+        SV pA8 = L.sv_at(R_P + 6 * PALM), pAc;
+        auto pass2 = [&](auto jc, Sym6 &IA, const SV &pA_in) {
+          constexpr int J = decltype(jc)::value;
+          const SV pAj = pA_in;
+          const float qj = L.at(R_Q + J), qdj = L.at(R_QD + J);
+          const float lim = sc.j_inom[J] * sc.accel_max;
+          const float tq = fmaxf(-lim, fminf(lim, sc.j_inom[J] * (wc * wc * (L.at(qref_row(J)) - qj) - 2.0f * zeta * wc * qdj)));
+          const SV Uj = rmx::sgn(J) * sym_col(IA, rmx::sub_idx(J));
+          const float di = 1.0f / s_comp_t<J>(Uj);
+          const float u = tq - s_comp_t<J>(pAj);
+          L.sv_put(R_P + 6 * J, di * Uj);  // pA of body J is consumed: its row now holds U / D
+          L.at(R_UD + J) = u * di;
+          if constexpr (J > 0) {
+            sym_rank1_t(IA, Uj, di);
+            SV pa = pAj + (u * di) * Uj;
+            if constexpr (J >= 2) pa = pa + sym_mul_masked<c_mask<J>()>(IA, c_get_t<J>(L));
+            JT X;
+            if constexpr (J >= 2 && J <= PALM) X = joint_cs<J>(qj, L.at(cs_row<J>(0)), L.at(cs_row<J>(1)));
+            else X = joint_t<J>(qj);
+            const Sym6 Ip = congruence_t<J>(X, IA);
+            if constexpr (J >= FL) {
+              pA8 = pA8 + x_force_T_t<J>(X, pa);
               sym_add(IA8, Ip);
             } else {
-              pAc = L.sv_at(R_P + 6 * p) + x_force_T_k<K>(X, pa);
-              IAc = inertia_of(sk, p);
-              sym_add(IAc, Ip);
+              pAc = L.sv_at(R_P + 6 * (J - 1)) + x_force_T_t<J>(X, pa);
+              IAc = body_plus<J - 1>(Ip);
             }
-          };
-          if (X.k == 0) fold(AxisK<0>());
-          else if (X.k == 1) fold(AxisK<1>());
-          else fold(AxisK<2>());
-        }
-      };
-      for (int j = FR; j >= FL; --j) {
-        Sym6 IA = inertia_of(sk, j);
-        pass2(j, IA, L.sv_at(R_P + 6 * j), BoolK<true>());
-      }
-      pass2(PALM, IA8, pA8, BoolK<false>());
-      for (int j = PALM - 1; j >= 0; --j) pass2(j, IAc, pAc, BoolK<false>());
+          }
+        };
+        sfor_down<FL, FR + 1>([&](auto jc) {
+          constexpr int J = decltype(jc)::value;
+          Sym6 IA = body_sym<J>();
+          pass2(jc, IA, L.sv_at(R_P + 6 * J));
+        });
+        pass2(std::integral_constant<int, PALM>(), IA8, pA8);
+        sfor_down<0, PALM>([&](auto jc) { pass2(jc, IAc, pAc); });
 
-      // ---- ABA pass 3 (root to leaves): accelerations and the joint update ----
-      auto pass3 = [&](int j, const SV &a_parent) {
-        const float qj = L.at(R_Q + j);
-        const JT X = joint_of(sc, j, qj);
-        const SV ap = x_motion(X, a_parent) + c_at(L, j);
-        const float qdd = L.at(R_UD + j) - dot6(L.sv_at(R_P + 6 * j), ap);
-        const float qdn = L.at(R_QD + j) + h * qdd;
-        L.at(R_QD + j) = qdn;
-        L.at(R_Q + j) = qj + h * qdn;
-        return ap + s_vec(sc, j, qdd);
-      };
-      SV a_prev = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, g));  // world: -gravity
-      for (int j = 0; j <= PALM; ++j) a_prev = pass3(j, a_prev);
-      for (int j = FL; j <= FR; ++j) pass3(j, a_prev);          // the fingers, from the palm's acceleration
+        SV a_prev = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, g));  // world: -gravity
+        SV a_palm;
+        sfor<0, NJ>([&](auto jc) {
+          constexpr int J = decltype(jc)::value;
+          const float qj = L.at(R_Q + J);
+          JT X;
+          if constexpr (J >= 2 && J <= PALM) X = joint_cs<J>(qj, L.at(cs_row<J>(0)), L.at(cs_row<J>(1)));
+          else X = joint_t<J>(qj);
+          const SV ap = x_motion_t<J>(X, J >= FL ? a_palm : a_prev) + c_get_t<J>(L);
+          const float qdd = L.at(R_UD + J) - dot6(L.sv_at(R_P + 6 * J), ap);
+          const float qdn = L.at(R_QD + J) + h * qdd;
+          L.at(R_QD + J) = qdn;
+          L.at(R_Q + J) = qj + h * qdn;
+          if constexpr (J <= PALM) a_prev = ap + s_vec_t<J>(qdd);
+          if constexpr (J == PALM) a_palm = a_prev;
+        });
+      } else {
+        Sym6 IA8 = inertia_of(sk, PALM);
+        Sym6 IAc = IA8;
+        SV pA8 = L.sv_at(R_P + 6 * PALM), pAc;
+        auto pass2 = [&](int j, Sym6 &IA, const SV &pA_in, auto into_palm) {
+          constexpr bool TO_PALM = decltype(into_palm)::value;
+          const SV pAj = pA_in;
+          const float qj = L.at(R_Q + j), qdj = L.at(R_QD + j);
+          const float lim = sc.j_inom[j] * sc.accel_max;
+          const float tq = fmaxf(-lim, fminf(lim, sc.j_inom[j] * (wc * wc * (L.at(qref_row(j)) - qj) - 2.0f * zeta * wc * qdj)));
+          const SV Uj = s_sign(sc, j) * sym_col(IA, s_index(sc, j));
+          const float di = 1.0f / s_comp(sc, j, Uj);
+          const float u = tq - s_comp(sc, j, pAj);
+          L.sv_put(R_P + 6 * j, di * Uj);  // pA of body j is consumed: its row now holds U / D
+          L.at(R_UD + j) = u * di;
+          if (j > 0) {
+            sym_rank1(IA, Uj, di);
+            SV pa = pAj + (u * di) * Uj;
+            if (j >= 2) pa = pa + sym_mul(IA, c_at(L, j));
+            const JT X = joint_of(sc, j, qj);
+            const int p = parent_of(j);
+            // fold body j into its parent, with the transform specialised to the joint's axis
+            auto fold = [&](auto axis) {
+              constexpr int K = decltype(axis)::value;
+              const Sym6 Ip = congruence_k<K>(X, IA);
+              if constexpr (TO_PALM) {
+                pA8 = pA8 + x_force_T_k<K>(X, pa);
+                sym_add(IA8, Ip);
+              } else {
+                pAc = L.sv_at(R_P + 6 * p) + x_force_T_k<K>(X, pa);
+                IAc = inertia_of(sk, p);
+                sym_add(IAc, Ip);
+              }
+            };
+            if (X.k == 0) fold(AxisK<0>());
+            else if (X.k == 1) fold(AxisK<1>());
+            else fold(AxisK<2>());
+          }
+        };
+        for (int j = FR; j >= FL; --j) {
+          Sym6 IA = inertia_of(sk, j);
+          pass2(j, IA, L.sv_at(R_P + 6 * j), BoolK<true>());
+        }
+        pass2(PALM, IA8, pA8, BoolK<false>());
+        for (int j = PALM - 1; j >= 0; --j) pass2(j, IAc, pAc, BoolK<false>());
+
+        // ---- ABA pass 3 (root to leaves): accelerations and the joint update ----
+        auto pass3 = [&](int j, const SV &a_parent) {
+          const float qj = L.at(R_Q + j);
+          const JT X = joint_of(sc, j, qj);
+          const SV ap = x_motion(X, a_parent) + c_at(L, j);
+          const float qdd = L.at(R_UD + j) - dot6(L.sv_at(R_P + 6 * j), ap);
+          const float qdn = L.at(R_QD + j) + h * qdd;
+          L.at(R_QD + j) = qdn;
+          L.at(R_Q + j) = qj + h * qdn;
+          return ap + s_vec(sc, j, qdd);
+        };
+        SV a_prev = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, g));  // world: -gravity
+        for (int j = 0; j <= PALM; ++j) a_prev = pass3(j, a_prev);
+        for (int j = FL; j <= FR; ++j) pass3(j, a_prev);          // the fingers, from the palm's acceleration
+      }
       integrate(ob, W, inv_om, oIb, gv, h);
     }
     if (TRACE && t < trace_steps && gi == 0) {

@@ -15,6 +15,8 @@
 // lanes stay busy while the instance has plans left.  Both modes execute the
 // same per-environment code in the same kernel, so an instance's results do
 // not depend on whether it ran alone or in a batch.
+#include <atomic>
+
 #include "internal.hpp"
 #include "robot_env.hpp"
 #include "push_env.hpp"
@@ -22,7 +24,7 @@
 namespace cem {
 namespace {
 
-template <bool TRACE, bool MULTI>
+template <bool TRACE, bool MULTI, bool SPEC>
 __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, const InstDesc *__restrict__ insts,
                                                            const WorkItem *__restrict__ items, int n_items,
                                                            int *__restrict__ queue, int *__restrict__ pool,
@@ -74,15 +76,33 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
     const long vl = env0 + lane, env = vl >> lg, row = env / R;
     const int g = (int)(vl & (G - 1));
     const bool pooled = pool && robot && R == 1;  // wave-uniform
-    if (active && pooled) {
-      // the item's plans: the next 64 of the instance's pool; then, lane by
-      // lane as rollouts end, one more each (one atomic add per wave)
+    if (active && robot && (pooled || lane < n)) {
+      // One inlined copy of the environment code serves both modes, so an
+      // instance's outcomes are bit for bit the same whether it ran alone or
+      // pooled in a batch.  Pooled: the item's plans are the next 64 of the
+      // instance's pool; then, lane by lane as rollouts end, one more each
+      // (one atomic add per wave).  Alone: this lane's one rollout (its
+      // group's, with G lanes per environment) with its scenario's draws.
       const int pop = d.pop;
-      int e0 = 0;
-      if (lane == 0) e0 = atomicAdd(&pool[inst], 64);
-      e0 = __builtin_amdgcn_readfirstlane(e0);
-      const long row0 = (long)e0 + lane;
+      long row0 = row;
+      bool live0 = true;
+      float mu = st->obj_mu, m = st->scene.obj_mass;
+      if (pooled) {
+        int e0 = 0;
+        if (lane == 0) e0 = atomicAdd(&pool[inst], 64);
+        e0 = __builtin_amdgcn_readfirstlane(e0);
+        row0 = (long)e0 + lane;
+        live0 = row0 < pop;
+      } else if (R > 1) {
+        const int r = (int)(env & (R - 1));
+        if (st->scene.dr_mu_hi > 0.0f) mu = st->dr_mu[r];
+        if (st->scene.dr_mass_hi > 0.0f) m = st->dr_mass[r];
+      }
       auto claim = [&](bool need, long &r, bool &live) {
+        if (!pooled) {
+          if (need) live = false;
+          return;
+        }
         const unsigned long long want = __ballot(need);
         if (want == 0ull) return;
         const int leader = __builtin_ctzll(want);
@@ -95,34 +115,23 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
         }
       };
       auto finish = [&](const EnvOut &e, long r) {
+        if (!pooled) {
+          o = e;
+          return;
+        }
         if (d.cost) d.cost[r] = e.cost;
         if (d.tier) d.tier[r] = (uint8_t)e.tier;
         if (d.pose)
 #pragma unroll
           for (int i = 0; i < 7; ++i) d.pose[r * 7 + i] = e.pose[i];
       };
-      steps = robot_env<false, false>(st, d.Z, row0, row0 < pop, st->obj_mu, st->scene.obj_mass, lds, lane, 0, 1,
-                                      nullptr, 0, claim, finish);
-    } else if (active && lane < n) {
-      if (!robot) {
-        push_env<TRACE>(st->scene, st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
-        steps = st->scene.horizon;
-      } else {
-        float mu = st->obj_mu, m = st->scene.obj_mass;
-        if (R > 1) {
-          const int r = (int)(env & (R - 1));
-          if (st->scene.dr_mu_hi > 0.0f) mu = st->dr_mu[r];
-          if (st->scene.dr_mass_hi > 0.0f) m = st->dr_mass[r];
-        }
-        // this lane's one rollout (its group's, with G lanes per environment)
-        auto one = [](bool need, long &, bool &live) {
-          if (need) live = false;
-        };
-        auto keep = [&](const EnvOut &e, long) { o = e; };
-        const int s = robot_env<TRACE, MULTI>(st, d.Z, row, true, mu, m, lds, lane, g, G, trace, trace_steps, one,
-                                              keep);
-        steps = g == 0 ? s : 0;
-      }
+      const int s = robot_env<TRACE, MULTI, SPEC>(st, d.Z, row0, live0, mu, m, lds, lane, pooled ? 0 : g,
+                                                  pooled ? 1 : G, pooled ? nullptr : trace, pooled ? 0 : trace_steps,
+                                                  claim, finish);
+      steps = (pooled || g == 0) ? s : 0;
+    } else if (active && !robot && lane < n) {
+      push_env<TRACE>(st->scene, st, d.Z, env, d.cost, d.tier, d.pose, trace, trace_steps);
+      steps = st->scene.horizon;
     }
     if (active && robot && !pooled) {
       // a row's scenarios sit in R adjacent lanes: the worst tier, and the
@@ -221,6 +230,22 @@ __global__ void pack_dataset_kernel(const float *__restrict__ Z, const float *__
 
 }  // namespace
 
+// Library-wide switch of the rollout instance specialised to the robot model
+// (on unless cem_set_robot_specialization turned it off).
+std::atomic<int> g_robot_spec{1};
+
+bool robot_spec_for(const cem_scene &sc) {
+  if (!g_robot_spec.load() || (sc.kind != CEM_SCENE_PICKPLACE && sc.kind != CEM_SCENE_MOVEPUSH)) return false;
+  if (sc.n_joints != rm::N) return false;
+  for (int j = 0; j < rm::N; ++j) {
+    if (sc.j_type[j] != rm::TYPE[j] || sc.j_axis[j] != rm::AXIS[j] || sc.b_mass[j] != rm::MASS[j]) return false;
+    for (int c = 0; c < 3; ++c)
+      if (sc.j_origin[j][c] != rm::ORIGIN[j][c] || sc.b_com[j][c] != rm::COM[j][c] || sc.b_half[j][c] != rm::HALF[j][c])
+        return false;
+  }
+  return true;
+}
+
 hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_steps, hipStream_t s) {
   if (d.scen < 1 || d.scen > 64 || (d.scen & (d.scen - 1))) return hipErrorInvalidValue;
   if ((d.lanes != 1 && d.lanes != 2 && d.lanes != 4 && d.lanes != 8 && d.lanes != 16) || d.scen * d.lanes > 64 ||
@@ -229,8 +254,11 @@ hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_step
   const int n_items = (d.pop * d.scen * d.lanes + 63) / 64;
   if (n_items == 0) return hipSuccess;
   const bool multi = d.lanes > 1;
-  const RolloutKernel k = trace ? (multi ? rollout_items_kernel<true, true> : rollout_items_kernel<true, false>)
-                                : (multi ? rollout_items_kernel<false, true> : rollout_items_kernel<false, false>);
+  const RolloutKernel k =
+      d.spec ? (trace ? (multi ? rollout_items_kernel<true, true, true> : rollout_items_kernel<true, false, true>)
+                      : (multi ? rollout_items_kernel<false, true, true> : rollout_items_kernel<false, false, true>))
+             : (trace ? (multi ? rollout_items_kernel<true, true, false> : rollout_items_kernel<true, false, false>)
+                      : (multi ? rollout_items_kernel<false, true, false> : rollout_items_kernel<false, false, false>));
   hipLaunchKernelGGL(k, dim3(n_items), dim3(64), 0, s, d, nullptr, nullptr, n_items, nullptr, nullptr, 0, trace,
                      trace ? trace_steps : 0);
   return hipGetLastError();
@@ -249,12 +277,14 @@ hipError_t launch_pack_dataset(const InstDesc &d, float cost_cap, float *X, floa
 }
 
 hipError_t launch_rollout_batch(const InstDesc *insts, int n_inst, const WorkItem *items, int n_items, int *queue,
-                                int *pool, int grid, hipStream_t s) {
+                                int *pool, int grid, bool spec, hipStream_t s) {
   hipLaunchKernelGGL(reset_counters_kernel, dim3((n_inst + 255) / 256 + 1), dim3(256), 0, s, queue, pool, n_inst);
   InstDesc none{};
-  const RolloutKernel k = rollout_items_kernel<false, false>;
+  const RolloutKernel k = spec ? rollout_items_kernel<false, false, true> : rollout_items_kernel<false, false, false>;
   hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, s, none, insts, items, n_items, queue, pool, 1, nullptr, 0);
   return hipGetLastError();
 }
 
 }  // namespace cem
+
+void cem_set_robot_specialization(int32_t enable) { cem::g_robot_spec.store(enable ? 1 : 0); }

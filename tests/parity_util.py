@@ -1,9 +1,9 @@
 """Shared certification and reporting for the GPU-against-oracle parity tests
 (not a test module).
 
-A row is certified when nudging every parameter by 1 or 4 ulps either way
-leaves the oracle's cost and tier unchanged: its outcome does not hang on
-rounding.  Where the goal predicate psi_g decides the tier (every action
+A row is certified when nudging every parameter by 1, 4, 16, 64 and 256 ulps
+either way leaves the oracle's cost and tier unchanged: its outcome does not
+hang on rounding.  Where the goal predicate psi_g decides the tier (every action
 succeeded), the row's tier is certified only when the oracle's final object
 position also lies farther from the boundary of the goal region than 0.8 of
 the object's smallest half extent: an object whose centre is nearer than its
@@ -58,8 +58,7 @@ def goal_decided(w, tier_ref, pose_ref, speed_ref, rest_ref):
     return (np.asarray(tier_ref) >= 2) | ((goal_margin(w, pose_ref) > m) & rest_ok)
 
 
-SPREAD = 1e-3        # m: the final object position's largest move under the 1- and 4-ulp nudges
-WIDE = (16, 64, 256)  # ulps: the further nudges a row must withstand when its final state spreads more
+WIDE = (16, 64, 256)  # ulps: the further nudges every row must withstand
 
 
 def nudged(Z, ulps, sign):
@@ -72,14 +71,16 @@ def nudged(Z, ulps, sign):
 def certify(oracle, w, seed, Z, inst=0):
     """The oracle's outcome of rows Z and which rows are certified.
 
-    A row is certified when nudging every parameter by 1 or 4 ulps either way
-    leaves the oracle's tier and cost unchanged.  A row whose final object
-    position those nudges move by SPREAD or more is in chaotic motion (an
-    object knocked over, tumbling, landing): its outcome must also survive
-    nudges of 16, 64 and 256 ulps, since the FP32 rollout's rounding perturbs
-    it throughout the horizon, not once at the start.  Where psi_g decides
-    the tier, goal_decided is required too.
-    Returns dict(cost, tier, pose, steps, spread, ok (cost and tier), okt (tier))."""
+    A row is certified when nudging every parameter by 1, 4, 16, 64 and 256
+    FP32 ulps either way leaves the oracle's tier and cost unchanged.  The FP32
+    rollout's rounding perturbs the state throughout the horizon, not once at
+    the start, so an outcome that moves under nudges of the inputs this small
+    (an action decided on the step a threshold is crossed, a grasp that barely
+    closes, an object knocked over or landing) is not decided by the method at
+    FP32 precision, and two FP32 evaluations of it that round differently may
+    both be right.  Where psi_g decides the tier, goal_decided is required too.
+    Returns dict(cost, tier, pose, steps, spread (the final object position's
+    largest move under the 1- and 4-ulp nudges), ok (cost and tier), okt (tier))."""
     c0, t0, p0, _, s0, sp0, rs0 = oracle.rollout(w, seed, Z, inst=inst, with_steps=True, with_rest=True)
     tol = 1e-6 if w["scene"]["kind"] == "push" else 1e-9
     ok = np.ones(len(Z), bool)
@@ -89,7 +90,7 @@ def certify(oracle, w, seed, Z, inst=0):
             c, t, p, _ = oracle.rollout(w, seed, nudged(Z, ulps, sign), inst=inst)
             ok &= (t == t0) & (np.abs(c - c0) < tol)
             spread = np.maximum(spread, np.max(np.abs(p[:, :3] - p0[:, :3]), axis=1))
-    wide = np.nonzero(ok & (spread >= SPREAD))[0]
+    wide = np.nonzero(ok)[0]
     if wide.size:
         for ulps in WIDE:
             for sign in (1, -1):

@@ -7,7 +7,7 @@ instances run three different action sequences in one launch.
 - Iteration 0 of sampled instances (the longest-horizon pick-and-place, the
   other pick-and-place instances with H >= 2000, and push instances): the
   sampled rows are the oracle's bit for bit; on 48 random rows of each, the
-  rows the oracle certifies (cost and tier unchanged by 1- and 4-ulp nudges of
+  rows the oracle certifies (cost and tier unchanged by 1- to 256-ulp nudges of
   every parameter) have the oracle's tier, and their costs agree within two
   control steps (robot plans) or 1e-3 (push).
 - The full CE runs of the 32 push instances (each its own problem, 5

@@ -109,7 +109,7 @@ def test_parity_with_the_oracle(oracle, B, lanes):
     w = _dr(workloads.load("movepush"), 4)
     seed = 2
     Z = _rows(oracle, w, seed, 64)
-    r = certify(oracle, w, seed, Z)            # certified: nudges of 1 and 4 ulps either way change nothing
+    r = certify(oracle, w, seed, Z)            # certified: nudges of 1 to 256 ulps either way change nothing
     ok, c0, t0 = r["ok"], r["cost"], r["tier"]
     assert ok.sum() >= 24
     cg, tg, _, _, _ = _run(B, w, Z, seed, lanes)
