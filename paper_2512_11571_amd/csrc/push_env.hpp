@@ -32,6 +32,7 @@ __device__ __forceinline__ void push_env(CScene &sc, CDevState *st,
   const float m = sc.obj_mass, inv_m = 1.0f / m;
   const V3f Ib = v3(m * (he.y * he.y + he.z * he.z) / 3.0f, m * (he.x * he.x + he.z * he.z) / 3.0f,
                     m * (he.x * he.x + he.y * he.y) / 3.0f);
+  const V3f inv_Ib = v3(1.0f / Ib.x, 1.0f / Ib.y, 1.0f / Ib.z);
 
   const float th = Z[(long)i * 3 + 0], off = Z[(long)i * 3 + 1];
   const float sp = fmaxf(0.0f, fminf(sc.pusher_vmax, Z[(long)i * 3 + 2]));
@@ -64,7 +65,7 @@ __device__ __forceinline__ void push_env(CScene &sc, CDevState *st,
       Wrench W{v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f)};
       box_ground(b, R, he, k, damp, sc.mu_ground, eps2, W);
       sphere_on_box(b, R, he, pc, sc.pusher_radius, vc, k, damp, sc.mu_tool, eps2, W);
-      integrate(b, W, inv_m, Ib, gv, h);
+      integrate(b, W, inv_m, Ib, inv_Ib, gv, h, R);
     }
     const float dx = b.p.x - gx, dy = b.p.y - gy;
     unsuccessful += (dx * dx + dy * dy > tol2) ? 1 : 0;

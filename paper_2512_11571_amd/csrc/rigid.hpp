@@ -23,13 +23,28 @@ struct Wrench {
 };
 
 // Penalty force on A; `on` masks inactive contacts (returns exactly zero).
+// The regularised friction's 1 / sqrt(|v_t|^2 + eps_v^2) is the hardware's
+// reciprocal square root (about 1 ulp; its argument is at least eps_v^2 > 0).
 __device__ __forceinline__ V3f contact_force(bool on, V3f n, float d, V3f vrel, float k, float damp, float mu,
                                              float eps2) {
   const float vn = dot(n, vrel);
   const float fn = on ? fmaxf(0.0f, k * d - damp * vn) : 0.0f;
   const V3f vt = vrel - vn * n;
-  const float s = -(mu * fn) / sqrtf(dot(vt, vt) + eps2);
+  const float s = -(mu * fn) * __builtin_amdgcn_rsqf(dot(vt, vt) + eps2);
   return fn * n + s * vt;
+}
+
+// The same force in the frame of box B, whose face normal there is sgn e_ax:
+// the normal speed is one component of vrel, the tangential velocity is vrel
+// with that component zero, and the force's component ax is the normal force.
+__device__ __forceinline__ V3f contact_force_b(int ax, float sgn, float d, V3f vrel, float k, float damp, float mu,
+                                               float eps2) {
+  const float va = ax == 0 ? vrel.x : (ax == 1 ? vrel.y : vrel.z);
+  const float fn = fmaxf(0.0f, k * d - damp * (sgn * va));
+  const V3f vt = v3(ax == 0 ? 0.0f : vrel.x, ax == 1 ? 0.0f : vrel.y, ax == 2 ? 0.0f : vrel.z);
+  const float s = -(mu * fn) * __builtin_amdgcn_rsqf(dot(vt, vt) + eps2);  // as in contact_force
+  const float f = fn * sgn;
+  return v3(ax == 0 ? f : s * vt.x, ax == 1 ? f : s * vt.y, ax == 2 ? f : s * vt.z);
 }
 
 __device__ __forceinline__ void apply(Wrench &W, V3f r, V3f F) {
@@ -103,14 +118,16 @@ __device__ __forceinline__ void sphere_on_box(const FreeBody &b, const M3f &R, V
   apply(W, r, F);
 }
 
-// Semi-implicit Euler step with principal inertia Ib (body frame) and gravity gv.
-__device__ __forceinline__ void integrate(FreeBody &b, const Wrench &W, float inv_m, V3f Ib, V3f gv, float h) {
-  const M3f R = rot_of(b.q);
+// Semi-implicit Euler step with principal inertia Ib (body frame; inv_Ib its
+// reciprocals), gravity gv and R = rot_of(b.q).  The quaternion's
+// renormalisation takes the hardware's reciprocal square root (about 1 ulp).
+__device__ __forceinline__ void integrate(FreeBody &b, const Wrench &W, float inv_m, V3f Ib, V3f inv_Ib, V3f gv,
+                                          float h, const M3f &R) {
   b.v = b.v + h * (inv_m * W.f + gv);
   const V3f wb = mulT(R, b.w);
   const V3f Lw = mul(R, v3(Ib.x * wb.x, Ib.y * wb.y, Ib.z * wb.z));
   const V3f rb = mulT(R, W.t - cross(b.w, Lw));
-  b.w = b.w + h * mul(R, v3(rb.x / Ib.x, rb.y / Ib.y, rb.z / Ib.z));
+  b.w = b.w + h * mul(R, v3(rb.x * inv_Ib.x, rb.y * inv_Ib.y, rb.z * inv_Ib.z));
   b.p = b.p + h * b.v;
   const float hh = 0.5f * h;
   const Q4f q = b.q;
@@ -119,7 +136,7 @@ __device__ __forceinline__ void integrate(FreeBody &b, const Wrench &W, float in
   const float nx = q.x + hh * (q.w * w.x + w.y * q.z - w.z * q.y);
   const float ny = q.y + hh * (q.w * w.y + w.z * q.x - w.x * q.z);
   const float nz = q.z + hh * (q.w * w.z + w.x * q.y - w.y * q.x);
-  const float inv = 1.0f / sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
+  const float inv = __builtin_amdgcn_rsqf(nw * nw + nx * nx + ny * ny + nz * nz);
   b.q = Q4f{nw * inv, nx * inv, ny * inv, nz * inv};
 }
 

@@ -417,6 +417,37 @@ __device__ __forceinline__ void verts_in_box(const Rel &r, V3f hA, const Box &B,
   }
 }
 
+// As verts_in_box, with the contact handed over in B's frame: f(xb, ax, sgn,
+// d) with xb the vertex relative to B's centre and sgn e_ax the outward normal
+// of B's nearest face, so that the caller forms the force there and rotates
+// its sums once per pair instead of every contact point into the world.
+template <class F>
+__device__ __forceinline__ void verts_in_box_b(const Rel &r, V3f hA, V3f hb, F &&f, unsigned vmask = 0xFFu) {
+  const V3f c0 = hA.x * col(r.M, 0), c1 = hA.y * col(r.M, 1), c2 = hA.z * col(r.M, 2);
+  unsigned inside = 0u;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const V3f xb = (r.t + ((i & 4) ? c2 : -c2) + ((i & 2) ? c1 : -c1)) + ((i & 1) ? c0 : -c0);
+    if (fabsf(xb.x) < hb.x && fabsf(xb.y) < hb.y && fabsf(xb.z) < hb.z) inside |= 1u << i;
+  }
+  inside &= vmask;
+  while (inside != 0u) {  // at most eight passes
+    const int i = __builtin_ctz(inside);
+    inside &= inside - 1u;
+    const V3f xb = (r.t + ((i & 4) ? c2 : -c2) + ((i & 2) ? c1 : -c1)) + ((i & 1) ? c0 : -c0);
+    const float ds[6] = {hb.x - xb.x, hb.x + xb.x, hb.y - xb.y, hb.y + xb.y, hb.z - xb.z, hb.z + xb.z};
+    int fb = 0;
+    float dmin = ds[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) {
+      const bool lt = ds[k] < dmin;
+      fb = lt ? k : fb;
+      dmin = lt ? ds[k] : dmin;
+    }
+    f(xb, fb >> 1, (fb & 1) ? -1.0f : 1.0f, dmin);
+  }
+}
+
 __device__ __forceinline__ Box static_box(CScene &sc, CConsts &k, int b) {
   Box B;
   B.p = v3(sc.st_center[b][0], sc.st_center[b][1], sc.st_center[b][2]);

@@ -214,6 +214,7 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
   const float inv_om = 1.0f / om;
   const V3f oIb = v3(om * (ohe.y * ohe.y + ohe.z * ohe.z) / 3.0f, om * (ohe.x * ohe.x + ohe.z * ohe.z) / 3.0f,
                      om * (ohe.x * ohe.x + ohe.y * ohe.y) / 3.0f);
+  const V3f inv_oIb = v3(1.0f / oIb.x, 1.0f / oIb.y, 1.0f / oIb.z);
   const V3f gv = v3(0.0f, 0.0f, -g);
 
   Params4 zp;
@@ -532,6 +533,13 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
       const bool w_halves = G >= 8 && sc.n_static + 1 <= 4;
       const int w_step = w_halves ? 4 : G;
       const unsigned w_mask = w_halves ? corner_part(gi, G) : 0xFFu;
+      // Contacts are formed in the frame of the box whose face they press on
+      // (there the normal is an axis): the object's velocity in its own frame,
+      // and the force and moment sums of the contacts on the object's faces in
+      // that frame (FO, TO, about its centre), rotated into the world once
+      // after the fingers' contacts
+      const V3f vO = mulT(OB.R, ob.v), wO = mulT(OB.R, ob.w);
+      V3f FO = v3(0.0f, 0.0f, 0.0f), TO = v3(0.0f, 0.0f, 0.0f);
       for (int u = gi & (w_step - 1); u <= sc.n_static; u += w_step) {
         if (u == 0) {
           box_ground(ob, OB.R, ohe, kc, damp, mu_o_ground, eps2, W, w_mask);
@@ -542,15 +550,23 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
         const float mu = mu_drawn ? mu_obj : (sc.st_ramp[b] ? sc.mu_ramp : sc.mu_static);
         const Rel r = rel_of(OB, SB);
         if (face_separated(r, ohe, SB.h)) continue;
-        // object vertices in the static box (A = object)
-        verts_in_box(r, ohe, SB, [&](V3f x, V3f n, float d) {
-          const V3f ro = x - ob.p;
-          apply(W, ro, contact_force(true, n, d, ob.v + cross(ob.w, ro), kc, damp, mu, eps2));
+        // object vertices in the static box (A = object), in the box's frame,
+        // where the object's centre is r.t
+        const V3f vB = mulT(SB.R, ob.v), wB = mulT(SB.R, ob.w);
+        V3f F = v3(0.0f, 0.0f, 0.0f), T = v3(0.0f, 0.0f, 0.0f);
+        verts_in_box_b(r, ohe, SB.h, [&](V3f xb, int ax, float sg, float d) {
+          const V3f ro = xb - r.t;
+          const V3f f = contact_force_b(ax, sg, d, vB + cross(wB, ro), kc, damp, mu, eps2);
+          F = F + f;
+          T = T + cross(ro, f);
         }, w_mask);
+        W.f = W.f + mul(SB.R, F);
+        W.t = W.t + mul(SB.R, T);
         // static-box vertices in the object (A = static box, the object receives the negative)
-        verts_in_box(rel_swap(r), SB.h, OB, [&](V3f x, V3f n, float d) {
-          const V3f ro = x - ob.p;
-          apply(W, ro, -contact_force(true, n, d, v3(0.0f, 0.0f, 0.0f) - (ob.v + cross(ob.w, ro)), kc, damp, mu, eps2));
+        verts_in_box_b(rel_swap(r), SB.h, ohe, [&](V3f xb, int ax, float sg, float d) {
+          const V3f f = -contact_force_b(ax, sg, d, v3(0.0f, 0.0f, 0.0f) - (vO + cross(wO, xb)), kc, damp, mu, eps2);
+          FO = FO + f;
+          TO = TO + cross(xb, f);
         }, w_mask);
       }
 
@@ -564,6 +580,9 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
       M3f Rw2;  // the base link's pose and velocity, for its contacts
       V3f pw2;
       SV v2;
+      M3f Rf[2];  // SPEC: the fingers' poses and velocities from the first pass
+      V3f pf[2];
+      SV vf[2];
       if constexpr (SPEC) {
         // the model's bodies in order, unrolled; the chain's pose and velocity
         // stay the palm's once the fingers come
@@ -591,6 +610,11 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
             Rw2 = Rb;
             pw2 = pb;
             v2 = vb;
+          }
+          if constexpr (J >= FL) {
+            Rf[J - FL] = Rb;
+            pf[J - FL] = pb;
+            vf[J - FL] = vb;
           }
         });
       } else {
@@ -646,15 +670,10 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
         // the base link against the static boxes
         {
           const Box LB = link_box(BASEB, Rw2, pw2);
-          // velocity of a point and the force sum in the world frame, the
-          // moment about the body origin; one rotation into the body at the end
-          const V3f wa = mul(Rw2, v2.a), wb = mul(Rw2, v2.b);
+          const V3f com = v3(sc.b_com[BASEB][0], sc.b_com[BASEB][1], sc.b_com[BASEB][2]);
+          // the spatial force on the link in its body frame (moment about the
+          // body origin); the link box's frame is the body's, offset by com
           V3f fm = v3(0.0f, 0.0f, 0.0f), ff = v3(0.0f, 0.0f, 0.0f);
-          auto link_v = [&](V3f x) { return wb + cross(wa, x - pw2); };
-          auto link_f = [&](V3f x, V3f F) {
-            fm = fm + cross(x - pw2, F);
-            ff = ff + F;
-          };
           // every G-th static box, or with 8 or 16 lanes and at most four
           // boxes every 4th on part of the corners, as for the object above
           const bool b_halves = G >= 8 && sc.n_static <= 4;
@@ -664,18 +683,32 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
             const Box SB = static_box(sc, sk, b);
             const Rel r = rel_of(LB, SB);
             if (face_separated(r, LB.h, SB.h)) continue;
-            verts_in_box(r, LB.h, SB, [&](V3f x, V3f n, float d) {
-              link_f(x, contact_force(true, n, d, link_v(x), kc, damp, sc.mu_static, eps2));
+            // link vertices in the static box, in the box's frame: the body
+            // origin at q, the link's velocity (M v2) there
+            const V3f q = r.t - mul(r.M, com), wa = mul(r.M, v2.a), wb = mul(r.M, v2.b);
+            V3f F = v3(0.0f, 0.0f, 0.0f), T = v3(0.0f, 0.0f, 0.0f);
+            verts_in_box_b(r, LB.h, SB.h, [&](V3f xb, int ax, float sg, float d) {
+              const V3f ro = xb - q;
+              const V3f f = contact_force_b(ax, sg, d, wb + cross(wa, ro), kc, damp, sc.mu_static, eps2);
+              F = F + f;
+              T = T + cross(ro, f);
             }, b_mask);
-            verts_in_box(rel_swap(r), SB.h, LB, [&](V3f x, V3f n, float d) {
-              link_f(x, -contact_force(true, n, d, v3(0.0f, 0.0f, 0.0f) - link_v(x), kc, damp, sc.mu_static, eps2));
+            ff = ff + mulT(r.M, F);
+            fm = fm + mulT(r.M, T);
+            // static-box vertices in the link, in the body frame
+            verts_in_box_b(rel_swap(r), SB.h, LB.h, [&](V3f xb, int ax, float sg, float d) {
+              const V3f ro = xb + com;
+              const V3f f = -contact_force_b(ax, sg, d, v3(0.0f, 0.0f, 0.0f) - (v2.b + cross(v2.a, ro)), kc, damp,
+                                             sc.mu_static, eps2);
+              ff = ff + f;
+              fm = fm + cross(ro, f);
             }, b_mask);
           }
           if (G > 1) {
             fm = group_sum(fm, G);
             ff = group_sum(ff, G);
           }
-          L.sv_put(R_P + 6 * BASEB, L.sv_at(R_P + 6 * BASEB) - sv(mulT(Rw2, fm), mulT(Rw2, ff)));
+          L.sv_put(R_P + 6 * BASEB, L.sv_at(R_P + 6 * BASEB) - sv(fm, ff));
         }
         // the fingers against the object (their pose again from the palm's);
         // G 1 takes both fingers, G 2 finger FL + gi, G 4 finger FL + gi / 2
@@ -688,49 +721,78 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
         SV part = sv(v3(0.0f, 0.0f, 0.0f), v3(0.0f, 0.0f, 0.0f));  // G > 1: this lane's body-frame share
         bool part_any = false;
         for (int j = jf0; j <= jf1; ++j) {
-          const JT X = joint_of(sc, j, L.at(R_Q + j));
-          const M3f Rb = rot_right(Rw, X);
-          const V3f pb = pw + mul(Rw, X.r);
-          const SV vb = x_motion(X, vprev) + s_vec(sc, j, L.at(R_QD + j));
+          M3f Rb;
+          V3f pb;
+          SV vb;
+          if constexpr (SPEC) {
+            Rb = j == FL ? Rf[0] : Rf[1];
+            pb = j == FL ? pf[0] : pf[1];
+            vb = j == FL ? vf[0] : vf[1];
+          } else {
+            const JT X = joint_of(sc, j, L.at(R_Q + j));
+            Rb = rot_right(Rw, X);
+            pb = pw + mul(Rw, X.r);
+            vb = x_motion(X, vprev) + s_vec(sc, j, L.at(R_QD + j));
+          }
           const Box LB = link_box(j, Rb, pb);
-          const V3f wa = mul(Rb, vb.a), wb = mul(Rb, vb.b);
+          const V3f com = v3(sc.b_com[j][0], sc.b_com[j][1], sc.b_com[j][2]);
+          // the spatial force on the finger in its body frame (the finger
+          // box's frame, offset by com)
           V3f fm = v3(0.0f, 0.0f, 0.0f), ff = v3(0.0f, 0.0f, 0.0f);
-          auto link_v = [&](V3f x) { return wb + cross(wa, x - pb); };
-          auto link_f = [&](V3f x, V3f F) {
-            fm = fm + cross(x - pb, F);
-            ff = ff + F;
-          };
           const Rel r = rel_of(LB, OB);
           bool any = false;
           if (!face_separated(r, LB.h, ohe)) {
-            // finger vertices in the object (A = finger, B = object)
-            if (dirs & 1) verts_in_box(r, LB.h, OB, [&](V3f x, V3f n, float d) {
-              const V3f ro = x - ob.p;
-              const V3f F = contact_force(true, n, d, link_v(x) - (ob.v + cross(ob.w, ro)), kc, damp, mu_o_tool, eps2);
-              link_f(x, F);
-              apply(W, ro, -F);
-              any = true;
-            }, f_mask);
-            // object vertices in the finger (A = object, B = finger)
-            if (dirs & 2) verts_in_box(rel_swap(r), ohe, LB, [&](V3f x, V3f n, float d) {
-              const V3f ro = x - ob.p;
-              const V3f F = contact_force(true, n, d, (ob.v + cross(ob.w, ro)) - link_v(x), kc, damp, mu_o_tool, eps2);
-              apply(W, ro, F);
-              link_f(x, -F);
-              any = true;
-            }, f_mask);
+            // finger vertices in the object (A = finger, B = object), in the
+            // object's frame: the finger's origin at q, its velocity (M vb) there
+            if (dirs & 1) {
+              const V3f q = r.t - mul(r.M, com), wa = mul(r.M, vb.a), wb = mul(r.M, vb.b);
+              V3f F = v3(0.0f, 0.0f, 0.0f), T = v3(0.0f, 0.0f, 0.0f);
+              verts_in_box_b(r, LB.h, ohe, [&](V3f xb, int ax, float sg, float d) {
+                const V3f f = contact_force_b(ax, sg, d, (wb + cross(wa, xb - q)) - (vO + cross(wO, xb)), kc, damp,
+                                              mu_o_tool, eps2);
+                F = F + f;
+                T = T + cross(xb - q, f);
+                FO = FO - f;
+                TO = TO - cross(xb, f);
+                any = true;
+              }, f_mask);
+              ff = ff + mulT(r.M, F);
+              fm = fm + mulT(r.M, T);
+            }
+            // object vertices in the finger (A = object, B = finger), in the
+            // finger's frame: the object's centre at rs.t, its velocity there
+            if (dirs & 2) {
+              const Rel rs = rel_swap(r);
+              const V3f vF = mulT(r.M, vO), wF = mulT(r.M, wO);
+              V3f F = v3(0.0f, 0.0f, 0.0f), T = v3(0.0f, 0.0f, 0.0f);
+              verts_in_box_b(rs, ohe, LB.h, [&](V3f xb, int ax, float sg, float d) {
+                const V3f ro = xb + com;
+                const V3f f = contact_force_b(ax, sg, d, (vF + cross(wF, xb - rs.t)) - (vb.b + cross(vb.a, ro)), kc,
+                                              damp, mu_o_tool, eps2);
+                F = F + f;
+                T = T + cross(xb - rs.t, f);
+                ff = ff - f;
+                fm = fm - cross(ro, f);
+                any = true;
+              }, f_mask);
+              FO = FO + mul(r.M, F);
+              TO = TO + mul(r.M, T);
+            }
           }
           if (G == 1) {
             if (last) {
               if (j == FL) touchL = any;
               else touchR = any;
             }
-            L.sv_put(R_P + 6 * j, L.sv_at(R_P + 6 * j) - sv(mulT(Rb, fm), mulT(Rb, ff)));
+            L.sv_put(R_P + 6 * j, L.sv_at(R_P + 6 * j) - sv(fm, ff));
           } else {
-            part = sv(mulT(Rb, fm), mulT(Rb, ff));
+            part = sv(fm, ff);
             part_any = any;
           }
         }
+        // the object's contacts on its own faces, into the world
+        W.f = W.f + mul(OB.R, FO);
+        W.t = W.t + mul(OB.R, TO);
         if (G > 1) {
           // each finger's force from the lanes that tested it (the others add
           // exact zeros), the object's wrench from the whole group
@@ -770,7 +832,7 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
           const float lim = sc.j_inom[J] * sc.accel_max;
           const float tq = fmaxf(-lim, fminf(lim, sc.j_inom[J] * (wc * wc * (L.at(qref_row(J)) - qj) - 2.0f * zeta * wc * qdj)));
           const SV Uj = rmx::sgn(J) * sym_col(IA, rmx::sub_idx(J));
-          const float di = 1.0f / s_comp_t<J>(Uj);
+          const float di = __builtin_amdgcn_rcpf(s_comp_t<J>(Uj));  // the hardware reciprocal (about 1 ulp)
           const float u = tq - s_comp_t<J>(pAj);
           L.sv_put(R_P + 6 * J, di * Uj);  // pA of body J is consumed: its row now holds U / D
           L.at(R_UD + J) = u * di;
@@ -826,7 +888,7 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
           const float lim = sc.j_inom[j] * sc.accel_max;
           const float tq = fmaxf(-lim, fminf(lim, sc.j_inom[j] * (wc * wc * (L.at(qref_row(j)) - qj) - 2.0f * zeta * wc * qdj)));
           const SV Uj = s_sign(sc, j) * sym_col(IA, s_index(sc, j));
-          const float di = 1.0f / s_comp(sc, j, Uj);
+          const float di = __builtin_amdgcn_rcpf(s_comp(sc, j, Uj));  // the hardware reciprocal (about 1 ulp)
           const float u = tq - s_comp(sc, j, pAj);
           L.sv_put(R_P + 6 * j, di * Uj);  // pA of body j is consumed: its row now holds U / D
           L.at(R_UD + j) = u * di;
@@ -876,7 +938,7 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
         for (int j = 0; j <= PALM; ++j) a_prev = pass3(j, a_prev);
         for (int j = FL; j <= FR; ++j) pass3(j, a_prev);          // the fingers, from the palm's acceleration
       }
-      integrate(ob, W, inv_om, oIb, gv, h);
+      integrate(ob, W, inv_om, oIb, inv_oIb, gv, h, OB.R);
     }
     if (TRACE && t < trace_steps && gi == 0) {
       float *o = trace + (row * trace_steps + t) * CEM_TRACE_ROBOT;

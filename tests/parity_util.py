@@ -113,3 +113,24 @@ def tier_mismatches(tag, ok, tier_gpu, tier_ref, cost_gpu, cost_ref, rows=None):
               % (rows[i], tier_gpu[i], cost_gpu[i], tier_ref[i], cost_ref[i]))
         out.append(int(rows[i]))
     return out
+
+
+def median_agreement(tag, gpu, ref, rel=1e-2):
+    """Paired seeds of Alg. 1 (the GPU's best cost and the oracle's, same seed):
+    at least half of the seeds agree within `rel`, and the medians agree within
+    `rel` or two standard errors of the median, whichever is larger.
+
+    The FP32 and FP64 runs share iteration 0's samples, so most seeds end at
+    the same plan; a seed whose elites part ways ends wherever CE takes it.
+    At small populations the seeds' best costs spread so widely that the
+    sampling error of a 32-seed median (1.2533 sd / sqrt(n), from the
+    oracle's spread) exceeds 1 % of the median, and a 1 % bound on the medians
+    alone would fail by chance; the paired count has no such noise."""
+    g, r = np.asarray(gpu, np.float64), np.asarray(ref, np.float64)
+    relgap = np.abs(g - r) / np.abs(r)
+    se = 1.2533 * np.std(r) / np.sqrt(len(r))
+    mg, mr = np.median(g), np.median(r)
+    print("%s: median best cost GPU %.4f oracle %.4f (standard error of the median %.4f); seeds within %.0e: %d of %d"
+          % (tag, mg, mr, se, rel, int(np.sum(relgap <= rel)), len(r)))
+    assert np.median(relgap) <= rel
+    assert abs(mg - mr) <= max(rel * abs(mr), 2.0 * se)

@@ -7,7 +7,9 @@ scenario 0's pose of R plain rollouts that carry the scenarios' friction and
 mass, and the step count covers all pop x R rollouts.  Against the oracle:
 tier and cost on certified rows (cost within two control steps).  Batched
 instances with scenarios give the bits of their single runs.  Statistical:
-median best cost of plan_solve over 32 seeds within 1e-2 relative.  The
+over 32 seeds of plan_solve, at least half the seeds' best costs within 1e-2
+relative of the oracle's, and the medians within 1e-2 or two standard errors
+of the median (parity_util.median_agreement).  The
 composition, oracle and population tests also run with 2 to 16 lanes per
 environment (the scenario butterfly then pairs lanes G, 2G, ... apart).
 """
@@ -19,7 +21,7 @@ import numpy as np
 import pytest
 
 from paper_2512_11571_amd import workloads
-from parity_util import certify, tier_mismatches
+from parity_util import certify, median_agreement, tier_mismatches
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plan_solve_oracle.json")
 
@@ -155,7 +157,7 @@ def test_plan_solve_median_matches_oracle(B):
             g.append(c.plan_solve(iters)["best_cost"])
         assert gold[str(seed)]["iters"] == iters
         r.append(gold[str(seed)]["best_cost"])
-    assert abs(np.median(g) - np.median(r)) <= 1e-2 * np.median(r)
+    median_agreement("DR pick-and-place (4 scenarios, pop 64, 2 iterations)", g, r)
 
 
 @pytest.mark.parametrize("name,R,lanes", [("pickplace", 1, 1), ("movepush", 64, 1), ("pickplace", 1, 4), ("movepush", 16, 4),

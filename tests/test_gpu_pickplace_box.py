@@ -6,9 +6,10 @@ Tolerances as for the ramp scene: FP32 joint angles / object position within
 non-chaotic; over the full horizon, tier and cost on certified rows (cost to
 within two control steps).  The rows: iteration-0 rows of the region and
 Gaussian rows around the ramp plan and around a plan that passes the obstacle
-on its +y side, so that all of psi_g's outcomes occur.  Statistical: the
-median best cost of plan_solve with the region and a reduced schedule over 32
-seeds within 1e-2 relative.  Each test also runs at 4 lanes per plan, the
+on its +y side, so that all of psi_g's outcomes occur.  Statistical: over 32
+seeds of plan_solve with the region and a reduced schedule, at least half the
+seeds' best costs within 1e-2 relative of the oracle's, and the medians within
+1e-2 or two standard errors of the median (parity_util.median_agreement).  Each test also runs at 4 lanes per plan, the
 launch the paper-setting benchmarks time (the rollouts also at 8), against
 the same oracle runs.
 """
@@ -20,7 +21,7 @@ import numpy as np
 import pytest
 
 from paper_2512_11571_amd import workloads
-from parity_util import certify, tier_mismatches
+from parity_util import certify, median_agreement, tier_mismatches
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plan_solve_oracle.json")
 
@@ -134,4 +135,4 @@ def test_plan_solve_median_matches_oracle(box, Context, lanes):
         g.append(res["best_cost"])
         assert gold[str(seed)]["iters"] == iters
         r.append(gold[str(seed)]["best_cost"])
-    assert abs(np.median(g) - np.median(r)) <= 1e-2 * np.median(r)
+    median_agreement("box scene (pop 256 -> 64, 3 iterations, %d lanes)" % lanes, g, r)
