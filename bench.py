@@ -14,8 +14,9 @@ uneven horizons and populations, one persistent launch per CE iteration, the
 largest configuration that fits one GPU), batch_mixed (push, pick-and-place
 and move-push instances), pickplace (1024 plans x 2000 steps), push,
 movepush, pickplace_paper and pickplace_box (iteration-0 regions, n_env
-schedule), movepush_dr (8 friction/mass scenarios per plan) and surrogate
-(screened against plain CE to the same cost).
+schedule), movepush_dr (8 friction/mass scenarios per plan), surrogate
+(screened against plain CE to the same cost) and mlp (the surrogate network's
+forward over 65,536 rows and its training step, against the BF16 MFMA peak).
 """
 import argparse
 import hashlib
@@ -224,6 +225,64 @@ def _first_reach(curve, target):
     return None
 
 
+def mlp_kernel_times(m, X, Y, rows, batch, reps=20):
+    """The surrogate's kernels alone: the mean of `reps` forward passes over `rows` rows of X and of `reps`
+    training steps (forward, backward, Adam) on the first `batch` rows, timed with HIP events."""
+    import torch
+    stream = torch.cuda.current_stream()
+    Yp = torch.empty((rows, 8), dtype=torch.float32, device=X.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    m.forward(X[:rows], Yp, stream)
+    e0.record(stream)
+    for _ in range(reps):
+        m.forward(X[:rows], Yp, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_s = e0.elapsed_time(e1) / reps / 1e3
+    m.train_step(X[:batch], Y[:batch], 0.0, None, stream)
+    e0.record(stream)
+    for _ in range(reps):
+        m.train_step(X[:batch], Y[:batch], 0.0, None, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    step_s = e0.elapsed_time(e1) / reps / 1e3
+    return {"forward_rows": rows, "forward_ms": fwd_s * 1e3,
+            "forward_tflops": rows * MLP_FLOP_PER_ROW / fwd_s / 1e12,
+            "forward_frac_of_bf16_peak": rows * MLP_FLOP_PER_ROW / fwd_s / 1e12 / PEAK_BF16_TFLOPS,
+            "train_step_rows": batch, "train_step_ms": step_s * 1e3,
+            "train_step_tflops": 3 * batch * MLP_FLOP_PER_ROW / step_s / 1e12}
+
+
+def bench_mlp(a):
+    """The surrogate network's kernels on synthetic rows: the screening forward over the screening population
+    (65,536 rows) and one training step at the training batch, on a freshly initialised network."""
+    import torch
+    from paper_2512_11571_amd import workloads
+    from paper_2512_11571_amd.binding import Mlp
+
+    spec = workloads.load("surrogate")["surrogate"]
+    rows, batch = spec["eval"]["screen_pop"], spec["train"]["batch"]
+    torch.cuda.set_device(0)
+    g = torch.Generator(device="cpu").manual_seed(a.seed)
+    X = torch.randn((rows, 16), generator=g).to("cuda:0")
+    Y = torch.randn((rows, 8), generator=g).to("cuda:0")
+    with Mlp(seed=a.seed, max_rows=rows) as m:
+        m.fit_norm(X, Y, rows)
+        for _ in range(max(1, a.warmup)):
+            mlp_kernel_times(m, X, Y, rows, batch, reps=2)
+        t = mlp_kernel_times(m, X, Y, rows, batch, reps=a.steps or 20)
+    ach = t["forward_tflops"]
+    print(json.dumps({
+        "metric": "surrogate forward TFLOP/s (training step alongside)", "value": ach, "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": a.steps or 20, "warmup": a.warmup, "ms_per_step": t["forward_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 operands, f32 accumulation",
+        "data": "synthetic (seeded normal rows, freshly initialised network)",
+        "config": {"workload": "mlp", "forward_rows": rows, "train_batch": batch, "layers": [16, 256, 256, 256, 8]},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_BF16_TFLOPS, "traffic": None},
+        "mlp": t}))
+
+
 def bench_surrogate(a):
     """Surrogate screening against plain CE on the pick-and-place plan: wall time
     to reach plain CE's final plan cost.  Dataset recording and training are
@@ -272,30 +331,7 @@ def bench_surrogate(a):
         t_train = time.perf_counter() - t0
         log("training: %d epochs in %.1f s, loss %.4f -> %.4f" % (tr["epochs"], t_train, losses[0], losses[-1]))
         # the network's kernels alone: the screening forward over one population, one training step
-        stream = torch.cuda.current_stream()
-        rows = ev["screen_pop"]
-        Yp = torch.empty((rows, 8), dtype=torch.float32, device=dev)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        m.forward(X[:rows], Yp, stream)
-        e0.record(stream)
-        for _ in range(20):
-            m.forward(X[:rows], Yp, stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        fwd_s = e0.elapsed_time(e1) / 20 / 1e3
-        b = tr["batch"]
-        m.train_step(X[:b], Y[:b], 0.0, None, stream)
-        e0.record(stream)
-        for _ in range(20):
-            m.train_step(X[:b], Y[:b], 0.0, None, stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        step_s = e0.elapsed_time(e1) / 20 / 1e3
-        mlp = {"forward_rows": rows, "forward_ms": fwd_s * 1e3,
-               "forward_tflops": rows * MLP_FLOP_PER_ROW / fwd_s / 1e12,
-               "forward_frac_of_bf16_peak": rows * MLP_FLOP_PER_ROW / fwd_s / 1e12 / PEAK_BF16_TFLOPS,
-               "train_step_rows": b, "train_step_ms": step_s * 1e3,
-               "train_step_tflops": 3 * b * MLP_FLOP_PER_ROW / step_s / 1e12}
+        mlp = mlp_kernel_times(m, X, Y, ev["screen_pop"], tr["batch"])
         log("mlp:", mlp)
         del X, Y
         solve(ev["seeds"][0], False, m)          # warm-up of both paths (graph capture, code load)
@@ -405,6 +441,9 @@ def main():
         return
     if a.workload == "surrogate":
         bench_surrogate(a)
+        return
+    if a.workload == "mlp":
+        bench_mlp(a)
         return
 
     import torch
