@@ -375,52 +375,17 @@ __device__ __forceinline__ bool face_separated(const Rel &r, V3f hA, V3f hB) {
          ta.y > hA.y + (m0.y * hB.x + m1.y * hB.y + m2.y * hB.z) ||
          ta.z > hA.z + (m0.z * hB.x + m1.z * hB.y + m2.z * hB.z);
 }
-// Vertex-face: the vertices of box A strictly inside box B (r = rel_of(A, B));
-// for each, depth = distance to B's nearest face, n = that face's outward
-// normal (world), x = the vertex (world), calling f(x, n, d) in ascending
-// vertex order.  Faces +x -x +y -y +z -z, first on ties.  Vertices are built
-// in B's frame from the scaled axes of A.  The inside test runs for all eight;
-// the face search and the contact then run once per inside vertex of a lane,
-// so lanes whose inside vertices differ share passes (the wave runs as many
-// passes as its lane with the most vertices inside, not one per vertex index).
-// Only the vertices in `vmask` (bit i: vertex i) are taken.
-template <class F>
-__device__ __forceinline__ void verts_in_box(const Rel &r, V3f hA, const Box &B, F &&f, unsigned vmask = 0xFFu) {
-  const V3f c0 = hA.x * col(r.M, 0), c1 = hA.y * col(r.M, 1), c2 = hA.z * col(r.M, 2);
-  const V3f hb = B.h;
-  unsigned inside = 0u;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const V3f xb = (r.t + ((i & 4) ? c2 : -c2) + ((i & 2) ? c1 : -c1)) + ((i & 1) ? c0 : -c0);
-    if (fabsf(xb.x) < hb.x && fabsf(xb.y) < hb.y && fabsf(xb.z) < hb.z) inside |= 1u << i;
-  }
-  inside &= vmask;
-  while (inside != 0u) {  // at most eight passes
-    const int i = __builtin_ctz(inside);
-    inside &= inside - 1u;
-    {
-      const V3f xb = (r.t + ((i & 4) ? c2 : -c2) + ((i & 2) ? c1 : -c1)) + ((i & 1) ? c0 : -c0);
-      const float ds[6] = {hb.x - xb.x, hb.x + xb.x, hb.y - xb.y, hb.y + xb.y, hb.z - xb.z, hb.z + xb.z};
-      int fb = 0;
-      float dmin = ds[0];
-#pragma unroll
-      for (int k = 1; k < 6; ++k) {
-        const bool lt = ds[k] < dmin;
-        fb = lt ? k : fb;
-        dmin = lt ? ds[k] : dmin;
-      }
-      const float sgn = (fb & 1) ? -1.0f : 1.0f;
-      const int ax = fb >> 1;
-      const V3f nl = v3(ax == 0 ? sgn : 0.0f, ax == 1 ? sgn : 0.0f, ax == 2 ? sgn : 0.0f);
-      f(B.p + mul(B.R, xb), mul(B.R, nl), dmin);
-    }
-  }
-}
-
-// As verts_in_box, with the contact handed over in B's frame: f(xb, ax, sgn,
-// d) with xb the vertex relative to B's centre and sgn e_ax the outward normal
-// of B's nearest face, so that the caller forms the force there and rotates
-// its sums once per pair instead of every contact point into the world.
+// Vertex-face: the vertices of box A strictly inside box B (r = rel_of(A, B),
+// hb B's half extents), each handed over in B's frame: f(xb, ax, sgn, d) with
+// xb the vertex relative to B's centre, sgn e_ax the outward normal of B's
+// nearest face and d the distance to it, in ascending vertex order (faces +x
+// -x +y -y +z -z, first on ties).  The caller forms the force in B's frame
+// and rotates its sums once per pair.  Vertices are built in B's frame from
+// the scaled axes of A.  The inside test runs for all eight; the face search
+// and the contact then run once per inside vertex of a lane, so lanes whose
+// inside vertices differ share passes (the wave runs as many passes as its
+// lane with the most vertices inside, not one per vertex index).  Only the
+// vertices in `vmask` (bit i: vertex i) are taken.
 template <class F>
 __device__ __forceinline__ void verts_in_box_b(const Rel &r, V3f hA, V3f hb, F &&f, unsigned vmask = 0xFFu) {
   const V3f c0 = hA.x * col(r.M, 0), c1 = hA.y * col(r.M, 1), c2 = hA.z * col(r.M, 2);

@@ -669,8 +669,17 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
         };
         // the base link against the static boxes
         {
-          const Box LB = link_box(BASEB, Rw2, pw2);
-          const V3f com = v3(sc.b_com[BASEB][0], sc.b_com[BASEB][1], sc.b_com[BASEB][2]);
+          Box LB;
+          V3f com;
+          if constexpr (SPEC) {  // the model's link box, its centre's offset with the structural zeros left out
+            com = v3(rm::COM[BASEB][0], rm::COM[BASEB][1], rm::COM[BASEB][2]);
+            LB.p = pw2 + rot_com<BASEB>(Rw2);
+            LB.R = Rw2;
+            LB.h = v3(rm::HALF[BASEB][0], rm::HALF[BASEB][1], rm::HALF[BASEB][2]);
+          } else {
+            LB = link_box(BASEB, Rw2, pw2);
+            com = v3(sc.b_com[BASEB][0], sc.b_com[BASEB][1], sc.b_com[BASEB][2]);
+          }
           // the spatial force on the link in its body frame (moment about the
           // body origin); the link box's frame is the body's, offset by com
           V3f fm = v3(0.0f, 0.0f, 0.0f), ff = v3(0.0f, 0.0f, 0.0f);
@@ -734,8 +743,20 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
             pb = pw + mul(Rw, X.r);
             vb = x_motion(X, vprev) + s_vec(sc, j, L.at(R_QD + j));
           }
-          const Box LB = link_box(j, Rb, pb);
-          const V3f com = v3(sc.b_com[j][0], sc.b_com[j][1], sc.b_com[j][2]);
+          Box LB;
+          V3f com;
+          if constexpr (SPEC) {  // the model's finger boxes: centres of mass off the x axis
+            static_assert(rm::COM[FL][0] == 0.0f && rm::COM[FR][0] == 0.0f, "finger centres of mass on x = 0");
+            const bool left = j == FL;
+            com = left ? v3(rm::COM[FL][0], rm::COM[FL][1], rm::COM[FL][2]) : v3(rm::COM[FR][0], rm::COM[FR][1], rm::COM[FR][2]);
+            LB.p = pb + (com.y * col(Rb, 1) + com.z * col(Rb, 2));
+            LB.R = Rb;
+            LB.h = left ? v3(rm::HALF[FL][0], rm::HALF[FL][1], rm::HALF[FL][2])
+                        : v3(rm::HALF[FR][0], rm::HALF[FR][1], rm::HALF[FR][2]);
+          } else {
+            LB = link_box(j, Rb, pb);
+            com = v3(sc.b_com[j][0], sc.b_com[j][1], sc.b_com[j][2]);
+          }
           // the spatial force on the finger in its body frame (the finger
           // box's frame, offset by com)
           V3f fm = v3(0.0f, 0.0f, 0.0f), ff = v3(0.0f, 0.0f, 0.0f);

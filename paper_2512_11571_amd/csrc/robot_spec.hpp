@@ -151,6 +151,14 @@ template <int J> __device__ __forceinline__ Sym6 body_plus(const Sym6 &S) {
   return O;
 }
 
+// body J's centre of mass, and R c_J
+template <int J> struct ComC {
+  static constexpr float v[3] = {rm::COM[J][0], rm::COM[J][1], rm::COM[J][2]};
+};
+template <int J> __device__ __forceinline__ V3f rot_com(const M3f &R) {
+  return v3(cdot3<ComC<J>>(R.r0), cdot3<ComC<J>>(R.r1), cdot3<ComC<J>>(R.r2));
+}
+
 // r_J x w, and Rp r_J (the joint's origin in the parent's world frame)
 template <int J> __device__ __forceinline__ V3f rx_c(V3f w) {
   return v3(cdot3<RxRow<J, 0>>(w), cdot3<RxRow<J, 1>>(w), cdot3<RxRow<J, 2>>(w));
@@ -410,31 +418,33 @@ template <bool SPEC> __device__ __forceinline__ void ik_dls(CScene &sc, float *q
       J[0][c] = jv.x; J[1][c] = jv.y; J[2][c] = jv.z;
       J[3][c] = z.x; J[4][c] = z.y; J[5][c] = z.z;
     }
+    // J J^T + lambda^2 I: its lower triangle (the matrix is symmetric)
     float A[6][6];
 #pragma unroll
     for (int r = 0; r < 6; ++r)
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
+      for (int c = 0; c <= r; ++c) {
         float acc = r == c ? lam2 : 0.0f;
 #pragma unroll
         for (int k = 0; k < NARM; ++k) acc += J[r][k] * J[c][k];
         A[r][c] = acc;
       }
-    // Cholesky solve
-    float L[6][6];
+    // Cholesky solve; each pivot's reciprocal from the hardware's reciprocal
+    // square root (about 1 ulp; the matrix is positive definite, d >= lambda^2)
+    float L[6][6], inv[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       float d = A[j][j];
 #pragma unroll
       for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-      const float ljj = sqrtf(d), inv = 1.0f / ljj;
-      L[j][j] = ljj;
+      inv[j] = __builtin_amdgcn_rsqf(d);
+      L[j][j] = d * inv[j];
 #pragma unroll
       for (int i = j + 1; i < 6; ++i) {
         float t = A[i][j];
 #pragma unroll
         for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-        L[i][j] = t * inv;
+        L[i][j] = t * inv[j];
       }
     }
     float y[6], x[6];
@@ -443,14 +453,14 @@ template <bool SPEC> __device__ __forceinline__ void ik_dls(CScene &sc, float *q
       float t = e[i];
 #pragma unroll
       for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
-      y[i] = t / L[i][i];
+      y[i] = t * inv[i];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
       float t = y[i];
 #pragma unroll
       for (int k = i + 1; k < 6; ++k) t -= L[k][i] * x[k];
-      x[i] = t / L[i][i];
+      x[i] = t * inv[i];
     }
 #pragma unroll
     for (int c = 0; c < NARM; ++c) {
