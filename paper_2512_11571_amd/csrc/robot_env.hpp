@@ -540,16 +540,23 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
       // after the fingers' contacts
       const V3f vO = mulT(OB.R, ob.v), wO = mulT(OB.R, ob.w);
       V3f FO = v3(0.0f, 0.0f, 0.0f), TO = v3(0.0f, 0.0f, 0.0f);
-      for (int u = gi & (w_step - 1); u <= sc.n_static; u += w_step) {
-        if (u == 0) {
-          box_ground(ob, OB.R, ohe, kc, damp, mu_o_ground, eps2, W, w_mask);
-          continue;
-        }
-        const int b = u - 1;
+      const int u0 = gi & (w_step - 1);
+      if (u0 == 0) box_ground(ob, OB.R, ohe, kc, damp, mu_o_ground, eps2, W, w_mask);
+      // The static boxes this lane takes that no face axis separates from the
+      // object, then one pass per such box of a lane in ascending order: lanes
+      // whose near boxes differ share passes (a wave runs as many as its lane
+      // with the most near boxes, not one per box that any lane is near).
+      unsigned near = 0u;
+      for (int u = u0 == 0 ? w_step : u0; u <= sc.n_static; u += w_step) {
+        const Box SB = static_box(sc, sk, u - 1);
+        if (!face_separated(rel_of(OB, SB), ohe, SB.h)) near |= 1u << (u - 1);
+      }
+      while (near != 0u) {  // at most CEM_MAX_STATIC passes
+        const int b = __builtin_ctz(near);
+        near &= near - 1u;
         const Box SB = static_box(sc, sk, b);
         const float mu = mu_drawn ? mu_obj : (sc.st_ramp[b] ? sc.mu_ramp : sc.mu_static);
         const Rel r = rel_of(OB, SB);
-        if (face_separated(r, ohe, SB.h)) continue;
         // object vertices in the static box (A = object), in the box's frame,
         // where the object's centre is r.t
         const V3f vB = mulT(SB.R, ob.v), wB = mulT(SB.R, ob.w);
@@ -688,10 +695,18 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
           const bool b_halves = G >= 8 && sc.n_static <= 4;
           const int b_step = b_halves ? 4 : G;
           const unsigned b_mask = b_halves ? corner_part(gi, G) : 0xFFu;
+          // the near boxes first, then one pass per near box of a lane, as
+          // for the object above
+          unsigned near = 0u;
           for (int b = gi & (b_step - 1); b < sc.n_static; b += b_step) {
             const Box SB = static_box(sc, sk, b);
+            if (!face_separated(rel_of(LB, SB), LB.h, SB.h)) near |= 1u << b;
+          }
+          while (near != 0u) {  // at most CEM_MAX_STATIC passes
+            const int b = __builtin_ctz(near);
+            near &= near - 1u;
+            const Box SB = static_box(sc, sk, b);
             const Rel r = rel_of(LB, SB);
-            if (face_separated(r, LB.h, SB.h)) continue;
             // link vertices in the static box, in the box's frame: the body
             // origin at q, the link's velocity (M v2) there
             const V3f q = r.t - mul(r.M, com), wa = mul(r.M, v2.a), wb = mul(r.M, v2.b);
