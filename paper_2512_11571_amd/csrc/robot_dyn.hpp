@@ -399,17 +399,25 @@ __device__ __forceinline__ void verts_in_box_b(const Rel &r, V3f hA, V3f hb, F &
   while (inside != 0u) {  // at most eight passes
     const int i = __builtin_ctz(inside);
     inside &= inside - 1u;
-    const V3f xb = (r.t + ((i & 4) ? c2 : -c2) + ((i & 2) ? c1 : -c1)) + ((i & 1) ? c0 : -c0);
-    const float ds[6] = {hb.x - xb.x, hb.x + xb.x, hb.y - xb.y, hb.y + xb.y, hb.z - xb.z, hb.z + xb.z};
-    int fb = 0;
-    float dmin = ds[0];
-#pragma unroll
-    for (int k = 1; k < 6; ++k) {
-      const bool lt = ds[k] < dmin;
-      fb = lt ? k : fb;
-      dmin = lt ? ds[k] : dmin;
-    }
-    f(xb, fb >> 1, (fb & 1) ? -1.0f : 1.0f, dmin);
+    // the vertex again, as ((t +- c2) +- c1) +- c0: a product with +-1 is
+    // exact, so each fused step rounds as the sum above does
+    const float s0 = (i & 1) ? 1.0f : -1.0f, s1 = (i & 2) ? 1.0f : -1.0f, s2 = (i & 4) ? 1.0f : -1.0f;
+    const V3f xb = v3(fmaf(s0, c0.x, fmaf(s1, c1.x, fmaf(s2, c2.x, r.t.x))),
+                      fmaf(s0, c0.y, fmaf(s1, c1.y, fmaf(s2, c2.y, r.t.y))),
+                      fmaf(s0, c0.z, fmaf(s1, c1.z, fmaf(s2, c2.z, r.t.z))));
+    // nearest face: per axis the lesser of h - x and h + x is h - |x| (the
+    // same rounded value); the first axis of least depth, and on it the -
+    // face only where h + x < h - x, so ties go to the + face
+    const float dx = hb.x - fabsf(xb.x), dy = hb.y - fabsf(xb.y), dz = hb.z - fabsf(xb.z);
+    const bool ly = dy < dx;
+    int ax = ly ? 1 : 0;
+    float dmin = ly ? dy : dx;
+    const bool lz = dz < dmin;
+    ax = lz ? 2 : ax;
+    dmin = lz ? dz : dmin;
+    const float xa = ax == 0 ? xb.x : (ax == 1 ? xb.y : xb.z);
+    const float ha = ax == 0 ? hb.x : (ax == 1 ? hb.y : hb.z);
+    f(xb, ax, ha + xa < ha - xa ? -1.0f : 1.0f, dmin);
   }
 }
 
