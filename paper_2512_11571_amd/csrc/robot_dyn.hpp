@@ -375,6 +375,18 @@ __device__ __forceinline__ bool face_separated(const Rel &r, V3f hA, V3f hB) {
          ta.y > hA.y + (m0.y * hB.x + m1.y * hB.y + m2.y * hB.z) ||
          ta.z > hA.z + (m0.z * hB.x + m1.z * hB.y + m2.z * hB.z);
 }
+// False when no corner of box B can lie inside box A (r = rel_of(A, B)):
+// B's corners sit at +-hB_i on each of B's axes, and A lies within
+// |x_i - t_i| <= sum_j |M_ij| hA_j there, so a corner is out of reach when
+// that interval stops short of hB_i.  The 0.1 mm margin is far above the
+// FP32 rounding of these positions, so the corner tests this rejects would
+// have found no corner inside: skipping them changes no contact.
+__device__ __forceinline__ bool corners_reach(const Rel &r, V3f hA, V3f hB) {
+  constexpr float MARGIN = 1e-4f;
+  const V3f m0 = vabs(r.M.r0), m1 = vabs(r.M.r1), m2 = vabs(r.M.r2);
+  return !(fabsf(r.t.x) + dot(m0, hA) + MARGIN < hB.x || fabsf(r.t.y) + dot(m1, hA) + MARGIN < hB.y ||
+           fabsf(r.t.z) + dot(m2, hA) + MARGIN < hB.z);
+}
 // Vertex-face: the vertices of box A strictly inside box B (r = rel_of(A, B),
 // hb B's half extents), each handed over in B's frame: f(xb, ax, sgn, d) with
 // xb the vertex relative to B's centre, sgn e_ax the outward normal of B's

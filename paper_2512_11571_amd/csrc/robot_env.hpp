@@ -569,12 +569,14 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
         }, w_mask);
         W.f = W.f + mul(SB.R, F);
         W.t = W.t + mul(SB.R, T);
-        // static-box vertices in the object (A = static box, the object receives the negative)
-        verts_in_box_b(rel_swap(r), SB.h, ohe, [&](V3f xb, int ax, float sg, float d) {
-          const V3f f = -contact_force_b(ax, sg, d, v3(0.0f, 0.0f, 0.0f) - (vO + cross(wO, xb)), kc, damp, mu, eps2);
-          FO = FO + f;
-          TO = TO + cross(xb, f);
-        }, w_mask);
+        // static-box vertices in the object (A = static box, the object
+        // receives the negative), where one can reach into it
+        if (corners_reach(r, ohe, SB.h))
+          verts_in_box_b(rel_swap(r), SB.h, ohe, [&](V3f xb, int ax, float sg, float d) {
+            const V3f f = -contact_force_b(ax, sg, d, v3(0.0f, 0.0f, 0.0f) - (vO + cross(wO, xb)), kc, damp, mu, eps2);
+            FO = FO + f;
+            TO = TO + cross(xb, f);
+          }, w_mask);
       }
 
       // ---- ABA pass 1 (root to leaves): poses, velocities, bias terms ----
@@ -719,14 +721,16 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
             }, b_mask);
             ff = ff + mulT(r.M, F);
             fm = fm + mulT(r.M, T);
-            // static-box vertices in the link, in the body frame
-            verts_in_box_b(rel_swap(r), SB.h, LB.h, [&](V3f xb, int ax, float sg, float d) {
-              const V3f ro = xb + com;
-              const V3f f = -contact_force_b(ax, sg, d, v3(0.0f, 0.0f, 0.0f) - (v2.b + cross(v2.a, ro)), kc, damp,
-                                             sc.mu_static, eps2);
-              ff = ff + f;
-              fm = fm + cross(ro, f);
-            }, b_mask);
+            // static-box vertices in the link, in the body frame, where one
+            // can reach into it
+            if (corners_reach(r, LB.h, SB.h))
+              verts_in_box_b(rel_swap(r), SB.h, LB.h, [&](V3f xb, int ax, float sg, float d) {
+                const V3f ro = xb + com;
+                const V3f f = -contact_force_b(ax, sg, d, v3(0.0f, 0.0f, 0.0f) - (v2.b + cross(v2.a, ro)), kc, damp,
+                                               sc.mu_static, eps2);
+                ff = ff + f;
+                fm = fm + cross(ro, f);
+              }, b_mask);
           }
           if (G > 1) {
             fm = group_sum(fm, G);
@@ -796,8 +800,9 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
               fm = fm + mulT(r.M, T);
             }
             // object vertices in the finger (A = object, B = finger), in the
-            // finger's frame: the object's centre at rs.t, its velocity there
-            if (dirs & 2) {
+            // finger's frame: the object's centre at rs.t, its velocity there;
+            // only where a corner of the object can reach into the finger
+            if ((dirs & 2) && corners_reach(r, LB.h, ohe)) {
               const Rel rs = rel_swap(r);
               const V3f vF = mulT(r.M, vO), wF = mulT(r.M, wO);
               V3f F = v3(0.0f, 0.0f, 0.0f), T = v3(0.0f, 0.0f, 0.0f);
