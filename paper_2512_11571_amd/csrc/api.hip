@@ -522,6 +522,7 @@ struct cem_batch {
   int n_items = 0, max_pop = 0, item_envs = 64, grid = 0, n_cu = 0;
   int *queue = nullptr;
   int *pool = nullptr;  // per instance: the next unstarted plan of its rollout (batched launch)
+  int32_t *perm = nullptr;  // the robot instances' plan orders (their pops, one after the other)
   hipStream_t own = nullptr;
   hipGraphExec_t graph = nullptr;
   std::string err;
@@ -618,6 +619,7 @@ void batch_release(cem_batch *b) {
   (void)hipFree(b->items);
   (void)hipFree(b->queue);
   (void)hipFree(b->pool);
+  (void)hipFree(b->perm);
   for (cem_ctx *c : b->ctx) cem_free(c);
 }
 
@@ -644,19 +646,35 @@ int cem_batch_init(const cem_problem *problems, const int32_t *iters, int32_t n,
   if (rc == CEM_OK) {
     b->iters.assign(iters, iters + n);
     std::vector<InstDesc> h(n);
+    // robot instances without scenarios draw their plans from a pool, in an
+    // order the launch sets (rollout.hip, plan_order_kernel)
+    auto ordered = [&](const cem_ctx *c) { return c->scene.kind != CEM_SCENE_PUSH && scenarios(c->scene) == 1; };
+    size_t n_perm = 0;
+    for (int i = 0; i < n; ++i)
+      if (ordered(b->ctx[i])) n_perm += (size_t)b->ctx[i]->pop;
+    if (n_perm > 0 && hipMalloc(&b->perm, sizeof(int32_t) * n_perm) != hipSuccess) {
+      rc = CEM_E_ALLOC;
+      b->err = "plan order buffers";
+    }
+    size_t off = 0;
     for (int i = 0; i < n; ++i) {
       cem_ctx *c = b->ctx[i];
       h[i] = desc_of(c, c->Z, c->pop, c->cost, c->tier, c->pose);
       h[i].iters = iters[i];
+      if (b->perm && ordered(c)) {
+        h[i].perm = b->perm + off;
+        off += (size_t)c->pop;
+      }
       b->max_pop = std::max(b->max_pop, c->pop);
     }
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
-        hipMalloc(&b->insts, sizeof(InstDesc) * n) != hipSuccess || hipMalloc(&b->queue, sizeof(int)) != hipSuccess ||
-        hipMalloc(&b->pool, sizeof(int) * n) != hipSuccess ||
-        hipMemcpy(b->insts, h.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    if (rc == CEM_OK &&
+        (hipGetDevice(&dev) != hipSuccess ||
+         hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+         hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+         hipMalloc(&b->insts, sizeof(InstDesc) * n) != hipSuccess || hipMalloc(&b->queue, sizeof(int)) != hipSuccess ||
+         hipMalloc(&b->pool, sizeof(int) * n) != hipSuccess ||
+         hipMemcpy(b->insts, h.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice) != hipSuccess)) {
       rc = CEM_E_HIP;
       b->err = "batch set-up";
     }

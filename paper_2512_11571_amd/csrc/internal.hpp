@@ -18,6 +18,7 @@ constexpr int MAX_STATS_ITERS = 4096;
 // kernel), so the rollout does not recompute them every substep.
 struct SceneConsts {
   float st_R[CEM_MAX_STATIC][9];       // static box rotations (box -> world), row-major
+  int32_t st_axis[CEM_MAX_STATIC];     // 1 where that rotation is exactly the identity (no yaw, no pitch)
   float I_body[CEM_MAX_JOINTS][21];    // spatial inertia of body j about its frame origin: A(6) B(9) C(6)
 };
 
@@ -63,6 +64,8 @@ struct InstDesc {
   int32_t scen;                 // scenarios per row (1: no domain randomisation); pop * scen environments
   int32_t lanes;                // lanes per environment (1, 2, 4); pop * scen * lanes lanes
   int32_t spec;                 // 1: the robot is the compiled-in model (robot_spec_for), use its instance
+  int32_t *perm;                // batch, robot instance without scenarios: the order in which its plan pool hands
+                                // out plans (pop entries, written by the launch); nullptr: plans in index order
 };
 // Up to 64 environments [env0, env0 + n) of instance `inst`.
 struct WorkItem {

@@ -356,6 +356,14 @@ __device__ __forceinline__ Rel rel_of(const Box &A, const Box &B) {
   r.t = mulT(B.R, A.p - B.p);
   return r;
 }
+// rel_of for a box B whose rotation is the identity: M = RA, t = pA - pB (the
+// same values, the products by exact ones and zeros left out).
+__device__ __forceinline__ Rel rel_of_axis(const Box &A, const Box &B) {
+  Rel r;
+  r.M = A.R;
+  r.t = A.p - B.p;
+  return r;
+}
 // B seen from A: M^T and -M^T t.
 __device__ __forceinline__ Rel rel_swap(const Rel &r) {
   Rel o;

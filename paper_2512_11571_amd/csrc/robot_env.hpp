@@ -549,7 +549,10 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
       unsigned near = 0u;
       for (int u = u0 == 0 ? w_step : u0; u <= sc.n_static; u += w_step) {
         const Box SB = static_box(sc, sk, u - 1);
-        if (!face_separated(rel_of(OB, SB), ohe, SB.h)) near |= 1u << (u - 1);
+        bool sep;
+        if (sk.st_axis[u - 1]) sep = face_separated(rel_of_axis(OB, SB), ohe, SB.h);  // an unrotated box
+        else sep = face_separated(rel_of(OB, SB), ohe, SB.h);
+        if (!sep) near |= 1u << (u - 1);
       }
       while (near != 0u) {  // at most CEM_MAX_STATIC passes
         const int b = __builtin_ctz(near);
@@ -702,7 +705,10 @@ __device__ __forceinline__ int robot_env(CDevState *st, const float *__restrict_
           unsigned near = 0u;
           for (int b = gi & (b_step - 1); b < sc.n_static; b += b_step) {
             const Box SB = static_box(sc, sk, b);
-            if (!face_separated(rel_of(LB, SB), LB.h, SB.h)) near |= 1u << b;
+            bool sep;
+            if (sk.st_axis[b]) sep = face_separated(rel_of_axis(LB, SB), LB.h, SB.h);  // an unrotated box
+            else sep = face_separated(rel_of(LB, SB), LB.h, SB.h);
+            if (!sep) near |= 1u << b;
           }
           while (near != 0u) {  // at most CEM_MAX_STATIC passes
             const int b = __builtin_ctz(near);

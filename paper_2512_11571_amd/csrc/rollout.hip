@@ -56,6 +56,7 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
       d.iters = di.iters;
       d.scen = di.scen;
       d.lanes = 1;
+      d.perm = di.perm;
       env0 = w.env0;
       n = w.n;
     } else {
@@ -87,12 +88,15 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
       long row0 = row;
       bool live0 = true;
       float mu = st->obj_mu, m = st->scene.obj_mass;
+      // the pool's k-th plan: plan perm[k] where the launch ordered the plans
+      const int32_t *perm = d.perm;
       if (pooled) {
         int e0 = 0;
         if (lane == 0) e0 = atomicAdd(&pool[inst], 64);
         e0 = __builtin_amdgcn_readfirstlane(e0);
         row0 = (long)e0 + lane;
         live0 = row0 < pop;
+        if (live0 && perm) row0 = perm[row0];
       } else if (R > 1) {
         const int r = (int)(env & (R - 1));
         if (st->scene.dr_mu_hi > 0.0f) mu = st->dr_mu[r];
@@ -112,6 +116,7 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
         if (need) {
           r = (long)base + __popcll(want & ((1ull << lane) - 1ull));
           live = r < pop;
+          if (live && perm) r = perm[r];
         }
       };
       auto finish = [&](const EnvOut &e, long r) {
@@ -175,6 +180,8 @@ __global__ void scene_consts_kernel(DevState *st) {
     const M3f R = static_rot(sc, b);
     const float m[9] = {R.r0.x, R.r0.y, R.r0.z, R.r1.x, R.r1.y, R.r1.z, R.r2.x, R.r2.y, R.r2.z};
     for (int i = 0; i < 9; ++i) k.st_R[b][i] = m[i];
+    k.st_axis[b] = m[0] == 1.0f && m[4] == 1.0f && m[8] == 1.0f && m[1] == 0.0f && m[2] == 0.0f && m[3] == 0.0f &&
+                   m[5] == 0.0f && m[6] == 0.0f && m[7] == 0.0f;
   }
   for (int j = 0; j < CEM_MAX_JOINTS; ++j) {
     const Sym6 I = body_inertia(sc, j);
@@ -184,6 +191,45 @@ __global__ void scene_consts_kernel(DevState *st) {
     }
     for (int i = 0; i < 9; ++i) k.I_body[j][6 + i] = I.B[i];
   }
+}
+
+// The order in which a batch hands out a robot instance's plans: by the
+// duration of the plan's first action (a base move from the start pose, as
+// the controller times it), in 64 bins of 0.1 s, so that the lanes of a wave
+// reach their next actions at similar steps and their contact passes
+// coincide more often.  A plan's rollout does not depend on the lane or the
+// wave that runs it, so every order gives the same outcomes; within a bin the
+// order is whatever the atomics give.  One workgroup per instance.
+__global__ void plan_order_kernel(const InstDesc *__restrict__ insts) {
+  constexpr int NB = 64;
+  constexpr float BIN = 0.1f;
+  const InstDesc &d = insts[blockIdx.x];
+  if (!d.perm) return;
+  __shared__ int hist[NB];
+  const cem_scene &sc = d.st->scene;
+  const float x0 = sc.q0[0], y0 = sc.q0[1], p0 = sc.q0[2];
+  const float vlo = sc.base_vmin, vhi = sc.base_vmax, wmax = sc.base_wmax;
+  auto bin_of = [&](int i) {
+    const float *z = d.Z + (long)i * d.D;
+    const float dx = z[0] - x0, dy = z[1] - y0;
+    const float dpsi = remainderf(z[2] - p0, 6.283185307179586f);
+    const float t = fmaxf(sqrtf(dx * dx + dy * dy) / fmaxf(vlo, fminf(vhi, z[3])), fabsf(dpsi) / wmax);
+    return t >= 0.0f && t < NB * BIN ? (int)(t * (1.0f / BIN)) : NB - 1;  // NaN and long moves last
+  };
+  for (int k = threadIdx.x; k < NB; k += blockDim.x) hist[k] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < d.pop; i += blockDim.x) atomicAdd(&hist[bin_of(i)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int k = 0; k < NB; ++k) {
+      const int c = hist[k];
+      hist[k] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < d.pop; i += blockDim.x) d.perm[atomicAdd(&hist[bin_of(i)], 1)] = i;
 }
 
 // Clears the work queue's ticket and the instances' plan pools before a
@@ -279,6 +325,7 @@ hipError_t launch_pack_dataset(const InstDesc &d, float cost_cap, float *X, floa
 hipError_t launch_rollout_batch(const InstDesc *insts, int n_inst, const WorkItem *items, int n_items, int *queue,
                                 int *pool, int grid, bool spec, hipStream_t s) {
   hipLaunchKernelGGL(reset_counters_kernel, dim3((n_inst + 255) / 256 + 1), dim3(256), 0, s, queue, pool, n_inst);
+  hipLaunchKernelGGL(plan_order_kernel, dim3(n_inst), dim3(256), 0, s, insts);
   InstDesc none{};
   const RolloutKernel k = spec ? rollout_items_kernel<false, false, true> : rollout_items_kernel<false, false, false>;
   hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, s, none, insts, items, n_items, queue, pool, 1, nullptr, 0);
