@@ -10,6 +10,8 @@ instances run three different action sequences in one launch.
   rows the oracle certifies (cost and tier unchanged by 1- to 256-ulp nudges of
   every parameter) have the oracle's tier, and their costs agree within two
   control steps (robot plans) or 1e-3 (push).
+- The whole batch's iteration 0: every row the batched launch reports as
+  diverged (tier 3) is one the oracle cannot complete either (tier 2 or 3).
 - The full CE runs of the 32 push instances (each its own problem, 5
   iterations): the median over instances of the best cost is within 1e-2
   relative of the oracle's (tests/golden/plan_solve_oracle.json, written by
@@ -105,6 +107,34 @@ def test_mixed_batch_iteration0_against_oracle(oracle, binding):
     kinds = [i["workload"]["scene"]["kind"] for i in insts]
     picks = [kinds.index("push"), kinds.index("pickplace"), kinds.index("movepush")]
     assert _iteration0(oracle, binding, insts, picks, "mixed batch") >= 40
+
+
+def test_batch_diverged_rows_against_the_oracle(oracle, binding):
+    # the configured batch's iteration 0 (141,184 plans of 64 instances, the
+    # pools in their launch order): every row the batched launch reports as
+    # diverged (tier 3) is one the FP64 oracle cannot complete either (tier 2:
+    # an action fails, or tier 3: it diverges too), so no plan that could enter
+    # an update is lost to FP32 arithmetic alone
+    insts = workloads.batch_instances()
+    with binding.Batch(insts) as B:
+        B.step()
+        torch.cuda.synchronize()
+        tiers = [B.instance(k).outcomes(i["workload"]["cem"]["pop"])[1] for k, i in enumerate(insts)]
+    n_bad = 0
+    for k, (inst, th) in enumerate(zip(insts, tiers)):
+        bad = np.nonzero(th == 3)[0]
+        if bad.size == 0:
+            continue
+        n_bad += bad.size
+        w, cem = inst["workload"], inst["workload"]["cem"]
+        L, _ = oracle.factor_cov(np.diag(np.asarray(cem["cov0_diag"], np.float64)))
+        Z = oracle.sample(inst["seed"], 0, inst["instance"], cem["pop"], np.asarray(cem["mu0"], np.float64), L)
+        _, tr, _, _ = oracle.rollout(w, inst["seed"], Z[bad], inst=inst["instance"])
+        print("batch instance %d (%s, H %d, pop %d): GPU tier-3 rows %s, oracle tiers %s"
+              % (k, w["scene"]["kind"], w["scene"]["horizon"], cem["pop"], bad.tolist(), tr.tolist()))
+        assert np.all(tr >= 2), (k, list(zip(bad.tolist(), tr.tolist())))
+    print("batch iteration 0: %d of %d rows diverged on the GPU" % (n_bad, sum(t.size for t in tiers)))
+    assert n_bad <= 1e-3 * sum(t.size for t in tiers)
 
 
 def test_batch_push_instances_median_best_cost(binding):
