@@ -25,6 +25,9 @@
  *    the elite scratch, the best-so-far record and the replay graph; all of it
  *    is allocated by cem_init, so the per-iteration calls never allocate.
  *  - One host thread at a time per context; separate contexts are independent.
+ *    Work of one context that overlaps on several streams races on the
+ *    context's device scratch (the elite scratch, and the order in which a
+ *    robot scene's rollout hands plans to lanes): keep it on one stream.
  */
 #ifndef CEMTAMP_H
 #define CEMTAMP_H
@@ -251,7 +254,11 @@ int cem_sample(cem_ctx *c, int32_t iter, float *Z_dev, void *stream);
  * horizon and write cost_dev[pop] (plan cost, Problem 2 objective),
  * tier_dev[pop] (0 feasible, 1 all actions succeeded but goal missed,
  * 2 other, 3 diverged) and, if pose_dev is non-NULL, the final object pose
- * pose_dev[pop][7] = (p, q).  pop may differ from the problem's pop. */
+ * pose_dev[pop][7] = (p, q).  pop may differ from the problem's pop.  For a
+ * robot scene at one lane per environment and pop up to the problem's, the
+ * launch first orders the rows by their first move's duration in the
+ * context's scratch, so that a wave's lanes run similar plans; each row's
+ * outcome is the same in any order. */
 int rollout_batch(cem_ctx *c, const float *Z_dev, int32_t pop, float *cost_dev, uint8_t *tier_dev,
                   float *pose_dev, void *stream);
 

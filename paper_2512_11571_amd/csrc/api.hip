@@ -151,6 +151,9 @@ InstDesc desc_of(cem_ctx *c, const float *Z, int pop, float *cost, uint8_t *tier
   d.scen = scenarios(c->scene);
   d.lanes = c->lanes;
   d.spec = robot_spec_for(c->scene) ? 1 : 0;
+  // one lane per environment: the launch hands out the plans in an order it
+  // sets (rollout.hip, order_plans); lane groups keep index order
+  if (c->perm && c->lanes == 1 && pop <= c->pop) d.perm = c->perm;
   return d;
 }
 
@@ -212,6 +215,7 @@ void release(cem_ctx *c) {
   (void)hipFree(c->pose);
   (void)hipFree(c->tier);
   (void)hipFree(c->stats);
+  (void)hipFree(c->perm);
 }
 
 }  // namespace
@@ -288,7 +292,8 @@ int cem_init(const cem_problem *p, cem_ctx **out) {
     if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess || hipMalloc(&c->Z, sizeof(float) * P * D) != hipSuccess ||
         hipMalloc(&c->cost, sizeof(float) * P) != hipSuccess || hipMalloc(&c->pose, sizeof(float) * P * 7) != hipSuccess ||
         hipMalloc(&c->tier, P) != hipSuccess ||
-        hipMalloc(&c->stats, sizeof(float) * MAX_STATS_ITERS * CEM_STATS_COLS) != hipSuccess) {
+        hipMalloc(&c->stats, sizeof(float) * MAX_STATS_ITERS * CEM_STATS_COLS) != hipSuccess ||
+        (c->scene.kind != CEM_SCENE_PUSH && hipMalloc(&c->perm, sizeof(int32_t) * P) != hipSuccess)) {
       rc = fail(c, CEM_E_ALLOC, "device allocation");
       break;
     }
@@ -522,7 +527,6 @@ struct cem_batch {
   int n_items = 0, max_pop = 0, item_envs = 64, grid = 0, n_cu = 0;
   int *queue = nullptr;
   int *pool = nullptr;  // per instance: the next unstarted plan of its rollout (batched launch)
-  int32_t *perm = nullptr;  // the robot instances' plan orders (their pops, one after the other)
   hipStream_t own = nullptr;
   hipGraphExec_t graph = nullptr;
   std::string err;
@@ -619,7 +623,6 @@ void batch_release(cem_batch *b) {
   (void)hipFree(b->items);
   (void)hipFree(b->queue);
   (void)hipFree(b->pool);
-  (void)hipFree(b->perm);
   for (cem_ctx *c : b->ctx) cem_free(c);
 }
 
@@ -646,35 +649,19 @@ int cem_batch_init(const cem_problem *problems, const int32_t *iters, int32_t n,
   if (rc == CEM_OK) {
     b->iters.assign(iters, iters + n);
     std::vector<InstDesc> h(n);
-    // robot instances without scenarios draw their plans from a pool, in an
-    // order the launch sets (rollout.hip, plan_order_kernel)
-    auto ordered = [&](const cem_ctx *c) { return c->scene.kind != CEM_SCENE_PUSH && scenarios(c->scene) == 1; };
-    size_t n_perm = 0;
-    for (int i = 0; i < n; ++i)
-      if (ordered(b->ctx[i])) n_perm += (size_t)b->ctx[i]->pop;
-    if (n_perm > 0 && hipMalloc(&b->perm, sizeof(int32_t) * n_perm) != hipSuccess) {
-      rc = CEM_E_ALLOC;
-      b->err = "plan order buffers";
-    }
-    size_t off = 0;
     for (int i = 0; i < n; ++i) {
       cem_ctx *c = b->ctx[i];
       h[i] = desc_of(c, c->Z, c->pop, c->cost, c->tier, c->pose);
       h[i].iters = iters[i];
-      if (b->perm && ordered(c)) {
-        h[i].perm = b->perm + off;
-        off += (size_t)c->pop;
-      }
       b->max_pop = std::max(b->max_pop, c->pop);
     }
     int dev = 0;
-    if (rc == CEM_OK &&
-        (hipGetDevice(&dev) != hipSuccess ||
-         hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-         hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
-         hipMalloc(&b->insts, sizeof(InstDesc) * n) != hipSuccess || hipMalloc(&b->queue, sizeof(int)) != hipSuccess ||
-         hipMalloc(&b->pool, sizeof(int) * n) != hipSuccess ||
-         hipMemcpy(b->insts, h.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice) != hipSuccess)) {
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(&b->insts, sizeof(InstDesc) * n) != hipSuccess || hipMalloc(&b->queue, sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->pool, sizeof(int) * n) != hipSuccess ||
+        hipMemcpy(b->insts, h.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice) != hipSuccess) {
       rc = CEM_E_HIP;
       b->err = "batch set-up";
     }

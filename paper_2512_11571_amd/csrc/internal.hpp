@@ -64,8 +64,8 @@ struct InstDesc {
   int32_t scen;                 // scenarios per row (1: no domain randomisation); pop * scen environments
   int32_t lanes;                // lanes per environment (1, 2, 4); pop * scen * lanes lanes
   int32_t spec;                 // 1: the robot is the compiled-in model (robot_spec_for), use its instance
-  int32_t *perm;                // batch, robot instance without scenarios: the order in which its plan pool hands
-                                // out plans (pop entries, written by the launch); nullptr: plans in index order
+  int32_t *perm;                // robot scene at one lane per environment: the order in which the launch hands
+                                // plans to lanes (pop entries, written by the launch); nullptr: index order
 };
 // Up to 64 environments [env0, env0 + n) of instance `inst`.
 struct WorkItem {
@@ -122,6 +122,7 @@ struct cem_ctx {
   hipGraphExec_t iter_graph = nullptr;
   int pop_final = 0, pop_ramp = 0;  // n_env schedule (pop_final 0: none)
   int lanes = 1;                    // lanes per environment
+  int32_t *perm = nullptr;          // robot scenes: the order of a launch's plans over the lanes (pop entries)
   uint64_t serial = 0;  // unique per context in the process (host addresses are reused after cem_free)
   std::string err;
 };

@@ -74,7 +74,9 @@ __global__ void __launch_bounds__(64) rollout_items_kernel(InstDesc single, cons
     EnvOut o{0.0f, 0, 0, {0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f}};
     // lane layout: ((row * R) + scenario) * G + g, g the lane's place in its environment's group
     const int lg = G == 16 ? 4 : G == 8 ? 3 : G == 4 ? 2 : G == 2 ? 1 : 0;
-    const long vl = env0 + lane, env = vl >> lg, row = env / R;
+    const long vl = env0 + lane, env = vl >> lg;
+    // the item's environments hold the plans in the order the launch set
+    const long row = d.perm && env / R < d.pop ? d.perm[env / R] : env / R;
     const int g = (int)(vl & (G - 1));
     const bool pooled = pool && robot && R == 1;  // wave-uniform
     if (active && robot && (pooled || lane < n)) {
@@ -193,18 +195,17 @@ __global__ void scene_consts_kernel(DevState *st) {
   }
 }
 
-// The order in which a batch hands out a robot instance's plans: by the
-// duration of the plan's first action (a base move from the start pose, as
-// the controller times it), in 64 bins of 0.1 s, so that the lanes of a wave
-// reach their next actions at similar steps and their contact passes
-// coincide more often.  A plan's rollout does not depend on the lane or the
-// wave that runs it, so every order gives the same outcomes; within a bin the
-// order is whatever the atomics give.  One workgroup per instance.
-__global__ void plan_order_kernel(const InstDesc *__restrict__ insts) {
+// The order in which a launch hands a robot instance's plans to its lanes (one
+// lane per environment): by the duration of the plan's first action (a base
+// move from the start pose, as the controller times it), in 64 bins of 0.1 s,
+// so that the lanes of a wave reach their next actions at similar steps and
+// their contact passes coincide more often.  A plan's rollout does not depend
+// on the lane or the wave that runs it, so every order gives the same
+// outcomes; within a bin the order is whatever the atomics give.  One
+// workgroup per instance writes d.perm[0 .. pop).
+__device__ void order_plans(const InstDesc &d) {
   constexpr int NB = 64;
   constexpr float BIN = 0.1f;
-  const InstDesc &d = insts[blockIdx.x];
-  if (!d.perm) return;
   __shared__ int hist[NB];
   const cem_scene &sc = d.st->scene;
   const float x0 = sc.q0[0], y0 = sc.q0[1], p0 = sc.q0[2];
@@ -231,6 +232,11 @@ __global__ void plan_order_kernel(const InstDesc *__restrict__ insts) {
   __syncthreads();
   for (int i = threadIdx.x; i < d.pop; i += blockDim.x) d.perm[atomicAdd(&hist[bin_of(i)], 1)] = i;
 }
+// A batch's instances, one workgroup each; and one instance.
+__global__ void plan_order_kernel(const InstDesc *__restrict__ insts) {
+  if (insts[blockIdx.x].perm) order_plans(insts[blockIdx.x]);
+}
+__global__ void plan_order_single_kernel(InstDesc d) { order_plans(d); }
 
 // Clears the work queue's ticket and the instances' plan pools before a
 // batched launch (a kernel rather than a memset, so the clearing can sit in a
@@ -300,6 +306,7 @@ hipError_t launch_rollout_single(const InstDesc &d, float *trace, int trace_step
   const int n_items = (d.pop * d.scen * d.lanes + 63) / 64;
   if (n_items == 0) return hipSuccess;
   const bool multi = d.lanes > 1;
+  if (d.perm) hipLaunchKernelGGL(plan_order_single_kernel, dim3(1), dim3(256), 0, s, d);
   const RolloutKernel k =
       d.spec ? (trace ? (multi ? rollout_items_kernel<true, true, true> : rollout_items_kernel<true, false, true>)
                       : (multi ? rollout_items_kernel<false, true, true> : rollout_items_kernel<false, false, true>))
