@@ -38,15 +38,15 @@ DEFAULT_WORKLOAD = "batch"
 # scaled by the copy-kernel calibration), keyed by workload; valid only while
 # the rollout sources hash to the recorded value.
 MEASURED_TRAFFIC = {
-    # one batched rollout launch (64 instances, 141,184 plans, 357.7 M env-steps): FETCH_SIZE 5372.0 KiB x 2.0
-    # (items of 64 envs) + WRITE_SIZE 7301.375 KiB x 1.0 (items of 32 envs; a 256 MiB copy reads as 131083.5 /
-    # 262144 KiB); algorithmic 10,243,712 B (Z in, cost, tier and pose out); the pools' plan order scatters the
+    # one batched rollout launch (64 instances, 141,184 plans, 357.7 M env-steps): FETCH_SIZE 5852.1875 KiB x 2.0
+    # (items of 32 envs) + WRITE_SIZE 7208.25 KiB x 1.0 (items of 64 envs; a 256 MiB copy reads as 131083.5 /
+    # 262144 KiB); algorithmic 10,243,712 B (Z in, cost, tier and pose out); the plans' launch order scatters the
     # rows' reads and the outcomes' writes
-    "batch": {"bytes_per_launch": int((5372.0 * 2.0 + 7301.375 * 1.0) * 1024), "src_hash": "8ee503a73f236852"},
+    "batch": {"bytes_per_launch": int((5852.1875 * 2.0 + 7208.25 * 1.0) * 1024), "src_hash": "a0f6363f63c6f0f4"},
     # rollout of 1024 pick-and-place plans over 2000 steps, 16 lanes per plan: FETCH_SIZE
-    # 559.5 KiB x 2.0 + WRITE_SIZE 24.0 KiB x 1.0
-    "pickplace": {"bytes_per_launch": int((559.5 * 2.0 + 24.0 * 1.0) * 1024), "lanes": 16,
-                  "src_hash": "8ee503a73f236852"},
+    # 553.5 KiB x 2.0 + WRITE_SIZE 24.0 KiB x 1.0
+    "pickplace": {"bytes_per_launch": int((553.5 * 2.0 + 24.0 * 1.0) * 1024), "lanes": 16,
+                  "src_hash": "a0f6363f63c6f0f4"},
 }
 
 _KERNEL_FILES = ["rollout.hip", "push_env.hpp", "robot_env.hpp", "robot_dyn.hpp", "robot_spec.hpp", "robot_model.hpp",
